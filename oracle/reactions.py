@@ -1,0 +1,114 @@
+"""Reaction terms g(w) of the coupled systems (paper Section 5).
+
+Each model maps a list of species fields to a list of reaction fields of
+the same shape, evaluated pointwise at t_n (explicitly, eq. (BVAM_SExpE)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+# --- Schnakenberg kinetics, eq. (schnaknl) with alpha_1 = 1 -----------------
+
+def schnakenberg(U, a, b):
+    u, v = U
+    u2v = u * u * v
+    return [a - u + u2v, b - u2v]
+
+
+def schnakenberg_equilibrium(a, b):
+    """Spatially uniform steady state (alpha_2 + beta_1, beta_1/(alpha_2+beta_1)^2)."""
+    return [a + b, b / (a + b) ** 2]
+
+
+def schnakenberg_jacobian(U, a, b):
+    """J[r][s] = d g_r / d w_s, pointwise."""
+    u, v = U
+    return [[-1.0 + 2.0 * u * v, u * u], [-2.0 * u * v, -u * u]]
+
+
+# --- BVAM kinetics, eq. (BVAMnl) ---------------------------------------------
+
+BVAM_FIG1 = dict(gamma=3.87e-3, delta=7.5e-3, alpha1=8.99e-1, alpha2=2e-1,
+                 alpha3=2e-1, beta1=-9.1e-1, beta2=-8.99e-1)
+
+
+def bvam(U, alpha1, alpha2, alpha3, beta1, beta2):
+    u, v = U
+    bu = alpha1 * u * (1.0 - alpha2 * v * v) + v * (1.0 - alpha3 * u)
+    cv = beta1 * v * (1.0 + alpha1 * alpha2 / beta1 * u * v) + u * (beta2 + alpha3 * v)
+    return [bu, cv]
+
+
+def bvam_exact(t, rho, theta):
+    """Exact solution of the Section 5.1 test (u, v) on a (rho, theta) mesh."""
+    f = np.exp(-t) * (1.0 - rho) ** 2
+    return [f * np.exp(np.cos(theta) / 10.0), f * np.exp(np.sin(theta) / 10.0)]
+
+
+def bvam_sources(t, rho, theta, p=BVAM_FIG1):
+    """Manufactured sources b_s, c_s of Section 5.1.
+
+    b_s = d_t u - gamma Lap_D u - b(u, v) with the *continuous* polar
+    Laplacian (eq. (lapdisk)) of the exact solution, likewise c_s.
+    For u = e^{-t} f(rho) g(theta): Lap_D u = e^{-t}[(f'/rho + f'') g + f g''/rho^2].
+    """
+    et = math.exp(-t)
+    f = (1.0 - rho) ** 2
+    f1 = -2.0 * (1.0 - rho)
+    f2 = 2.0 * np.ones_like(rho)
+    gu = np.exp(np.cos(theta) / 10.0)
+    gu2 = (np.sin(theta) ** 2 / 100.0 - np.cos(theta) / 10.0) * gu
+    gv = np.exp(np.sin(theta) / 10.0)
+    gv2 = (np.cos(theta) ** 2 / 100.0 - np.sin(theta) / 10.0) * gv
+    u = et * f * gu
+    v = et * f * gv
+    lap_u = et * ((f1 / rho + f2) * gu + f * gu2 / rho**2)
+    lap_v = et * ((f1 / rho + f2) * gv + f * gv2 / rho**2)
+    r = bvam([u, v], p["alpha1"], p["alpha2"], p["alpha3"], p["beta1"], p["beta2"])
+    bs = -u - p["gamma"] * lap_u - r[0]
+    cs = -v - p["delta"] * lap_v - r[1]
+    return [bs, cs]
+
+
+# --- 3-species activator / substrate / inhibitor (builder's model) ----------
+# g_u = a - u + u^2 v - kappa u w,  g_v = b - u^2 v,  g_w = mu (u - w).
+# Not from the paper: it is the reading adopted for the 3-species workload.
+
+def ais3(U, a, b, kappa, mu):
+    u, v, w = U
+    u2v = u * u * v
+    return [a - u + u2v - kappa * u * w, b - u2v, mu * (u - w)]
+
+
+def ais3_equilibrium(a, b, kappa, mu):
+    ue = (-1.0 + math.sqrt(1.0 + 4.0 * kappa * (a + b))) / (2.0 * kappa)
+    return [ue, b / ue**2, ue]
+
+
+def ais3_jacobian(U, a, b, kappa, mu):
+    u, v, w = U
+    one = np.ones_like(u)
+    return [[-1.0 + 2.0 * u * v - kappa * w, u * u, -kappa * u],
+            [-2.0 * u * v, -u * u, 0.0 * one],
+            [mu * one, 0.0 * one, -mu * one]]
+
+
+MODELS = {
+    "schnakenberg": (schnakenberg, schnakenberg_equilibrium, schnakenberg_jacobian),
+    "ais3": (ais3, ais3_equilibrium, ais3_jacobian),
+}
+
+
+def reaction(kind, U, params):
+    return MODELS[kind][0](U, *params)
+
+
+def equilibrium(kind, params):
+    return MODELS[kind][1](*params)
+
+
+def jacobian(kind, U, params):
+    return MODELS[kind][2](U, *params)

@@ -1,0 +1,75 @@
+"""Pins of the gradient oracle (discrete adjoint of the split step).
+
+* the op chain reproduces the tensor-form split action;
+* dot-product identity <S x, y> = <x, S^T y>;
+* the d-derivative of the chain and the full gradient against central
+  finite differences in float64.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint, splitee
+import workloads
+
+GEOMS = [("disk", (5, 7)), ("sphere", (6, 5)), ("ball", (4, 5, 6)), ("cylinder", (4, 5, 3))]
+
+
+@pytest.mark.parametrize("geometry,n", GEOMS)
+def test_chain_matches_split_and_transpose(geometry, n):
+    se = splitee.SplitEE(geometry, n, [1.3, 9.0], 0.02)
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    for s in range(2):
+        ops = adjoint.chain(se, s)
+        Sx = adjoint.apply_chain(ops, x)
+        np.testing.assert_allclose(Sx, se.split_phi1(x, s), atol=1e-13)
+        lhs = np.sum(Sx * y)
+        rhs = np.sum(x * adjoint.apply_chain_T(ops, y))
+        assert abs(lhs - rhs) < 1e-13 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("geometry,n", GEOMS)
+def test_chain_derivative_in_d(geometry, n):
+    d, h = 4.0, 1e-4
+    x = np.random.default_rng(2).standard_normal(n)
+    dd = adjoint.apply_chain_dd(adjoint.chain(splitee.SplitEE(geometry, n, [d], 0.02), 0), x)
+    p = splitee.SplitEE(geometry, n, [d + h], 0.02).split_phi1(x, 0)
+    m = splitee.SplitEE(geometry, n, [d - h], 0.02).split_phi1(x, 0)
+    np.testing.assert_allclose(dd, (p - m) / (2 * h), atol=1e-8 * np.abs(dd).max())
+
+
+def _richardson(f, h):
+    """Central difference with one Richardson step (error O(h^4))."""
+    c1 = (f(h) - f(-h)) / (2 * h)
+    c2 = (f(h / 2) - f(-h / 2)) / h
+    return (4 * c2 - c1) / 3, c1
+
+
+def test_gradient_vs_central_differences():
+    w = workloads.scaled(workloads.WORKLOADS["disk_256x512"], (6, 8), steps=5)
+    pert = workloads.perturbation(w)
+    W0 = splitee.initial_state(w, pert)
+    target = W0[0] + 1e-3 * np.random.default_rng(7).random(w.n)
+    L, lam0, gd, gp = adjoint.loss_and_grad(w, W0, target, w.steps)
+    h = 1e-4
+    dirs = [np.random.default_rng(9).standard_normal(w.n) for _ in range(2)]
+    ic = lambda e: adjoint.loss(w, [W0[0] + e * dirs[0], W0[1] + e * dirs[1]], target, w.steps)  # noqa
+    an = np.sum(lam0[0] * dirs[0]) + np.sum(lam0[1] * dirs[1])
+    rich, plain = _richardson(ic, h)
+    assert abs(plain - an) < 1e-5 * abs(an)  # plain central difference, h = 1e-4
+    assert abs(rich - an) < 1e-9 * abs(an)
+    scale = max(np.abs(gd).max(), np.abs(gp).max())
+    for s in range(2):
+        def fd(e, s=s):
+            d = list(w.diff)
+            d[s] += e
+            return adjoint.loss(w, W0, target, w.steps, diff=d)
+        rich, _ = _richardson(fd, h)
+        assert abs(rich - gd[s]) < 1e-6 * abs(gd[s]) + 1e-7 * scale
+    for q in range(2):
+        def fp(e, q=q):
+            p = list(w.params)
+            p[q] += e
+            return adjoint.loss(w, W0, target, w.steps, params=p)
+        rich, _ = _richardson(fp, h)
+        assert abs(rich - gp[q]) < 1e-6 * abs(gp[q]) + 1e-7 * scale
