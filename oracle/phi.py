@@ -44,14 +44,30 @@ def eig_tridiag(A: np.ndarray):
     """
     if np.allclose(A, A.T, rtol=0, atol=0):
         lam, Q = np.linalg.eigh(A)
+        _exact_zero_eigenvalue(A, lam)
         return lam, Q, Q.T.copy()
     xi = symmetriser(A)
     S = (A * xi[None, :]) / xi[:, None]  # Xi^{-1} A Xi
     S = 0.5 * (S + S.T)  # exact symmetry up to rounding of the products above
     lam, Q = np.linalg.eigh(S)
+    _exact_zero_eigenvalue(A, lam)
     V = xi[:, None] * Q
     Vinv = Q.T / xi[None, :]
     return lam, V, Vinv
+
+
+def _exact_zero_eigenvalue(A, lam):
+    """Operators with zero row sums (Neumann, periodic and pole-free ends)
+    have the constants as an eigenvector with eigenvalue exactly 0, the case
+    the scalar phi_1(0) = 1 of Section 4 is written for.  The eigensolver
+    returns it only to O(eps ||A||); that residue, multiplied by tau d and
+    by 1/rho^2 or 1/sin^2 scalings, would perturb the constant mode, so the
+    eigenvalue closest to 0 is set to 0 exactly."""
+    scale = np.abs(A).max()
+    if np.abs(A.sum(axis=1)).max() <= 1e-12 * scale:
+        k = int(np.argmin(np.abs(lam)))
+        assert abs(lam[k]) <= 1e-10 * scale
+        lam[k] = 0.0
 
 
 def phi1_matrix(A: np.ndarray, c: float) -> np.ndarray:
