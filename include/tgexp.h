@@ -1,0 +1,153 @@
+/*
+ * tgexp -- split exponential Euler for diffusion-reaction systems on the
+ * disk, sphere, ball and cylinder, on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Caliari & Cassini, "A tensor-based exponential
+ * integrator for diffusion-reaction equations in common curvilinear
+ * coordinates":
+ *   - grids and 1D finite-difference operators: Section 3, Table 1,
+ *     eqs. (A_theta), (disk_discr), (ball_discr), (syscn), (A_phi), (A_z);
+ *   - Kronecker-sum Laplacians M = M_1 + ... + M_d: Section 2,
+ *     eqs. (disk), (sphere), (ball), (cylinder);
+ *   - one step for species s of an N-coupled system (Section 4, eqs.
+ *     (ee), (splitorder), (BVAM_SExpE)):
+ *         F_s   = d_s M W_s + g_s(W)
+ *         W_s  <- W_s + tau phi_1(tau d_s M_1) ... phi_1(tau d_s M_d) F_s,
+ *     the factors applied as mu-mode products in the order of eqs.
+ *     (ee_disk), (ee_sphere), (ee_ball), (ee_cylinder) (M_d first).
+ *
+ * Conventions
+ *   - Every function returns 0 (TG_OK) or a negative TG_E* code; the text
+ *     of the last error of the calling thread is returned by
+ *     tg_last_error().  Nothing throws across this interface.
+ *   - Grid sizes n[] are given in the paper's coordinate order:
+ *       disk (n_rho, n_theta); sphere (n_theta, n_phi);
+ *       ball (n_rho, n_theta, n_phi); cylinder (n_rho, n_theta, n_z).
+ *     Each n must be >= 3.
+ *   - State layout (device memory, caller-owned): C-contiguous
+ *     [batch][n_species][n3][n2][n1], first coordinate fastest, i.e. the
+ *     paper's vectorisation w_{i + (j-1) n1 + (k-1) n1 n2} per species
+ *     (2D: n3 = 1).  Element type is double for TG_FP64 and float for
+ *     TG_FP32 / TG_BF16X2 / TG_BF16X3.
+ *   - The state holds deviations W - w_ref from a per-(instance, species)
+ *     reference state (by default the homogeneous equilibrium of the
+ *     reaction).  For the cylinder the Dirichlet value at z_* is w_ref.
+ *   - Device pointers and the hipStream_t argument (passed as void*, NULL =
+ *     default stream) are the caller's; calls enqueue work asynchronously
+ *     unless stated otherwise.  A plan owns its device factors and scratch
+ *     buffers until tg_plan_destroy.  Calls on one plan must not overlap.
+ */
+#ifndef TGEXP_H
+#define TGEXP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TG_OK = 0,
+  TG_EINVAL = -1,     /* invalid argument (sizes, kinds, null pointers) */
+  TG_ENOMEM = -2,     /* device or host allocation failed */
+  TG_EHIP = -3,       /* HIP runtime error (launch, copy, graph) */
+  TG_ENOTSUP = -4,    /* combination not supported */
+  TG_ENONFINITE = -5  /* a non-finite value was produced by the update */
+};
+
+enum { TG_DISK = 0, TG_SPHERE = 1, TG_BALL = 2, TG_CYLINDER = 3 };
+
+/* Arithmetic of the mu-mode products.  Factors are always computed in
+ * FP64 on the host and rounded to the storage type.
+ *   TG_FP64   : FP64 MFMA, FP64 state.
+ *   TG_FP32   : FP32 MFMA, FP32 state.
+ *   TG_BF16X2 / TG_BF16X3 : reserved (bf16-split products). */
+enum { TG_FP64 = 0, TG_FP32 = 1, TG_BF16X2 = 2, TG_BF16X3 = 3 };
+
+/* Reaction g(w) (explicit, evaluated at t_n).  params per instance:
+ *   TG_REACT_SCHNAKENBERG: (a, b):  g_u = a - u + u^2 v,  g_v = b - u^2 v
+ *       (paper eq. (schnaknl) with alpha_1 = 1); equilibrium
+ *       (a + b, b / (a + b)^2).
+ *   TG_REACT_AIS3: (a, b, kappa, mu), three species (u, v, w):
+ *       g_u = a - u + u^2 v - kappa u w, g_v = b - u^2 v, g_w = mu (u - w).
+ *   TG_REACT_NONE: g = 0 (pure diffusion). */
+enum { TG_REACT_NONE = 0, TG_REACT_SCHNAKENBERG = 1, TG_REACT_AIS3 = 2 };
+
+/* tg_apply_operator selectors */
+enum { TG_APPLY_F = 0, TG_APPLY_DIFFUSION = 1, TG_APPLY_REACTION = 2 };
+
+typedef struct tg_grid_s* tg_grid;
+typedef struct tg_plan_s* tg_plan;
+
+/* Thread-local text of the last failure; never NULL. */
+const char* tg_last_error(void);
+/* Interface version (incremented on incompatible change). */
+int tg_version(void);
+
+/* ---- grid and operator set-up (host, FP64) ------------------------------
+ * extent = {rho_*, z_*}: radius of disk / ball / cylinder, or of the sphere
+ * (its operator is scaled by rho_*^-2), and the cylinder height (ignored
+ * elsewhere).  NULL means {1, 1}.  Section 3, Table 1. */
+int tg_grid_create(int32_t geometry, const int32_t* n, const double* extent, tg_grid* out);
+int tg_grid_destroy(tg_grid g);
+/* ndim (2 or 3) and the n[] of the grid (n must hold 3 ints). */
+int tg_grid_dims(tg_grid g, int32_t* ndim, int32_t* n);
+/* Grid points of mode mode (1-based): rho_i, theta_j, phi_k or z_k. */
+int tg_grid_coords(tg_grid g, int32_t mode, double* out);
+/* The tridiagonal 1D operator of mode `mode` (unscaled, without D_rho /
+ * D_phi): row r has lo[r] (column r-1), diag[r], up[r] (column r+1).  For
+ * the periodic theta operator lo[0] couples to column n-1 and up[n-1] to
+ * column 0; otherwise those two entries are 0. */
+int tg_grid_operator(tg_grid g, int32_t mode, double* lo, double* diag, double* up);
+/* Real eigen-decomposition A = V diag(lam) Vinv of mode `mode`'s operator
+ * (row-major n x n; Proposition 1 for the tridiagonal ones, the closed-form
+ * real Fourier basis for theta). */
+int tg_grid_eig(tg_grid g, int32_t mode, double* lam, double* V, double* Vinv);
+/* phi_1(c A) of mode `mode`'s operator, row-major n x n (Section 4). */
+int tg_grid_phi1(tg_grid g, int32_t mode, double c, double* out);
+
+/* ---- plans ---------------------------------------------------------------
+ * diff[batch][n_species] diffusion coefficients d_s; params[batch][n_params]
+ * reaction constants; w_ref[batch][n_species] the deviation origin or NULL
+ * for the reaction's homogeneous equilibrium (zeros for TG_REACT_NONE).
+ * tau > 0 is the time step.  Computes every phi_1 factor in FP64, rounds
+ * it to the precision's storage type and uploads it; allocates two
+ * state-sized scratch buffers.  Synchronous. */
+int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* diff,
+                   int32_t reaction, int32_t n_params, const double* params,
+                   const double* w_ref, double tau, int32_t precision, tg_plan* out);
+int tg_plan_destroy(tg_plan p);
+/* Number of state elements (batch * n_species * n1 * n2 * n3) and the
+ * element size in bytes. */
+int tg_plan_state_size(tg_plan p, int64_t* elems, int32_t* elem_bytes);
+/* The reference state w_ref used by the plan, [batch][n_species]. */
+int tg_plan_reference(tg_plan p, double* w_ref);
+
+/* One step of the split exponential Euler method on `state` (in place). */
+int tg_step(tg_plan p, void* state, void* stream);
+/* n_steps steps (in place); steps are replayed from a captured HIP graph.
+ * Synchronises the stream at the end and returns TG_ENONFINITE if any
+ * update produced a non-finite value. */
+int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
+
+/* Test hooks for the pieces of one step (same layouts as the state):
+ *   what = TG_APPLY_F:         out = d_s M in + g(in)     (the F stage)
+ *   what = TG_APPLY_DIFFUSION: out = d_s M in
+ *   what = TG_APPLY_REACTION:  out = g(in)
+ * in and out must not overlap. */
+int tg_apply_operator(tg_plan p, const void* in, void* out, int32_t what, void* stream);
+/* out = phi_1(tau d_s M_1) ... phi_1(tau d_s M_d) in, per species. */
+int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream);
+/* Number of mu-mode products in the plan's split chain (in application
+ * order, eqs. (ee_*)) and, if modes != NULL, the mode mu of each. */
+int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes);
+/* Benchmark / test hook: apply chain product `op` (0-based) alone,
+ * out = in x_mu L (with its Hadamard phi_1 factor where the chain has one;
+ * the final update is replaced by a plain store). */
+int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TGEXP_H */

@@ -1,0 +1,700 @@
+// C interface: grids, plans (FP64 factor precompute + upload) and the step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <limits>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tgexp.h"
+#include "plan.hpp"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+struct Fail : std::runtime_error {
+  int code;
+  Fail(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TG_REQUIRE(cond, code, msg) \
+  do {                              \
+    if (!(cond)) throw Fail((code), (msg)); \
+  } while (0)
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    throw Fail(TG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Fail& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return TG_ENOMEM;
+  } catch (const std::invalid_argument& e) {
+    g_last_error = e.what();
+    return TG_EINVAL;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return TG_EINVAL;
+  }
+}
+
+// Host staging of the plan's small device arrays and factors: every block
+// is 256-byte aligned inside one allocation.
+struct Arena {
+  std::vector<char> bytes;
+  size_t add(const void* src, size_t n) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+  size_t add_d(const std::vector<double>& v) { return add(v.data(), v.size() * sizeof(double)); }
+  template <typename T>
+  size_t add_t(const std::vector<double>& v) {
+    std::vector<T> t(v.begin(), v.end());
+    return add(t.data(), t.size() * sizeof(T));
+  }
+};
+
+std::vector<double> transpose(const std::vector<double>& A, int n) {
+  std::vector<double> B(A.size());
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) B[c * n + r] = A[r * n + c];
+  return B;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+double tg_grid_s::extent_of(int mode) const {
+  switch (coord[mode]) {
+    case tg::RHO2:
+    case tg::RHO3: return extent[0];
+    case tg::ZED: return extent[1];
+    default: return 1.0;
+  }
+}
+tg::Tridiag tg_grid_s::op(int mode) const { return tg::coord_operator(coord[mode], n[mode], extent_of(mode)); }
+std::vector<double> tg_grid_s::coords(int mode) const {
+  return tg::coord_grid(coord[mode], n[mode], extent_of(mode));
+}
+tg::Eig tg_grid_s::eig(int mode) const {
+  if (coord[mode] == tg::THETA) return tg::eig_theta(n[mode]);
+  return tg::eig_tridiag(op(mode));
+}
+
+extern "C" {
+
+const char* tg_last_error(void) { return g_last_error.c_str(); }
+int tg_version(void) { return 1; }
+
+int tg_grid_create(int32_t geometry, const int32_t* n, const double* extent, tg_grid* out) {
+  return guarded([&] {
+    TG_REQUIRE(n && out, TG_EINVAL, "tg_grid_create: null pointer");
+    auto g = new tg_grid_s();
+    g->geometry = geometry;
+    switch (geometry) {
+      case TG_DISK: g->ndim = 2; g->coord[0] = tg::RHO2; g->coord[1] = tg::THETA; break;
+      case TG_SPHERE: g->ndim = 2; g->coord[0] = tg::THETA; g->coord[1] = tg::PHI; break;
+      case TG_BALL: g->ndim = 3; g->coord[0] = tg::RHO3; g->coord[1] = tg::THETA; g->coord[2] = tg::PHI; break;
+      case TG_CYLINDER: g->ndim = 3; g->coord[0] = tg::RHO2; g->coord[1] = tg::THETA; g->coord[2] = tg::ZED; break;
+      default: delete g; throw Fail(TG_EINVAL, "tg_grid_create: unknown geometry");
+    }
+    for (int m = 0; m < g->ndim; ++m) {
+      if (n[m] < 3 || n[m] > 65536) {
+        delete g;
+        throw Fail(TG_EINVAL, "tg_grid_create: each n must be in [3, 65536]");
+      }
+      g->n[m] = n[m];
+    }
+    if (extent) {
+      if (!(extent[0] > 0.0) || !(extent[1] > 0.0)) {
+        delete g;
+        throw Fail(TG_EINVAL, "tg_grid_create: extents must be positive");
+      }
+      g->extent[0] = extent[0];
+      g->extent[1] = extent[1];
+    }
+    *out = g;
+    return TG_OK;
+  });
+}
+
+int tg_grid_destroy(tg_grid g) {
+  delete g;
+  return TG_OK;
+}
+
+int tg_grid_dims(tg_grid g, int32_t* ndim, int32_t* n) {
+  return guarded([&] {
+    TG_REQUIRE(g && ndim && n, TG_EINVAL, "tg_grid_dims: null pointer");
+    *ndim = g->ndim;
+    for (int m = 0; m < 3; ++m) n[m] = g->n[m];
+    return TG_OK;
+  });
+}
+
+static int check_mode(tg_grid g, int32_t mode) {
+  TG_REQUIRE(g, TG_EINVAL, "null grid");
+  TG_REQUIRE(mode >= 1 && mode <= g->ndim, TG_EINVAL, "mode out of range");
+  return mode - 1;
+}
+
+int tg_grid_coords(tg_grid g, int32_t mode, double* out) {
+  return guarded([&] {
+    const int m = check_mode(g, mode);
+    TG_REQUIRE(out, TG_EINVAL, "null output");
+    auto c = g->coords(m);
+    std::memcpy(out, c.data(), c.size() * sizeof(double));
+    return TG_OK;
+  });
+}
+
+int tg_grid_operator(tg_grid g, int32_t mode, double* lo, double* diag, double* up) {
+  return guarded([&] {
+    const int m = check_mode(g, mode);
+    TG_REQUIRE(lo && diag && up, TG_EINVAL, "null output");
+    auto T = g->op(m);
+    std::memcpy(lo, T.lo.data(), T.n * sizeof(double));
+    std::memcpy(diag, T.dg.data(), T.n * sizeof(double));
+    std::memcpy(up, T.up.data(), T.n * sizeof(double));
+    return TG_OK;
+  });
+}
+
+int tg_grid_eig(tg_grid g, int32_t mode, double* lam, double* V, double* Vinv) {
+  return guarded([&] {
+    const int m = check_mode(g, mode);
+    TG_REQUIRE(lam && V && Vinv, TG_EINVAL, "null output");
+    auto e = g->eig(m);
+    std::memcpy(lam, e.lam.data(), e.n * sizeof(double));
+    std::memcpy(V, e.V.data(), e.V.size() * sizeof(double));
+    std::memcpy(Vinv, e.Vinv.data(), e.Vinv.size() * sizeof(double));
+    return TG_OK;
+  });
+}
+
+int tg_grid_phi1(tg_grid g, int32_t mode, double c, double* out) {
+  return guarded([&] {
+    const int m = check_mode(g, mode);
+    TG_REQUIRE(out && std::isfinite(c), TG_EINVAL, "bad argument");
+    auto P = tg::phi1_from_eig(g->eig(m), c);
+    std::memcpy(out, P.data(), P.size() * sizeof(double));
+    return TG_OK;
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+namespace {
+
+std::vector<double> default_reference(int reaction, int ns, const double* rp) {
+  std::vector<double> w(ns, 0.0);
+  if (reaction == TG_REACT_SCHNAKENBERG) {
+    const double a = rp[0], b = rp[1];
+    w[0] = a + b;
+    w[1] = b / ((a + b) * (a + b));
+  } else if (reaction == TG_REACT_AIS3) {
+    const double a = rp[0], b = rp[1], kap = rp[2];
+    const double ue = (-1.0 + std::sqrt(1.0 + 4.0 * kap * (a + b))) / (2.0 * kap);
+    w[0] = ue;
+    w[1] = b / (ue * ue);
+    w[2] = ue;
+  }
+  return w;
+}
+
+std::vector<double> reaction_at(int reaction, int ns, const double* rp, const double* w) {
+  std::vector<double> g(ns, 0.0);
+  if (reaction == TG_REACT_SCHNAKENBERG) {
+    const double u2v = w[0] * w[0] * w[1];
+    g[0] = rp[0] - w[0] + u2v;
+    g[1] = rp[1] - u2v;
+  } else if (reaction == TG_REACT_AIS3) {
+    const double u2v = w[0] * w[0] * w[1];
+    g[0] = rp[0] - w[0] + u2v - rp[2] * w[0] * w[2];
+    g[1] = rp[1] - u2v;
+    g[2] = rp[3] * (w[0] - w[2]);
+  }
+  return g;
+}
+
+// Pick the GEMM tile: the largest tile that still gives about two
+// workgroups per compute unit, else the smallest.
+int pick_tile(int M, int N, int64_t batches) {
+  const int64_t want = 512;
+  const int tms[4] = {64, 32, 64, 32}, tns[4] = {64, 64, 32, 32};
+  for (int t = 0; t < 4; ++t) {
+    const int64_t wg = static_cast<int64_t>((M + tms[t] - 1) / tms[t]) * ((N + tns[t] - 1) / tns[t]) * batches;
+    if (wg >= want) return t;
+  }
+  return 3;
+}
+
+template <typename T>
+void build_plan(tg_plan_s* P) {
+  const tg_grid_s& G = P->grid;
+  const int nd = G.ndim;
+  const int n1 = G.n[0], n2 = G.n[1], n3 = nd == 3 ? G.n[2] : 1;
+  const int nslab = P->nslab;
+  const double tau = P->tau;
+  Arena ar;
+  // stencil coefficients and scales: [3 modes][3][nmax]
+  const int nmax = std::max(n1, std::max(n2, n3));
+  P->nmax = nmax;
+  std::vector<double> coef(9 * nmax, 0.0), scale(9 * nmax, 1.0);
+  P->periodic_mask = 0;
+  for (int m = 0; m < nd; ++m) {
+    auto T_ = G.op(m);
+    if (T_.periodic) P->periodic_mask |= 1 << m;
+    for (int r = 0; r < T_.n; ++r) {
+      coef[(m * 3 + 0) * nmax + r] = T_.lo[r];
+      coef[(m * 3 + 1) * nmax + r] = T_.dg[r];
+      coef[(m * 3 + 2) * nmax + r] = T_.up[r];
+    }
+  }
+  auto set_scale = [&](int mode, int coord, const std::vector<double>& v) {
+    for (size_t r = 0; r < v.size(); ++r) scale[(mode * 3 + coord) * nmax + r] *= v[r];
+  };
+  auto inv2 = [](const std::vector<double>& x) {
+    std::vector<double> y(x.size());
+    for (size_t i = 0; i < x.size(); ++i) y[i] = 1.0 / (x[i] * x[i]);
+    return y;
+  };
+  auto sininv2 = [](const std::vector<double>& x, double s) {
+    std::vector<double> y(x.size());
+    for (size_t i = 0; i < x.size(); ++i) {
+      const double si = std::sin(x[i]);
+      y[i] = s / (si * si);
+    }
+    return y;
+  };
+  // per-slab tau * d_s
+  std::vector<double> cs(nslab);
+  for (int s = 0; s < nslab; ++s) cs[s] = tau * P->diff[s];
+  // distinct factors: per species if every instance shares d, else per slab
+  bool shared = true;
+  for (int b = 1; b < P->batch && shared; ++b)
+    for (int s = 0; s < P->ns; ++s)
+      if (P->diff[b * P->ns + s] != P->diff[s]) shared = false;
+  const int fmod = shared ? P->ns : nslab;
+  auto per_slab_factor = [&](const tg::Eig& e, double extra) {
+    std::vector<double> all;
+    all.reserve(static_cast<size_t>(fmod) * e.n * e.n);
+    for (int f = 0; f < fmod; ++f) {
+      auto Pm = tg::phi1_from_eig(e, cs[f] * extra);
+      all.insert(all.end(), Pm.begin(), Pm.end());
+    }
+    return all;
+  };
+
+  struct PendingOp {
+    int mode, epi, fmod;
+    size_t L, pm = SIZE_MAX, pn = SIZE_MAX, pb = SIZE_MAX;
+  };
+  std::vector<PendingOp> ops;
+  const double s2 = (G.geometry == TG_SPHERE) ? 1.0 / (G.extent[0] * G.extent[0]) : 1.0;
+
+  if (G.geometry == TG_DISK) {  // eq. (ee_disk)
+    auto rinv2 = inv2(G.coords(0));
+    set_scale(1, 0, rinv2);
+    auto et = G.eig(1);
+    auto er = G.eig(0);
+    PendingOp o1{2, tg::EPI_PHI, 1, ar.add_t<T>(et.Vinv)};
+    o1.pm = ar.add_d(et.lam);
+    o1.pn = ar.add_d(rinv2);
+    PendingOp o2{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
+    PendingOp o3{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(per_slab_factor(er, 1.0))};
+    ops = {o1, o2, o3};
+  } else if (G.geometry == TG_SPHERE) {  // eq. (ee_sphere)
+    auto sph = sininv2(G.coords(1), s2);
+    set_scale(0, 1, sph);
+    set_scale(1, 0, std::vector<double>(n1, s2));
+    auto et = G.eig(0);
+    auto ep = G.eig(1);
+    PendingOp o1{2, tg::EPI_STORE, fmod, ar.add_t<T>(per_slab_factor(ep, s2))};
+    PendingOp o2{1, tg::EPI_PHI, 1, ar.add_t<T>(et.Vinv)};
+    o2.pm = ar.add_d(sph);
+    o2.pn = ar.add_d(et.lam);
+    PendingOp o3{1, tg::EPI_UPDATE, 1, ar.add_t<T>(et.V)};
+    ops = {o1, o2, o3};
+  } else if (G.geometry == TG_BALL) {  // eq. (ee_ball)
+    auto rinv2 = inv2(G.coords(0));
+    auto sph = sininv2(G.coords(2), 1.0);
+    set_scale(1, 0, rinv2);
+    set_scale(1, 2, sph);
+    set_scale(2, 0, rinv2);
+    auto er = G.eig(0);
+    auto et = G.eig(1);
+    auto ep = G.eig(2);
+    std::vector<double> rinv2_a(static_cast<size_t>(n1) * n2);
+    for (int j = 0; j < n2; ++j)
+      for (int i = 0; i < n1; ++i) rinv2_a[j * n1 + i] = rinv2[i];
+    PendingOp o1{3, tg::EPI_PHI, 1, ar.add_t<T>(ep.Vinv)};
+    o1.pm = ar.add_d(ep.lam);
+    o1.pn = ar.add_d(rinv2_a);
+    PendingOp o2{3, tg::EPI_STORE, 1, ar.add_t<T>(ep.V)};
+    PendingOp o3{2, tg::EPI_PHI, 1, ar.add_t<T>(et.Vinv)};
+    o3.pm = ar.add_d(et.lam);
+    o3.pn = ar.add_d(rinv2);
+    o3.pb = ar.add_d(sph);
+    PendingOp o4{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
+    PendingOp o5{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(per_slab_factor(er, 1.0))};
+    ops = {o1, o2, o3, o4, o5};
+  } else {  // TG_CYLINDER, eq. (ee_cylinder)
+    auto rinv2 = inv2(G.coords(0));
+    set_scale(1, 0, rinv2);
+    auto er = G.eig(0);
+    auto et = G.eig(1);
+    auto ez = G.eig(2);
+    PendingOp o1{3, tg::EPI_STORE, fmod, ar.add_t<T>(per_slab_factor(ez, 1.0))};
+    PendingOp o2{2, tg::EPI_PHI, 1, ar.add_t<T>(et.Vinv)};
+    o2.pm = ar.add_d(et.lam);
+    o2.pn = ar.add_d(rinv2);
+    PendingOp o3{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
+    PendingOp o4{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(per_slab_factor(er, 1.0))};
+    ops = {o1, o2, o3, o4};
+  }
+
+  const size_t o_coef = ar.add_d(coef), o_scale = ar.add_d(scale);
+  const size_t o_diff = ar.add_d(P->diff), o_rp = ar.add_d(P->rparams);
+  const size_t o_wref = ar.add_d(P->wref), o_g0 = ar.add_d(P->g0), o_cs = ar.add_d(cs);
+
+  hip_check(hipMalloc(reinterpret_cast<void**>(&P->dmem), ar.bytes.size()), "hipMalloc(plan)");
+  hip_check(hipMemcpy(P->dmem, ar.bytes.data(), ar.bytes.size(), hipMemcpyHostToDevice), "hipMemcpy(plan)");
+  auto D = [&](size_t off) { return reinterpret_cast<const double*>(P->dmem + off); };
+  P->d_coef = D(o_coef);
+  P->d_scale = D(o_scale);
+  P->d_diff = D(o_diff);
+  P->d_rparams = D(o_rp);
+  P->d_wref = D(o_wref);
+  P->d_g0 = D(o_g0);
+  P->d_cs = D(o_cs);
+  const int nn[3] = {n1, n2, n3};
+  for (const auto& o : ops) {
+    tg::ChainOp c;
+    c.mode = o.mode;
+    c.L = P->dmem + o.L;
+    c.fmod = o.fmod;
+    c.epi = o.epi;
+    c.pm = o.pm == SIZE_MAX ? nullptr : D(o.pm);
+    c.pn = o.pn == SIZE_MAX ? nullptr : D(o.pn);
+    c.pb = o.pb == SIZE_MAX ? nullptr : D(o.pb);
+    int64_t na = 1, nb = 1;
+    for (int m = 0; m < o.mode - 1; ++m) na *= nn[m];
+    for (int m = o.mode; m < 3; ++m) nb *= nn[m];
+    const int nm = nn[o.mode - 1];
+    if (o.mode == 1) c.tile = pick_tile(static_cast<int>(nb), nm, nslab);
+    else c.tile = pick_tile(nm, static_cast<int>(na), nb * nslab);
+    P->chain.push_back(c);
+  }
+  const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
+  for (int i = 0; i < 2; ++i) hip_check(hipMalloc(&P->scratch[i], bytes), "hipMalloc(scratch)");
+  hip_check(hipMalloc(reinterpret_cast<void**>(&P->dflag), sizeof(int)), "hipMalloc(flag)");
+  hip_check(hipMemset(P->dflag, 0, sizeof(int)), "hipMemset(flag)");
+}
+
+// Launch one chain op reading X and writing Y (or updating Y += tau * acc).
+template <typename T>
+void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y, int epi, hipStream_t st) {
+  const int nd = P->grid.ndim;
+  const int nn[3] = {P->grid.n[0], P->grid.n[1], nd == 3 ? P->grid.n[2] : 1};
+  int64_t na = 1, nb = 1;
+  for (int m = 0; m < c.mode - 1; ++m) na *= nn[m];
+  for (int m = c.mode; m < 3; ++m) nb *= nn[m];
+  const int nm = nn[c.mode - 1];
+  tg::GemmArgs g{};
+  g.nslab = P->nslab;
+  g.epi = epi;
+  g.alpha = P->tau;
+  g.cs = P->d_cs;
+  g.pm = c.pm;
+  g.pn = c.pn;
+  g.pb = c.pb;
+  g.tile = c.tile;
+  g.flag = P->dflag;
+  const int64_t slab = P->npts;
+  const int big = std::numeric_limits<int>::max();
+  if (c.mode == 1) {
+    // C (nb x nm) = X (nb x nm, K-contiguous) * L^T
+    g.A = X; g.B = c.L; g.C = Y;
+    g.M = static_cast<int>(nb); g.N = nm; g.K = nm; g.nbatch = 1;
+    g.lda = nm; g.ldb = nm; g.ldc = nm;
+    g.a_sstride = slab; g.a_smod = big;
+    g.b_sstride = static_cast<int64_t>(nm) * nm; g.b_smod = c.fmod;
+    g.c_sstride = slab;
+    g.b_kcontig = 1;
+  } else {
+    // per b: C (nm x na) = L (nm x nm) * X_b (nm x na)
+    g.A = c.L; g.B = X; g.C = Y;
+    g.M = nm; g.N = static_cast<int>(na); g.K = nm; g.nbatch = static_cast<int>(nb);
+    g.lda = nm; g.ldb = na; g.ldc = na;
+    g.a_bstride = 0; g.b_bstride = nm * na; g.c_bstride = nm * na;
+    g.a_sstride = static_cast<int64_t>(nm) * nm; g.a_smod = c.fmod;
+    g.b_sstride = slab; g.b_smod = big;
+    g.c_sstride = slab;
+    g.b_kcontig = 0;
+  }
+  hip_check(tg::launch_mode_gemm<T>(g, st), "mode product launch");
+}
+
+template <typename T>
+void launch_stencil_stage(const tg_plan_s* P, const void* W, void* F, int what, hipStream_t st) {
+  tg::StencilArgs a{};
+  a.W = W;
+  a.F = F;
+  a.ndim = P->grid.ndim;
+  a.n[0] = P->grid.n[0];
+  a.n[1] = P->grid.n[1];
+  a.n[2] = P->grid.ndim == 3 ? P->grid.n[2] : 1;
+  a.nspecies = P->ns;
+  a.batch = P->batch;
+  a.what = what;
+  a.coef = P->d_coef;
+  a.scale = P->d_scale;
+  a.nmax = P->nmax;
+  a.periodic_mask = P->periodic_mask;
+  a.diff = P->d_diff;
+  a.reaction = P->reaction;
+  a.rparams = P->d_rparams;
+  a.wref = P->d_wref;
+  a.g0 = P->d_g0;
+  hip_check(tg::launch_stencil<T>(a, st), "stencil launch");
+}
+
+// Apply the split chain to `in`.  final_update: last op does state += tau*acc
+// on `out`; otherwise the last op stores into `out`.
+template <typename T>
+void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update, hipStream_t st) {
+  const size_t nops = P->chain.size();
+  const void* X = in;
+  int buf = (in == P->scratch[0]) ? 1 : 0;
+  for (size_t o = 0; o < nops; ++o) {
+    const auto& c = P->chain[o];
+    const bool last = (o + 1 == nops);
+    void* Y = last ? out : P->scratch[buf];
+    int epi = c.epi;
+    if (last) epi = final_update ? tg::EPI_UPDATE : tg::EPI_STORE;
+    launch_op<T>(P, c, X, Y, epi, st);
+    X = Y;
+    buf ^= 1;
+  }
+}
+
+template <typename T>
+void step_impl(tg_plan_s* P, void* state, hipStream_t st) {
+  launch_stencil_stage<T>(P, state, P->scratch[0], TG_APPLY_F, st);
+  run_chain<T>(P, P->scratch[0], state, true, st);
+}
+
+void step_any(tg_plan_s* P, void* state, hipStream_t st) {
+  if (P->precision == TG_FP64) step_impl<double>(P, state, st);
+  else step_impl<float>(P, state, st);
+}
+
+constexpr int kStepsPerGraph = 8;
+
+// A HIP graph of `steps` consecutive steps on `state`, captured once per
+// state pointer on the plan's private stream and replayed on the caller's.
+hipGraphExec_t step_graph(tg_plan_s* P, void* state, int steps) {
+  auto it = P->graphs.find(state);
+  if (it != P->graphs.end()) return it->second;
+  if (!P->capture_stream)
+    hip_check(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking), "capture stream");
+  hipGraph_t graph = nullptr;
+  hip_check(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  try {
+    for (int i = 0; i < steps; ++i) step_any(P, state, P->capture_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(P->capture_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(P->capture_stream, &graph), "end capture");
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  hip_check(e, "graph instantiate");
+  P->graphs[state] = ex;
+  return ex;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* diff, int32_t reaction,
+                   int32_t n_params, const double* params, const double* w_ref, double tau,
+                   int32_t precision, tg_plan* out) {
+  tg_plan_s* P = nullptr;
+  int rc = guarded([&] {
+    TG_REQUIRE(g && diff && out, TG_EINVAL, "tg_plan_create: null pointer");
+    TG_REQUIRE(batch >= 1 && batch <= 65535, TG_EINVAL, "tg_plan_create: batch out of range");
+    TG_REQUIRE(std::isfinite(tau) && tau > 0.0, TG_EINVAL, "tg_plan_create: tau must be positive");
+    TG_REQUIRE(precision == TG_FP64 || precision == TG_FP32, TG_ENOTSUP,
+               "tg_plan_create: precision not supported");
+    int need_ns = 0, need_np = 0;
+    switch (reaction) {
+      case TG_REACT_NONE: need_ns = -1; need_np = 0; break;
+      case TG_REACT_SCHNAKENBERG: need_ns = 2; need_np = 2; break;
+      case TG_REACT_AIS3: need_ns = 3; need_np = 4; break;
+      default: throw Fail(TG_EINVAL, "tg_plan_create: unknown reaction");
+    }
+    TG_REQUIRE(n_species >= 1 && n_species <= 3, TG_EINVAL, "tg_plan_create: 1 to 3 species");
+    TG_REQUIRE(need_ns < 0 || n_species == need_ns, TG_EINVAL, "tg_plan_create: species count does not match reaction");
+    TG_REQUIRE(n_params >= need_np && (n_params == 0 || params), TG_EINVAL, "tg_plan_create: missing reaction parameters");
+    P = new tg_plan_s();
+    P->grid = *g;
+    P->ns = n_species;
+    P->batch = batch;
+    P->nslab = n_species * batch;
+    TG_REQUIRE(P->nslab <= 65535, TG_EINVAL, "tg_plan_create: too many instances");
+    P->reaction = reaction;
+    P->precision = precision;
+    P->tau = tau;
+    P->esize = precision == TG_FP64 ? 8 : 4;
+    P->npts = static_cast<int64_t>(g->n[0]) * g->n[1] * (g->ndim == 3 ? g->n[2] : 1);
+    P->state_elems = P->npts * P->nslab;
+    P->diff.assign(diff, diff + P->nslab);
+    for (double d : P->diff) TG_REQUIRE(std::isfinite(d) && d > 0.0, TG_EINVAL, "tg_plan_create: diffusion must be positive");
+    P->rparams.assign(static_cast<size_t>(batch) * 4, 0.0);
+    for (int b = 0; b < batch; ++b)
+      for (int q = 0; q < n_params && q < 4; ++q) P->rparams[b * 4 + q] = params[b * n_params + q];
+    P->wref.resize(P->nslab);
+    P->g0.resize(P->nslab);
+    for (int b = 0; b < batch; ++b) {
+      std::vector<double> w = w_ref ? std::vector<double>(w_ref + b * n_species, w_ref + (b + 1) * n_species)
+                                    : default_reference(reaction, n_species, &P->rparams[b * 4]);
+      auto g0 = reaction_at(reaction, n_species, &P->rparams[b * 4], w.data());
+      for (int s = 0; s < n_species; ++s) {
+        P->wref[b * n_species + s] = w[s];
+        P->g0[b * n_species + s] = g0[s];
+      }
+    }
+    if (precision == TG_FP64) build_plan<double>(P);
+    else build_plan<float>(P);
+    *out = P;
+    return TG_OK;
+  });
+  if (rc != TG_OK && P) tg_plan_destroy(P);
+  return rc;
+}
+
+int tg_plan_destroy(tg_plan p) {
+  if (!p) return TG_OK;
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->dmem) (void)hipFree(p->dmem);
+  for (auto& s : p->scratch)
+    if (s) (void)hipFree(s);
+  if (p->dflag) (void)hipFree(p->dflag);
+  delete p;
+  return TG_OK;
+}
+
+int tg_plan_state_size(tg_plan p, int64_t* elems, int32_t* elem_bytes) {
+  return guarded([&] {
+    TG_REQUIRE(p && elems && elem_bytes, TG_EINVAL, "null pointer");
+    *elems = p->state_elems;
+    *elem_bytes = p->esize;
+    return TG_OK;
+  });
+}
+
+int tg_plan_reference(tg_plan p, double* w_ref) {
+  return guarded([&] {
+    TG_REQUIRE(p && w_ref, TG_EINVAL, "null pointer");
+    std::memcpy(w_ref, p->wref.data(), p->wref.size() * sizeof(double));
+    return TG_OK;
+  });
+}
+
+int tg_step(tg_plan p, void* state, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state, TG_EINVAL, "tg_step: null pointer");
+    step_any(p, state, static_cast<hipStream_t>(stream));
+    return TG_OK;
+  });
+}
+
+int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state && n_steps >= 0, TG_EINVAL, "tg_run: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t chunk = kStepsPerGraph;
+    const int64_t full = n_steps / chunk;
+    if (full > 0) {
+      hipGraphExec_t ex = step_graph(p, state, static_cast<int>(chunk));
+      for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(ex, st), "tg_run: graph launch");
+    }
+    for (int64_t it = full * chunk; it < n_steps; ++it) step_any(p, state, st);
+    int flag = 0;
+    hip_check(hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "tg_run: flag copy");
+    hip_check(hipStreamSynchronize(st), "tg_run: synchronize");
+    if (flag) {
+      hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_run: flag reset");
+      throw Fail(TG_ENONFINITE, "tg_run: non-finite value in the state");
+    }
+    return TG_OK;
+  });
+}
+
+int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_chain_op: bad pointers");
+    TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(p->chain.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const auto& c = p->chain[op];
+    const int epi = c.epi == tg::EPI_UPDATE ? tg::EPI_STORE : c.epi;
+    if (p->precision == TG_FP64) launch_op<double>(p, c, in, out, epi, st);
+    else launch_op<float>(p, c, in, out, epi, st);
+    return TG_OK;
+  });
+}
+
+int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes) {
+  return guarded([&] {
+    TG_REQUIRE(p && n_ops, TG_EINVAL, "tg_plan_chain: null pointer");
+    *n_ops = static_cast<int32_t>(p->chain.size());
+    if (modes)
+      for (size_t i = 0; i < p->chain.size(); ++i) modes[i] = p->chain[i].mode;
+    return TG_OK;
+  });
+}
+
+int tg_apply_operator(tg_plan p, const void* in, void* out, int32_t what, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_operator: bad pointers");
+    TG_REQUIRE(what >= 0 && what <= 2, TG_EINVAL, "tg_apply_operator: bad selector");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == TG_FP64) launch_stencil_stage<double>(p, in, out, what, st);
+    else launch_stencil_stage<float>(p, in, out, what, st);
+    return TG_OK;
+  });
+}
+
+int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_split_phi1: bad pointers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == TG_FP64) run_chain<double>(p, in, out, false, st);
+    else run_chain<float>(p, in, out, false, st);
+    return TG_OK;
+  });
+}
+
+}  // extern "C"

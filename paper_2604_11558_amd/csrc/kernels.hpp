@@ -1,0 +1,68 @@
+// Device kernels of the split exponential Euler step and their launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tg {
+
+enum Epilogue : int { EPI_STORE = 0, EPI_PHI = 1, EPI_UPDATE = 2 };
+
+// One mu-mode product over a batch of "slabs" (species x instances), as a
+// GEMM C = A * B per (slab, batch b):
+//   strided mode (mu >= 2):  A = factor L (M x K, row-major), B = X_b (K x N,
+//                            row-major, N = product of faster modes), C = Y_b.
+//   first mode  (mu == 1):   A = X (M x K row-major, M = slower points),
+//                            B(k, n) = L[n][k] (factor stored N x K), C = Y.
+// Epilogues: EPI_STORE C = acc; EPI_PHI C = acc * phi_1(cs[s] pm[m] pn[n] pb[b])
+// (any of pm/pn/pb may be null = 1); EPI_UPDATE C += alpha * acc.
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  int nbatch;   // b range (strided mode); 1 otherwise
+  int nslab;
+  int64_t lda, ldb, ldc;
+  int64_t a_bstride, b_bstride, c_bstride;  // per b
+  int64_t a_sstride, b_sstride, c_sstride;  // per slab (times slab % *_smod)
+  int a_smod, b_smod;                       // modulus of slab index for factors
+  int b_kcontig;                            // B stored N x K (first-mode form)
+  int epi;
+  double alpha;
+  const double* cs;                // per slab phi_1 argument multiplier (tau d_s)
+  const double* pm;                // per row
+  const double* pn;                // per column
+  const double* pb;                // per batch b
+  int tile;                        // 0: 64x64, 1: 32x64, 2: 64x32, 3: 32x32
+  int* flag;                       // EPI_UPDATE: set to 1 if a non-finite value is written
+};
+
+template <typename T>
+hipError_t launch_mode_gemm(const GemmArgs& g, hipStream_t s);
+
+// F = d_s * M W (+ G(W)) pointwise stencil over all modes, deviation form.
+struct StencilArgs {
+  const void* W;
+  void* F;
+  int ndim;
+  int n[3];
+  int nspecies;
+  int batch;
+  int what;                 // 0: operator + reaction, 1: operator only, 2: reaction only
+  const double* coef;       // [3 modes][3][nmax]: lo, dg, up of each mode's operator
+  const double* scale;      // [3 modes][3 coords][nmax]: per-coordinate scale factors
+  int nmax;
+  int periodic_mask;        // bit mu-1 set: mode mu wraps around
+  const double* diff;       // [batch][nspecies]
+  int reaction;             // 0 none, 1 Schnakenberg, 2 AIS3
+  const double* rparams;    // [batch][4]
+  const double* wref;       // [batch][nspecies] reference state (deviation origin)
+  const double* g0;         // [batch][nspecies] reaction at the reference state
+};
+
+template <typename T>
+hipError_t launch_stencil(const StencilArgs& a, hipStream_t s);
+
+}  // namespace tg

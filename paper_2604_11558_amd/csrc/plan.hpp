@@ -1,0 +1,68 @@
+// Grid and plan objects behind the C interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hostmath.hpp"
+#include "kernels.hpp"
+
+struct tg_grid_s {
+  int geometry = 0;
+  int ndim = 0;
+  int n[3] = {1, 1, 1};
+  double extent[2] = {1.0, 1.0};
+  tg::Coord coord[3] = {tg::RHO2, tg::THETA, tg::PHI};
+  double extent_of(int mode) const;          // 0-based mode
+  tg::Tridiag op(int mode) const;            // 0-based mode, unscaled
+  std::vector<double> coords(int mode) const;
+  tg::Eig eig(int mode) const;
+};
+
+namespace tg {
+
+// One mu-mode product of the split chain, resolved to device pointers.
+struct ChainOp {
+  int mode = 1;            // 1-based mode index mu
+  const void* L = nullptr; // factor(s): fmod blocks of n_mu x n_mu, row-major (T)
+  int fmod = 1;            // slab s uses factor block s % fmod
+  int epi = EPI_STORE;     // EPI_UPDATE is replaced by EPI_STORE for the test hook
+  const double* pm = nullptr;
+  const double* pn = nullptr;
+  const double* pb = nullptr;
+  int tile = 0;
+};
+
+}  // namespace tg
+
+struct tg_plan_s {
+  tg_grid_s grid;
+  int ns = 0, batch = 0, nslab = 0;
+  int reaction = 0, precision = 0;
+  double tau = 0.0;
+  int64_t npts = 0, state_elems = 0;
+  int esize = 8;
+  std::vector<double> diff, rparams, wref, g0;
+  // device memory
+  char* dmem = nullptr;      // all small arrays and factors
+  void* scratch[2] = {nullptr, nullptr};
+  int* dflag = nullptr;
+  // device pointers into dmem
+  const double* d_coef = nullptr;
+  const double* d_scale = nullptr;
+  const double* d_diff = nullptr;
+  const double* d_rparams = nullptr;
+  const double* d_wref = nullptr;
+  const double* d_g0 = nullptr;
+  const double* d_cs = nullptr;
+  int nmax = 0;
+  int periodic_mask = 0;
+  std::vector<tg::ChainOp> chain;
+  // captured step graphs keyed by state pointer
+  std::map<void*, hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;
+};

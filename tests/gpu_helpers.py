@@ -1,0 +1,72 @@
+"""Shared set-up for GPU parity tests: build a plan and the oracle for the
+same seeded problem and convert between the two layouts."""
+from __future__ import annotations
+
+import numpy as np
+
+import workloads
+from oracle import assemble, reactions, splitee
+
+
+def model_for(geometry, n_species=2):
+    if n_species == 3:
+        return "ais3", workloads.AIS3, (1.0, 10.0, 40.0)
+    return "schnakenberg", workloads.SCHNAK, (1.0, 20.0)
+
+
+class Case:
+    """One problem: a plan on the device and the FP64 oracle on the host."""
+
+    def __init__(self, geometry, n, precision="fp64", tau=5e-3, n_species=2, batch=1,
+                 extent=(1.0, 1.0), seed=0, params=None, diff=None, amplitude=1e-3):
+        import paper_2604_11558_amd as tg
+        self.geometry, self.n, self.tau = geometry, tuple(n), tau
+        kind, p0, d0 = model_for(geometry, n_species)
+        self.kind = kind
+        self.params = np.atleast_2d(np.asarray(p0 if params is None else params, float))
+        if self.params.shape[0] == 1:
+            self.params = np.repeat(self.params, batch, axis=0)
+        self.diff = np.atleast_2d(np.asarray(d0 if diff is None else diff, float))
+        if self.diff.shape[0] == 1:
+            self.diff = np.repeat(self.diff, batch, axis=0)
+        self.batch, self.ns = batch, n_species
+        self.extent = extent
+        self.grid = tg.Grid(geometry, n, extent)
+        self.plan = tg.Plan(self.grid, self.diff, kind, self.params, tau, precision, batch)
+        shape = (batch, n_species) + tuple(reversed(self.n))
+        self.pert = amplitude * np.random.default_rng(seed).random(shape)
+        self.oracles = [splitee.SplitEE(geometry, n, self.diff[b], tau, extent) for b in range(batch)]
+        self.eq = [reactions.equilibrium(kind, tuple(self.params[b])) for b in range(batch)]
+
+    # layout helpers
+    def to_species(self, dev_b):
+        """[ns][n3][n2][n1] deviation of one instance -> list of [i,j,k] arrays."""
+        return [assemble.from_layout(dev_b[s]) for s in range(self.ns)]
+
+    def oracle_full(self, b):
+        return [self.eq[b][s] + W for s, W in enumerate(self.to_species(self.pert[b]))]
+
+    def oracle_run(self, steps):
+        out = []
+        for b in range(self.batch):
+            W = self.oracle_full(b)
+            react = lambda U, b=b: reactions.reaction(self.kind, U, tuple(self.params[b]))  # noqa
+            wd = self.eq[b] if self.geometry == "cylinder" else None
+            for _ in range(steps):
+                W = self.oracles[b].step(W, react, w_dirichlet=wd)
+            out.append(np.stack([assemble.to_layout(x) for x in W]))
+        return np.stack(out)  # [batch][ns][n3][n2][n1] full values
+
+    def device_state(self):
+        return self.plan.state_from_deviation(self.pert)
+
+    def full_from_device(self, t):
+        dev = t.detach().double().cpu().numpy().reshape((self.batch, self.ns) + tuple(reversed(self.n)))
+        ref = self.plan.reference[:, :, None, None, None] if len(self.n) == 3 else \
+            self.plan.reference[:, :, None, None]
+        return dev + ref
+
+
+def rel_err(a, b, mask=None):
+    """max |a - b| / max |b|."""
+    return float(np.abs(a - b).max() / np.abs(b).max())

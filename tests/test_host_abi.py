@@ -1,0 +1,86 @@
+"""CPU checks of the C interface: exported symbols and the host-side FP64
+set-up (grids, 1D operators, eigen-decompositions, phi_1 factors) against
+the oracle.  No GPU work is launched here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2604_11558_amd as tg
+from oracle import operators as op
+from oracle.phi import phi1_matrix
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "tgexp.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    names = set(re.findall(r"\b(tg_[a-z0-9_]+)\s*\(", header))
+    assert len(names) >= 15
+    L = tg.lib()
+    for name in sorted(names):
+        assert hasattr(L, name), name
+    assert L.tg_version() == 1
+
+
+def _oracle_ops(geometry, n, extent):
+    return op.operators_1d(geometry, n, extent)
+
+
+CASES = [("disk", (7, 12), (1.3, 1.0)), ("sphere", (10, 9), (1.0, 1.0)),
+         ("ball", (8, 6, 11), (0.8, 1.0)), ("cylinder", (9, 10, 7), (1.2, 2.5)),
+         ("ball", (64, 64, 128), (1.0, 1.0))]
+
+
+@pytest.mark.parametrize("geometry,n,extent", CASES)
+def test_grid_and_operators_match_oracle(geometry, n, extent):
+    g = tg.Grid(geometry, n, extent)
+    ref = _oracle_ops(geometry, n, extent)
+    for m in range(1, len(n) + 1):
+        np.testing.assert_allclose(g.coords(m), ref["grid"][m - 1], rtol=1e-15, atol=1e-15)
+        A = ref["A"][m - 1]
+        np.testing.assert_allclose(g.dense_operator(m), A, rtol=1e-14, atol=1e-14 * np.abs(A).max())
+
+
+@pytest.mark.parametrize("geometry,n,extent", CASES)
+def test_eigendecomposition(geometry, n, extent):
+    g = tg.Grid(geometry, n, extent)
+    for m in range(1, len(n) + 1):
+        A = g.dense_operator(m)
+        lam, V, Vi = g.eig(m)
+        scale = np.abs(A).max()
+        np.testing.assert_allclose(A @ V, V * lam[None, :], atol=2e-13 * scale * np.sqrt(n[m - 1]))
+        np.testing.assert_allclose(V @ Vi, np.eye(n[m - 1]), atol=1e-12)
+        np.testing.assert_allclose(np.sort(lam), np.sort(np.linalg.eigvals(A).real),
+                                   atol=1e-11 * scale)
+
+
+@pytest.mark.parametrize("geometry,n,extent", CASES[:4])
+@pytest.mark.parametrize("c", [1e-5, 3e-3, 0.2])
+def test_phi1_factor_matches_oracle(geometry, n, extent, c):
+    g = tg.Grid(geometry, n, extent)
+    ref = _oracle_ops(geometry, n, extent)
+    for m in range(1, len(n) + 1):
+        P = g.phi1(m, c)
+        R = phi1_matrix(ref["A"][m - 1], c)
+        np.testing.assert_allclose(P, R, atol=2e-14 * n[m - 1], rtol=0)
+
+
+def test_sigma_large_n():
+    g = tg.Grid("sphere", (8, 2049))
+    np.testing.assert_allclose(g.coords(2), op.phi_grid(2049), rtol=1e-15, atol=1e-15)
+
+
+@pytest.mark.parametrize("geometry,n", [("disk", (2, 8)), ("ball", (4, 4, 1)), ("nope", (4, 4))])
+def test_invalid_grid(geometry, n):
+    with pytest.raises((tg.TGError, KeyError, ValueError)) as ei:
+        tg.Grid(geometry, n)
+    if isinstance(ei.value, tg.TGError):
+        assert ei.value.code == -1
+
+
+def test_invalid_extent():
+    with pytest.raises(tg.TGError):
+        tg.Grid("disk", (4, 4), (0.0, 1.0))
