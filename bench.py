@@ -78,14 +78,6 @@ def time_chain_op(plan, op, x, y, reps, torch):
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
-def chain_flops(geometry, n, ns):
-    """Algorithmic flops of each chain product (2 n_mu per output element)."""
-    pts = int(np.prod(n))
-    mode_of = {"disk": [2, 2, 1], "sphere": [2, 1, 1], "ball": [3, 3, 2, 2, 1],
-               "cylinder": [3, 2, 2, 1]}[geometry]
-    return [2.0 * n[m - 1] * pts * ns for m in mode_of], mode_of
-
-
 def cpu_baseline(w, pert, steps):
     """Oracle steps on the host (set-up and one warm-up step excluded)."""
     from oracle import reactions, splitee
@@ -136,14 +128,29 @@ def main():
         torch.cuda.synchronize()
         sec = time_gpu_run(plan, x, args.steps, 0, torch)
         states[prec] = x.double().cpu().numpy()
-        # dominant kernel: the mode-3 product with the phi_1 Hadamard factor
-        flops, modes = chain_flops(w.geometry, w.n, w.n_species)
-        y = torch.empty_like(x)
-        op_times = [time_chain_op(plan, i, x, y, 200, torch) for i in range(len(modes))]
+        # per-launch timing of the step's kernels (HIP events on the launch stream)
+        chain = plan.chain()
+        bufs = [x, torch.empty_like(x), torch.empty_like(x)]
+        op_times = []
+        for i in range(len(chain)):
+            src = bufs[0] if i == 0 else bufs[1 + (i - 1) % 2]
+            dst = bufs[1 + i % 2]
+            op_times.append(time_chain_op(plan, i, src, dst, 200, torch))
         dom = int(np.argmax(op_times))
-        res[prec] = dict(sec=sec, setup=setup, op_times=op_times, dom=dom, flops=flops,
-                         modes=modes, ref=plan.reference.copy())
-        del plan, x, xw, y
+        route = plan.route
+        # the other routes for comparison
+        other = {}
+        for rname in ("generic", "fused_stencil_apart"):
+            plan.set_route(rname)
+            xg = plan.state_from_deviation(pert)
+            plan.run(xg, args.warmup)
+            other[rname] = time_gpu_run(plan, xg, min(args.steps, 200), 0, torch)
+            del xg
+        plan.set_route(route)
+        res[prec] = dict(sec=sec, setup=setup, op_times=op_times, dom=dom,
+                         flops=[f for _, f in chain], modes=[m for m, _ in chain],
+                         ref=plan.reference.copy(), route=route, other=other)
+        del plan, x, xw, bufs
         torch.cuda.empty_cache()
 
     dof = w.dof
@@ -178,11 +185,13 @@ def main():
         "speedup_fp32_vs_fp64": v32 / v64,
         "rel_err_fp32_vs_fp64": {"after_steps": args.steps, "vs_max_state": err_32_64,
                                  "vs_max_deviation": err_32_64_dev},
-        "chain_op_us": {p: [t * 1e6 for t in res[p]["op_times"]] for p in res},
+        "route": res["fp32"]["route"],
+        "launch_us": {p: [t * 1e6 for t in res[p]["op_times"]] for p in res},
+        "ms_per_step_other_routes": {p: {k: v * 1e3 for k, v in res[p]["other"].items()} for p in res},
         "plan_setup_s": {p: res[p]["setup"] for p in res},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": None,
-                     "kernel": f"mode_gemm_kernel<float> chain op {dom} (mode {r['modes'][dom]})",
+                     "kernel": f"launch {dom} of the {r['route']} route (leading mode {r['modes'][dom]})",
                      "flops_per_launch": r["flops"][dom],
                      "avg_launch_us": r["op_times"][dom] * 1e6},
     }

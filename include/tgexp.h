@@ -32,6 +32,8 @@
  *   - The state holds deviations W - w_ref from a per-(instance, species)
  *     reference state (by default the homogeneous equilibrium of the
  *     reaction).  For the cylinder the Dirichlet value at z_* is w_ref.
+ *   - Device buffers (state, hook inputs and outputs) must be aligned to 4
+ *     elements (16 bytes for float, 32 for double); TG_EINVAL otherwise.
  *   - Device pointers and the hipStream_t argument (passed as void*, NULL =
  *     default stream) are the caller's; calls enqueue work asynchronously
  *     unless stated otherwise.  A plan owns its device factors and scratch
@@ -138,12 +140,28 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
 int tg_apply_operator(tg_plan p, const void* in, void* out, int32_t what, void* stream);
 /* out = phi_1(tau d_s M_1) ... phi_1(tau d_s M_d) in, per species. */
 int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream);
-/* Number of mu-mode products in the plan's split chain (in application
- * order, eqs. (ee_*)) and, if modes != NULL, the mode mu of each. */
-int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes);
-/* Benchmark / test hook: apply chain product `op` (0-based) alone,
- * out = in x_mu L (with its Hadamard phi_1 factor where the chain has one;
- * the final update is replaced by a plain store). */
+/* Kernel route of a plan.  0 (default): fused launches -- the stencil and
+ * reaction inside the first product's tile load, each eigen-basis
+ * sandwich (x V^-1, Hadamard phi_1, x V) in one launch, and the theta
+ * sandwich, the rho product and the update in one launch per (rho, theta)
+ * plane when it fits in LDS.  2: the same fused products after a separate
+ * stencil + reaction launch.  1: one launch per mu-mode product plus the
+ * stencil launch.  Routes 0 and 2 fall back to 1 where a shape does not
+ * fit in LDS.  All routes compute the same step. */
+int tg_plan_set_route(tg_plan p, int32_t route);
+/* The route actually used by tg_step / tg_run (after fall-back). */
+int tg_plan_route(tg_plan p, int32_t* route);
+/* Number of launches of the active route's split chain (in application
+ * order, eqs. (ee_*)); if modes != NULL the mode mu of the leading product
+ * of each launch, and if flops != NULL its algorithmic flop count (2 n_mu
+ * per output element of every mu-mode product it performs). */
+int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops);
+/* Benchmark / test hook: run launch `op` (0-based) of the active route's
+ * split chain alone.  Route 1: out = in x_mu L (with its Hadamard phi_1
+ * factor where the chain has one).  Routes 0 and 2: as in a step, `in`
+ * being the previous launch's output, except for the first launch of route
+ * 0, which reads the state and evaluates F = d M W + g(W) itself.  A final
+ * update is replaced by a store. */
 int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream);
 
 #ifdef __cplusplus

@@ -21,6 +21,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 REACTION = {"none": 0, "schnakenberg": 1, "ais3": 2}
 APPLY = {"F": 0, "diffusion": 1, "reaction": 2}
 NDIM = {"disk": 2, "sphere": 2, "ball": 3, "cylinder": 3}
+ROUTES = {"fused": 0, "generic": 1, "fused_stencil_apart": 2}
 
 _c_int = ctypes.c_int32
 _c_i64 = ctypes.c_int64
@@ -48,8 +49,10 @@ _SIGNATURES = {
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
     "tg_apply_operator": (ctypes.c_int, [_p, _p, _p, _c_int, _p]),
     "tg_apply_split_phi1": (ctypes.c_int, [_p, _p, _p, _p]),
-    "tg_plan_chain": (ctypes.c_int, [_p, _pi, _pi]),
+    "tg_plan_chain": (ctypes.c_int, [_p, _pi, _pi, _pd]),
     "tg_apply_chain_op": (ctypes.c_int, [_p, _c_int, _p, _p, _p]),
+    "tg_plan_set_route": (ctypes.c_int, [_p, _c_int]),
+    "tg_plan_route": (ctypes.c_int, [_p, _pi]),
 }
 
 _lib = None
@@ -224,11 +227,26 @@ class Plan:
         _check(lib().tg_apply_operator(self._h, x.data_ptr(), out.data_ptr(), APPLY[what],
                                        _stream_ptr(stream)))
 
-    def chain_modes(self):
+    def set_route(self, route: str):
+        """'fused' (default), 'fused_stencil_apart' or 'generic'."""
+        _check(lib().tg_plan_set_route(self._h, ROUTES[route]))
+
+    @property
+    def route(self) -> str:
+        r = ctypes.c_int32()
+        _check(lib().tg_plan_route(self._h, ctypes.byref(r)))
+        return {v: k for k, v in ROUTES.items()}[r.value]
+
+    def chain(self):
+        """[(mode, flops)] of each launch of the active route's split chain."""
         n = ctypes.c_int32()
         modes = (ctypes.c_int32 * 16)()
-        _check(lib().tg_plan_chain(self._h, ctypes.byref(n), modes))
-        return [modes[i] for i in range(n.value)]
+        flops = (ctypes.c_double * 16)()
+        _check(lib().tg_plan_chain(self._h, ctypes.byref(n), modes, flops))
+        return [(modes[i], flops[i]) for i in range(n.value)]
+
+    def chain_modes(self):
+        return [m for m, _ in self.chain()]
 
     def apply_chain_op(self, op: int, x, out, stream=None):
         self._check_tensor(x)

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -233,6 +234,8 @@ std::vector<double> reaction_at(int reaction, int ns, const double* rp, const do
   return g;
 }
 
+constexpr size_t kLdsLimit = 160 * 1024;
+
 // Pick the GEMM tile: the largest tile that still gives about two
 // workgroups per compute unit, else the smallest.
 int pick_tile(int M, int N, int64_t batches) {
@@ -267,8 +270,10 @@ void build_plan(tg_plan_s* P) {
       coef[(m * 3 + 2) * nmax + r] = T_.up[r];
     }
   }
+  P->scale_mask = 0;
   auto set_scale = [&](int mode, int coord, const std::vector<double>& v) {
     for (size_t r = 0; r < v.size(); ++r) scale[(mode * 3 + coord) * nmax + r] *= v[r];
+    P->scale_mask |= 1 << (3 * mode + coord);
   };
   auto inv2 = [](const std::vector<double>& x) {
     std::vector<double> y(x.size());
@@ -309,6 +314,32 @@ void build_plan(tg_plan_s* P) {
   std::vector<PendingOp> ops;
   const double s2 = (G.geometry == TG_SPHERE) ? 1.0 / (G.extent[0] * G.extent[0]) : 1.0;
 
+  // Fused route: factors zero-padded to a multiple of 128 in both dimensions
+  // so that 16-wide vector loads over the padded k range stay in bounds.
+  struct PadF {
+    size_t off = SIZE_MAX;
+    int ld = 0, fmod = 1;
+  };
+  auto addpad = [&](const std::vector<double>& stack, int n, int blocks) {
+    PadF f;
+    f.ld = (n + 127) / 128 * 128;
+    f.fmod = blocks;
+    std::vector<double> pad(static_cast<size_t>(blocks) * f.ld * f.ld, 0.0);
+    for (int b = 0; b < blocks; ++b)
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c)
+          pad[(static_cast<size_t>(b) * f.ld + r) * f.ld + c] = stack[(static_cast<size_t>(b) * n + r) * n + c];
+    f.off = ar.add_t<T>(pad);
+    return f;
+  };
+  struct FSpec {
+    int kind = 0, mode = 1, nm = 0, na = 1, nb = 1, rows = 0;
+    int sandwich = 0, phi = 0, stencil = 0, plane = 0;
+    PadF L1, L2, Pf;
+    size_t pm = SIZE_MAX, pn = SIZE_MAX, pb = SIZE_MAX;
+  };
+  std::vector<FSpec> fspecs;
+
   if (G.geometry == TG_DISK) {  // eq. (ee_disk)
     auto rinv2 = inv2(G.coords(0));
     set_scale(1, 0, rinv2);
@@ -318,8 +349,15 @@ void build_plan(tg_plan_s* P) {
     o1.pm = ar.add_d(et.lam);
     o1.pn = ar.add_d(rinv2);
     PendingOp o2{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
-    PendingOp o3{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(per_slab_factor(er, 1.0))};
+    auto Pr = per_slab_factor(er, 1.0);
+    PendingOp o3{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(Pr)};
     ops = {o1, o2, o3};
+    FSpec a;  // theta sandwich with the stencil, then rho (plane tail when it fits)
+    a.mode = 2; a.nm = n2; a.na = n1; a.nb = 1;
+    a.sandwich = 1; a.phi = 1; a.stencil = 1; a.plane = 1;
+    a.L1 = addpad(et.Vinv, n2, 1); a.L2 = addpad(et.V, n2, 1); a.Pf = addpad(Pr, n1, fmod);
+    a.pm = o1.pm; a.pn = o1.pn;
+    fspecs = {a};
   } else if (G.geometry == TG_SPHERE) {  // eq. (ee_sphere)
     auto sph = sininv2(G.coords(1), s2);
     set_scale(0, 1, sph);
@@ -332,6 +370,14 @@ void build_plan(tg_plan_s* P) {
     o2.pn = ar.add_d(et.lam);
     PendingOp o3{1, tg::EPI_UPDATE, 1, ar.add_t<T>(et.V)};
     ops = {o1, o2, o3};
+    FSpec a;  // phi product with the stencil
+    a.mode = 2; a.nm = n2; a.na = n1; a.nb = 1; a.stencil = 1;
+    a.L1 = addpad(per_slab_factor(ep, s2), n2, fmod);
+    FSpec b;  // theta sandwich + update
+    b.kind = 1; b.mode = 1; b.nm = n1; b.rows = n2; b.sandwich = 1; b.phi = 1;
+    b.L1 = addpad(et.Vinv, n1, 1); b.L2 = addpad(et.V, n1, 1);
+    b.pm = o2.pm; b.pn = o2.pn;
+    fspecs = {a, b};
   } else if (G.geometry == TG_BALL) {  // eq. (ee_ball)
     auto rinv2 = inv2(G.coords(0));
     auto sph = sininv2(G.coords(2), 1.0);
@@ -353,21 +399,44 @@ void build_plan(tg_plan_s* P) {
     o3.pn = ar.add_d(rinv2);
     o3.pb = ar.add_d(sph);
     PendingOp o4{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
-    PendingOp o5{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(per_slab_factor(er, 1.0))};
+    auto Pr = per_slab_factor(er, 1.0);
+    PendingOp o5{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(Pr)};
     ops = {o1, o2, o3, o4, o5};
+    FSpec a;  // phi sandwich with the stencil
+    a.mode = 3; a.nm = n3; a.na = n1 * n2; a.nb = 1;
+    a.sandwich = 1; a.phi = 1; a.stencil = 1;
+    a.L1 = addpad(ep.Vinv, n3, 1); a.L2 = addpad(ep.V, n3, 1);
+    a.pm = o1.pm; a.pn = o1.pn;
+    FSpec b;  // theta sandwich + rho product + update over (rho, theta) planes
+    b.mode = 2; b.nm = n2; b.na = n1; b.nb = n3;
+    b.sandwich = 1; b.phi = 1; b.plane = 1;
+    b.L1 = addpad(et.Vinv, n2, 1); b.L2 = addpad(et.V, n2, 1); b.Pf = addpad(Pr, n1, fmod);
+    b.pm = o3.pm; b.pn = o3.pn; b.pb = o3.pb;
+    fspecs = {a, b};
   } else {  // TG_CYLINDER, eq. (ee_cylinder)
     auto rinv2 = inv2(G.coords(0));
     set_scale(1, 0, rinv2);
     auto er = G.eig(0);
     auto et = G.eig(1);
     auto ez = G.eig(2);
-    PendingOp o1{3, tg::EPI_STORE, fmod, ar.add_t<T>(per_slab_factor(ez, 1.0))};
+    auto Pz = per_slab_factor(ez, 1.0);
+    auto Pr = per_slab_factor(er, 1.0);
+    PendingOp o1{3, tg::EPI_STORE, fmod, ar.add_t<T>(Pz)};
     PendingOp o2{2, tg::EPI_PHI, 1, ar.add_t<T>(et.Vinv)};
     o2.pm = ar.add_d(et.lam);
     o2.pn = ar.add_d(rinv2);
     PendingOp o3{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
-    PendingOp o4{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(per_slab_factor(er, 1.0))};
+    PendingOp o4{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(Pr)};
     ops = {o1, o2, o3, o4};
+    FSpec a;  // z product with the stencil
+    a.mode = 3; a.nm = n3; a.na = n1 * n2; a.nb = 1; a.stencil = 1;
+    a.L1 = addpad(Pz, n3, fmod);
+    FSpec b;  // theta sandwich + rho product + update over (rho, theta) planes
+    b.mode = 2; b.nm = n2; b.na = n1; b.nb = n3;
+    b.sandwich = 1; b.phi = 1; b.plane = 1;
+    b.L1 = addpad(et.Vinv, n2, 1); b.L2 = addpad(et.V, n2, 1); b.Pf = addpad(Pr, n1, fmod);
+    b.pm = o2.pm; b.pn = o2.pn;
+    fspecs = {a, b};
   }
 
   const size_t o_coef = ar.add_d(coef), o_scale = ar.add_d(scale);
@@ -400,7 +469,105 @@ void build_plan(tg_plan_s* P) {
     const int nm = nn[o.mode - 1];
     if (o.mode == 1) c.tile = pick_tile(static_cast<int>(nb), nm, nslab);
     else c.tile = pick_tile(nm, static_cast<int>(na), nb * nslab);
+    c.flops = 2.0 * nm * static_cast<double>(P->state_elems);
     P->chain.push_back(c);
+  }
+  // Fused route: resolve the specs, choose tile widths, check LDS budgets.
+  {
+    auto mkF = [&](const PadF& f) {
+      tg::Factor F{};
+      F.L = f.off == SIZE_MAX ? nullptr : P->dmem + f.off;
+      F.ld = f.ld;
+      F.fstride = static_cast<int64_t>(f.ld) * f.ld;
+      F.fmod = f.fmod;
+      return F;
+    };
+    auto Dp = [&](size_t off) { return off == SIZE_MAX ? nullptr : D(off); };
+    auto first_op = [&](int nm, int rows, const PadF& L1, const PadF& L2, int sandwich, int in) {
+      tg::FusedOp op;
+      op.kind = 1;
+      op.mode = 1;
+      tg::FirstArgs& fa = op.fa;
+      fa.nm = nm;
+      fa.rows = rows;
+      fa.nslab = nslab;
+      fa.sandwich = sandwich;
+      fa.L1 = mkF(L1);
+      if (sandwich) fa.L2 = mkF(L2);
+      fa.update = 1;
+      fa.alpha = tau;
+      fa.flag = P->dflag;
+      const int64_t wg32 = static_cast<int64_t>((rows + 31) / 32) * nslab;
+      fa.tm = wg32 >= 512 ? 32 : 16;
+      op.in = in;
+      op.out = -1;
+      op.updates_state = true;
+      op.flops = (sandwich ? 2.0 : 1.0) * 2.0 * nm * static_cast<double>(P->state_elems);
+      return op;
+    };
+    std::vector<tg::FusedOp> out;
+    bool ok = true;
+    int buf = 0, prev = -1;
+    for (const auto& f : fspecs) {
+      if (f.kind == 1) {
+        auto op = first_op(f.nm, f.rows, f.L1, f.L2, f.sandwich, prev);
+        op.fa.ph = {P->d_cs, Dp(f.pm), Dp(f.pn), nullptr};
+        if (tg::first_lds_bytes<T>(f.nm, op.fa.tm, f.sandwich) > kLdsLimit) { ok = false; break; }
+        out.push_back(op);
+        prev = -1;
+        continue;
+      }
+      tg::FusedOp op;
+      op.kind = 0;
+      op.mode = f.mode;
+      tg::StridedArgs& sa = op.sa;
+      sa.nm = f.nm;
+      sa.na = f.na;
+      sa.nb = f.nb;
+      sa.nslab = nslab;
+      sa.sandwich = f.sandwich;
+      sa.phi = f.phi;
+      sa.stencil = f.stencil;
+      sa.L1 = mkF(f.L1);
+      if (f.sandwich) sa.L2 = mkF(f.L2);
+      sa.ph = {P->d_cs, Dp(f.pm), Dp(f.pn), Dp(f.pb)};
+      sa.alpha = tau;
+      sa.flag = P->dflag;
+      sa.update = 1;
+      bool plane = f.plane != 0;
+      if (plane) {
+        sa.tn = (f.na + 31) / 32 * 32;
+        if (tg::strided_lds_bytes<T>(f.nm, sa.tn, f.sandwich, 1) > kLdsLimit) plane = false;
+      }
+      if (!plane) {
+        const int64_t wg32 = static_cast<int64_t>((f.na + 31) / 32) * f.nb * nslab;
+        sa.tn = wg32 >= 512 ? 32 : 16;
+        if (tg::strided_lds_bytes<T>(f.nm, sa.tn, f.sandwich, 0) > kLdsLimit) { ok = false; break; }
+      }
+      sa.plane = plane ? 1 : 0;
+      if (plane) sa.P = mkF(f.Pf);
+      op.flops = ((f.sandwich ? 2.0 : 1.0) * 2.0 * f.nm + (plane ? 2.0 * f.na : 0.0)) *
+                 static_cast<double>(P->state_elems);
+      op.in = prev;
+      if (plane) {
+        op.out = -1;
+        op.updates_state = true;
+        prev = -1;
+      } else {
+        op.out = buf;
+        prev = buf;
+        buf ^= 1;
+      }
+      out.push_back(op);
+      if (f.plane && !plane) {  // split tail: mode-1 product + update
+        auto t = first_op(n1, static_cast<int>(P->npts / n1), f.Pf, f.Pf, 0, prev);
+        if (tg::first_lds_bytes<T>(n1, t.fa.tm, 0) > kLdsLimit) { ok = false; break; }
+        out.push_back(t);
+        prev = -1;
+      }
+    }
+    P->fused_ok = ok && !out.empty() && out.back().updates_state;
+    if (P->fused_ok) P->fused = out;
   }
   const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
   for (int i = 0; i < 2; ++i) hip_check(hipMalloc(&P->scratch[i], bytes), "hipMalloc(scratch)");
@@ -468,12 +635,83 @@ void launch_stencil_stage(const tg_plan_s* P, const void* W, void* F, int what, 
   a.scale = P->d_scale;
   a.nmax = P->nmax;
   a.periodic_mask = P->periodic_mask;
+  a.scale_mask = P->scale_mask;
   a.diff = P->d_diff;
   a.reaction = P->reaction;
   a.rparams = P->d_rparams;
   a.wref = P->d_wref;
   a.g0 = P->d_g0;
   hip_check(tg::launch_stencil<T>(a, st), "stencil launch");
+}
+
+tg::StencilArgs stencil_args(const tg_plan_s* P, const void* W, void* F, int what) {
+  tg::StencilArgs a{};
+  a.W = W;
+  a.F = F;
+  a.ndim = P->grid.ndim;
+  a.n[0] = P->grid.n[0];
+  a.n[1] = P->grid.n[1];
+  a.n[2] = P->grid.ndim == 3 ? P->grid.n[2] : 1;
+  a.nspecies = P->ns;
+  a.batch = P->batch;
+  a.what = what;
+  a.coef = P->d_coef;
+  a.scale = P->d_scale;
+  a.nmax = P->nmax;
+  a.periodic_mask = P->periodic_mask;
+  a.scale_mask = P->scale_mask;
+  a.diff = P->d_diff;
+  a.reaction = P->reaction;
+  a.rparams = P->d_rparams;
+  a.wref = P->d_wref;
+  a.g0 = P->d_g0;
+  return a;
+}
+
+// Launch one fused op.  src: input tile data (or, for the stencil op, the
+// state W it is computed from); dst: output buffer, or the state / target
+// of the final product; update: add tau * result to dst instead of storing.
+template <typename T>
+void launch_fused(const tg_plan_s* P, const tg::FusedOp& op, const void* src, void* dst, bool update,
+                  bool from_state, hipStream_t st) {
+  if (op.kind == 0) {
+    tg::StridedArgs a = op.sa;
+    if (!from_state) a.stencil = 0;
+    if (a.stencil) {
+      a.st = stencil_args(P, src, nullptr, TG_APPLY_F);
+      a.X = nullptr;
+    } else {
+      a.X = src;
+    }
+    if (a.plane) {
+      a.W = dst;
+      a.Y = nullptr;
+      a.update = update ? 1 : 0;
+    } else {
+      a.Y = dst;
+    }
+    hip_check(tg::launch_strided<T>(a, st), "fused strided launch");
+  } else {
+    tg::FirstArgs a = op.fa;
+    a.X = src;
+    a.Y = dst;
+    a.update = update ? 1 : 0;
+    hip_check(tg::launch_first<T>(a, st), "fused first-mode launch");
+  }
+}
+
+// Run the fused chain: the first op reads `src` (the state when it carries
+// the stencil), intermediate results go to scratch, the last op updates or
+// stores `dst`.
+template <typename T>
+void run_fused(const tg_plan_s* P, const void* src, void* dst, bool update, bool from_state, hipStream_t st) {
+  for (size_t i = 0; i < P->fused.size(); ++i) {
+    const auto& op = P->fused[i];
+    const void* in = op.in < 0 ? src : P->scratch[op.in];
+    const bool last = i + 1 == P->fused.size();
+    void* out = last ? dst : P->scratch[op.out];
+    launch_fused<T>(P, op, in, out, last ? update : false, from_state, st);
+  }
 }
 
 // Apply the split chain to `in`.  final_update: last op does state += tau*acc
@@ -495,8 +733,24 @@ void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update,
   }
 }
 
+// 0: fused with the stencil in the first tile load; 2: fused products after
+// a separate stencil launch; 1: one launch per mode product.
+int active_route(const tg_plan_s* P) { return P->fused_ok && P->route != 1 ? P->route : 1; }
+bool use_fused(const tg_plan_s* P) { return active_route(P) != 1; }
+
 template <typename T>
 void step_impl(tg_plan_s* P, void* state, hipStream_t st) {
+  const int r = active_route(P);
+  if (r == 0) {
+    // the first fused op computes F from the state inside its tile load
+    run_fused<T>(P, state, state, true, true, st);
+    return;
+  }
+  if (r == 2) {
+    launch_stencil_stage<T>(P, state, P->scratch[1], TG_APPLY_F, st);
+    run_fused<T>(P, P->scratch[1], state, true, false, st);
+    return;
+  }
   launch_stencil_stage<T>(P, state, P->scratch[0], TG_APPLY_F, st);
   run_chain<T>(P, P->scratch[0], state, true, st);
 }
@@ -623,9 +877,15 @@ int tg_plan_reference(tg_plan p, double* w_ref) {
   });
 }
 
+// Device buffers are read and written as 4-element vectors.
+static bool aligned(const tg_plan_s* p, const void* ptr) {
+  return reinterpret_cast<uintptr_t>(ptr) % (4u * static_cast<unsigned>(p->esize)) == 0;
+}
+
 int tg_step(tg_plan p, void* state, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && state, TG_EINVAL, "tg_step: null pointer");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_step: state must be aligned to 4 elements");
     step_any(p, state, static_cast<hipStream_t>(stream));
     return TG_OK;
   });
@@ -634,6 +894,7 @@ int tg_step(tg_plan p, void* state, void* stream) {
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && state && n_steps >= 0, TG_EINVAL, "tg_run: bad argument");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run: state must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t chunk = kStepsPerGraph;
     const int64_t full = n_steps / chunk;
@@ -656,8 +917,16 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
 int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_chain_op: bad pointers");
-    TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(p->chain.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
+    TG_REQUIRE(aligned(p, in) && aligned(p, out), TG_EINVAL, "tg_apply_chain_op: buffers must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (use_fused(p)) {
+      TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(p->fused.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
+      const bool from_state = active_route(p) == 0;
+      if (p->precision == TG_FP64) launch_fused<double>(p, p->fused[op], in, out, false, from_state, st);
+      else launch_fused<float>(p, p->fused[op], in, out, false, from_state, st);
+      return TG_OK;
+    }
+    TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(p->chain.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
     const auto& c = p->chain[op];
     const int epi = c.epi == tg::EPI_UPDATE ? tg::EPI_STORE : c.epi;
     if (p->precision == TG_FP64) launch_op<double>(p, c, in, out, epi, st);
@@ -666,12 +935,42 @@ int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* st
   });
 }
 
-int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes) {
+int tg_plan_set_route(tg_plan p, int32_t route) {
+  return guarded([&] {
+    TG_REQUIRE(p && route >= 0 && route <= 2, TG_EINVAL, "tg_plan_set_route: bad argument");
+    if (route != p->route) {
+      for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+      p->graphs.clear();
+      p->route = route;
+    }
+    return TG_OK;
+  });
+}
+
+int tg_plan_route(tg_plan p, int32_t* route) {
+  return guarded([&] {
+    TG_REQUIRE(p && route, TG_EINVAL, "tg_plan_route: null pointer");
+    *route = active_route(p);
+    return TG_OK;
+  });
+}
+
+int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops) {
   return guarded([&] {
     TG_REQUIRE(p && n_ops, TG_EINVAL, "tg_plan_chain: null pointer");
-    *n_ops = static_cast<int32_t>(p->chain.size());
-    if (modes)
-      for (size_t i = 0; i < p->chain.size(); ++i) modes[i] = p->chain[i].mode;
+    if (use_fused(p)) {
+      *n_ops = static_cast<int32_t>(p->fused.size());
+      for (size_t i = 0; i < p->fused.size(); ++i) {
+        if (modes) modes[i] = p->fused[i].mode;
+        if (flops) flops[i] = p->fused[i].flops;
+      }
+    } else {
+      *n_ops = static_cast<int32_t>(p->chain.size());
+      for (size_t i = 0; i < p->chain.size(); ++i) {
+        if (modes) modes[i] = p->chain[i].mode;
+        if (flops) flops[i] = p->chain[i].flops;
+      }
+    }
     return TG_OK;
   });
 }
@@ -690,9 +989,15 @@ int tg_apply_operator(tg_plan p, const void* in, void* out, int32_t what, void* 
 int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_split_phi1: bad pointers");
+    TG_REQUIRE(aligned(p, in) && aligned(p, out), TG_EINVAL, "tg_apply_split_phi1: buffers must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (p->precision == TG_FP64) run_chain<double>(p, in, out, false, st);
-    else run_chain<float>(p, in, out, false, st);
+    if (use_fused(p)) {
+      if (p->precision == TG_FP64) run_fused<double>(p, in, out, false, false, st);
+      else run_fused<float>(p, in, out, false, false, st);
+    } else {
+      if (p->precision == TG_FP64) run_chain<double>(p, in, out, false, st);
+      else run_chain<float>(p, in, out, false, st);
+    }
     return TG_OK;
   });
 }

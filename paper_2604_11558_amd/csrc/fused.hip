@@ -1,0 +1,699 @@
+// Fused mu-mode product kernels (see fused.hpp).
+//
+// Both kernels run 256 threads = 4 waves.  The workgroup's data tile holds
+// the whole contracted index in LDS; each wave computes 16FM x 16FN output
+// sub-tiles with 16x16x4 MFMAs.  Factor operands are read from global
+// memory (L2 resident: a few hundred KB at most) four consecutive k at a
+// time; to make that a single vector load the k index of MFMA step t in
+// lane group g is k0 + 4 g + t instead of k0 + 4 t + g (any assignment of
+// k to (step, group) is valid as long as both operands use the same one).
+#include <cstdio>
+
+#include "fused.hpp"
+#include "stencil_dev.hpp"
+
+namespace tg {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct M16;
+template <> struct M16<double> {
+  using acc = f64x4;
+  using v4 = f64x4;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane group g is row g + 4 r (FP64 layout)
+  static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+  static __device__ __forceinline__ double phi1(double x) { return x == 0.0 ? 1.0 : expm1(x) / x; }
+};
+template <> struct M16<float> {
+  using acc = f32x4;
+  using v4 = f32x4;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of lane group g is row 4 g + r (FP32 layout)
+  static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+  static __device__ __forceinline__ float phi1(float x) { return x == 0.0f ? 1.0f : expm1f(x) / x; }
+};
+
+static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// LDS row pitch (elements).  With w a multiple of 16, w + 4 puts the rows
+// read by lane groups 0 and 1 of a 16-wide access in different halves of
+// the 32 banks (FP32), and gives the 16-byte (FP32) / 32-byte (FP64) row
+// vectors read by 8 / 4 consecutive lanes distinct banks.
+template <typename T>
+__host__ __device__ inline int pitch_kmajor(int w) { return w + 4; }
+template <typename T>
+__host__ __device__ inline int pitch_rowvec(int w) { return w + 4; }
+
+// acc[f][j] += sum_{k < K} A[r0 + 16 f + li][k] * sB[k][c0 + 16 j + li]
+// A: zero-padded factor rows in global memory; sB: k-major LDS tile.
+template <typename T, int FM, int FN>
+__device__ __forceinline__ void gemm_gA_sB(typename M16<T>::acc (&acc)[FM][FN], const T* __restrict__ A,
+                                           int lda, int r0, const T* sB, int ldb, int c0, int K, int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+  const T* arow[FM];
+#pragma unroll
+  for (int f = 0; f < FM; ++f) arow[f] = A + static_cast<int64_t>(r0 + 16 * f + li) * lda + 4 * g;
+  // factor vectors are fetched two k-chunks ahead of their use
+  v4 cur[FM], nx1[FM];
+#pragma unroll
+  for (int f = 0; f < FM; ++f) {
+    cur[f] = *reinterpret_cast<const v4*>(arow[f]);
+    if (K > 16) nx1[f] = *reinterpret_cast<const v4*>(arow[f] + 16);
+  }
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    v4 nx2[FM];
+    const bool more = k0 + 32 < K;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+      if (more) nx2[f] = *reinterpret_cast<const v4*>(arow[f] + k0 + 32);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T* brow = sB + (k0 + 4 * g + t) * ldb + c0 + li;
+      T b[FN];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = brow[16 * j];
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[f][j] = M16<T>::mac(cur[f][t], b[j], acc[f][j]);
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+      cur[f] = nx1[f];
+      if (more) nx1[f] = nx2[f];
+    }
+  }
+}
+
+// acc[f][j] += sum_{k < K} sA[r0 + 16 f + li][k] * B[c0 + 16 j + li][k]
+// sA: row-major LDS tile; B: zero-padded factor rows (= output columns).
+template <typename T, int FM, int FN>
+__device__ __forceinline__ void gemm_sA_gB(typename M16<T>::acc (&acc)[FM][FN], const T* sA, int lda,
+                                           int r0, const T* __restrict__ B, int ldb, int c0, int K,
+                                           int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+  const T* brow[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) brow[j] = B + static_cast<int64_t>(c0 + 16 * j + li) * ldb + 4 * g;
+  v4 cur[FN], nx1[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    cur[j] = *reinterpret_cast<const v4*>(brow[j]);
+    if (K > 16) nx1[j] = *reinterpret_cast<const v4*>(brow[j] + 16);
+  }
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    v4 nx2[FN];
+    const bool more = k0 + 32 < K;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      if (more) nx2[j] = *reinterpret_cast<const v4*>(brow[j] + k0 + 32);
+    v4 a[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+      a[f] = *reinterpret_cast<const v4*>(sA + (r0 + 16 * f + li) * lda + k0 + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[f][j] = M16<T>::mac(a[f][t], cur[j][t], acc[f][j]);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      cur[j] = nx1[j];
+      if (more) nx1[j] = nx2[j];
+    }
+  }
+}
+
+// Fully unrolled variants for K = 16 KCH: every factor vector of the wave's
+// rows is requested before the first MFMA, so the loads overlap each other
+// and a single wait covers them (the runtime-K loops above are used for
+// larger contractions).
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void gemm_gA_sB_u(typename M16<T>::acc (&acc)[FM][FN], const T* __restrict__ A,
+                                             int lda, int r0, const T* sB, int ldb, int c0, int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+  v4 av[FM][KCH];
+#pragma unroll
+  for (int f = 0; f < FM; ++f) {
+    const T* arow = A + static_cast<int64_t>(r0 + 16 * f + li) * lda + 4 * g;
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) av[f][c] = *reinterpret_cast<const v4*>(arow + 16 * c);
+  }
+#pragma unroll
+  for (int c = 0; c < KCH; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T* brow = sB + (16 * c + 4 * g + t) * ldb + c0 + li;
+      T b[FN];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = brow[16 * j];
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[f][j] = M16<T>::mac(av[f][c][t], b[j], acc[f][j]);
+    }
+}
+
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void gemm_sA_gB_u(typename M16<T>::acc (&acc)[FM][FN], const T* sA, int lda,
+                                             int r0, const T* __restrict__ B, int ldb, int c0, int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+  v4 bv[FN][KCH];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const T* brow = B + static_cast<int64_t>(c0 + 16 * j + li) * ldb + 4 * g;
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) bv[j][c] = *reinterpret_cast<const v4*>(brow + 16 * c);
+  }
+#pragma unroll
+  for (int c = 0; c < KCH; ++c) {
+    v4 a[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+      a[f] = *reinterpret_cast<const v4*>(sA + (r0 + 16 * f + li) * lda + 16 * c + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[f][j] = M16<T>::mac(a[f][t], bv[j][c][t], acc[f][j]);
+  }
+}
+
+// Dispatch on the compile-time chunk count (KCH == 0: runtime K).
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void mm_gA_sB(typename M16<T>::acc (&acc)[FM][FN], const T* A, int lda, int r0,
+                                         const T* sB, int ldb, int c0, int K, int lane) {
+  if constexpr (KCH > 0) gemm_gA_sB_u<T, FM, FN, KCH>(acc, A, lda, r0, sB, ldb, c0, lane);
+  else gemm_gA_sB<T, FM, FN>(acc, A, lda, r0, sB, ldb, c0, K, lane);
+}
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void mm_sA_gB(typename M16<T>::acc (&acc)[FM][FN], const T* sA, int lda, int r0,
+                                         const T* B, int ldb, int c0, int K, int lane) {
+  if constexpr (KCH > 0) {
+    if (K == 16 * KCH) {
+      gemm_sA_gB_u<T, FM, FN, KCH>(acc, sA, lda, r0, B, ldb, c0, lane);
+      return;
+    }
+  }
+  gemm_sA_gB<T, FM, FN>(acc, sA, lda, r0, B, ldb, c0, K, lane);
+}
+
+template <typename T, int FM, int FN>
+__device__ __forceinline__ void zero(typename M16<T>::acc (&acc)[FM][FN]) {
+#pragma unroll
+  for (int f = 0; f < FM; ++f)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[f][j] = typename M16<T>::acc{0, 0, 0, 0};
+}
+
+__device__ __forceinline__ double phi_arg(const PhiArgs& p, int s, int row, int col, int b) {
+  double x = p.cs[s];
+  if (p.pm) x *= p.pm[row];
+  if (p.pn) x *= p.pn[col];
+  if (p.pb) x *= p.pb[b];
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* factor_of(const Factor& F, int s) {
+  return static_cast<const T*>(F.L) + static_cast<int64_t>(s % F.fmod) * F.fstride;
+}
+
+// Tile loads.  Rows of the source are contiguous; when the row length is a
+// multiple of 4 every thread moves 4-element vectors, eight of them in
+// flight before the LDS stores.
+constexpr int kBatch = 8;
+
+// sX[k][c] = X[k * na + a0 + c] for k < nm, a0 + c < na, else 0 (k < NP, c < TN)
+template <typename T>
+__device__ __forceinline__ void load_tile_kmajor(const T* __restrict__ X, int na, int nm, int a0, int NP,
+                                                 int TN, T* sX, int ld, int tid) {
+  using v4 = typename M16<T>::v4;
+  if (na % 4 == 0) {
+    const int nvec = NP * TN / 4;
+    for (int v0 = 0; v0 < nvec; v0 += 256 * kBatch) {
+      v4 r[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int v = v0 + tid + 256 * q;
+        const int k = (4 * v) / TN, c = (4 * v) % TN;
+        r[q] = v4{0, 0, 0, 0};
+        if (v < nvec && k < nm && a0 + c < na)
+          r[q] = *reinterpret_cast<const v4*>(X + static_cast<int64_t>(k) * na + a0 + c);
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int v = v0 + tid + 256 * q;
+        if (v < nvec) {
+          const int k = (4 * v) / TN, c = (4 * v) % TN;
+          *reinterpret_cast<v4*>(sX + k * ld + c) = r[q];
+        }
+      }
+    }
+    return;
+  }
+  for (int e = tid; e < NP * TN; e += 256) {
+    const int k = e / TN, c = e % TN;
+    sX[k * ld + c] = (k < nm && a0 + c < na) ? X[static_cast<int64_t>(k) * na + a0 + c] : T(0);
+  }
+}
+
+// sX[r][c] = X[(rt0 + r) * nm + c] for rt0 + r < rows, c < nm, else 0 (r < TM, c < NP)
+template <typename T>
+__device__ __forceinline__ void load_tile_rows(const T* __restrict__ X, int nm, int rows, int rt0, int TM,
+                                               int NP, T* sX, int ld, int tid) {
+  using v4 = typename M16<T>::v4;
+  if (nm % 4 == 0) {
+    const int nvec = TM * NP / 4;
+    for (int v0 = 0; v0 < nvec; v0 += 256 * kBatch) {
+      v4 r[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int v = v0 + tid + 256 * q;
+        const int rr = (4 * v) / NP, c = (4 * v) % NP;
+        r[q] = v4{0, 0, 0, 0};
+        if (v < nvec && c < nm && rt0 + rr < rows)
+          r[q] = *reinterpret_cast<const v4*>(X + static_cast<int64_t>(rt0 + rr) * nm + c);
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int v = v0 + tid + 256 * q;
+        if (v < nvec) {
+          const int rr = (4 * v) / NP, c = (4 * v) % NP;
+          *reinterpret_cast<v4*>(sX + rr * ld + c) = r[q];
+        }
+      }
+    }
+    return;
+  }
+  for (int e = tid; e < TM * NP; e += 256) {
+    const int r = e / NP, c = e % NP;
+    sX[r * ld + c] = (c < nm && rt0 + r < rows) ? X[static_cast<int64_t>(rt0 + r) * nm + c] : T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue helpers.  Every lane owns FM x FN x 4 accumulator elements: rows
+// r0 + 16 f + row(g, r), columns c0 + 16 j + li.  Loads that feed an
+// epilogue (phi_1 argument factors, the state of an update) are issued with
+// clamped indices before the product, so they overlap it and each other;
+// only the final store is predicated.
+template <typename T, int FM>
+__device__ __forceinline__ void row_factors(double (&fr)[FM][4], const double* pm, int r0, int g, int lim,
+                                            int off) {
+#pragma unroll
+  for (int f = 0; f < FM; ++f)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * f + M16<T>::row(g, r);
+      fr[f][r] = pm ? pm[off + min(row, lim - 1)] : 1.0;
+    }
+}
+
+template <int FN>
+__device__ __forceinline__ void col_factors(double (&fc)[FN], const double* pn, int c0, int li, int lim, int off) {
+#pragma unroll
+  for (int j = 0; j < FN; ++j) fc[j] = pn ? pn[off + min(c0 + 16 * j + li, lim - 1)] : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int FM, int FN, int KCH>
+__global__ __launch_bounds__(256) void strided_kernel(StridedArgs a) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  using acc_t = typename M16<T>::acc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, na = a.na, TN = a.tn;
+  const int NP = KCH > 0 ? 16 * KCH : (nm + 16 * FM - 1) / (16 * FM) * (16 * FM);
+  const int ld = pitch_kmajor<T>(TN);
+  T* sX = reinterpret_cast<T*>(smem);
+  T* sT = sX + NP * ld;
+  const int a0 = blockIdx.x * TN, b = blockIdx.y, s = blockIdx.z;
+  const int64_t slab = static_cast<int64_t>(nm) * na * a.nb;
+  const int64_t base = static_cast<int64_t>(s) * slab + static_cast<int64_t>(b) * nm * na;
+
+  // 1. data tile: rows k < NP (zero beyond nm), columns a0 .. a0 + TN
+  if (a.stencil) {
+    // The stencil launch is always the last mode (nb == 1): the column a
+    // holds the faster coordinates, the row k the slowest one.
+    const int inst = s / a.st.nspecies, sp = s % a.st.nspecies;
+    const int n1 = a.st.n[0];
+    const bool three = a.st.ndim == 3;
+#pragma unroll 4
+    for (int e = tid; e < NP * TN; e += 256) {
+      const int k = e / TN, c = e % TN;
+      const int aa = a0 + c;
+      double v = 0.0;
+      if (k < nm && aa < na) {
+        const int i = three ? aa % n1 : aa;
+        const int j = three ? aa / n1 : k;
+        const int kk = three ? k : 0;
+        v = stencil_point_ijk<T>(a.st, inst, sp, k * na + aa, i, j, kk);
+      }
+      sX[k * ld + c] = static_cast<T>(v);
+    }
+  } else {
+    load_tile_kmajor<T>(static_cast<const T*>(a.X) + base, na, nm, a0, NP, TN, sX, ld, tid);
+  }
+  __syncthreads();
+
+  const int nrt = NP / (16 * FM), nct = TN / (16 * FN);
+  const int nsub = nrt * nct;
+  const bool keep = a.sandwich || a.plane;  // result of the first product stays in LDS
+  const T* L1 = factor_of<T>(a.L1, s);
+  T* Y = static_cast<T*>(a.Y) + base;
+  const double cb = a.phi ? a.ph.cs[s] * (a.ph.pb ? a.ph.pb[b] : 1.0) : 0.0;
+
+  // 2. first product (and the phi_1 factor)
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    // phi_1 factors of this lane's elements, evaluated before the product
+    // (they do not depend on it, so they overlap the MFMA latency)
+    T ph[FM][FN][4];
+    if (a.phi) {
+      double fr[FM][4], fc[FN];
+      row_factors<T, FM>(fr, a.ph.pm, r0, g, nm, 0);
+      col_factors<FN>(fc, a.ph.pn, c0, li, na - a0, a0);
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ph[f][j][r] = M16<T>::phi1(static_cast<T>(cb * fr[f][r] * fc[j]));
+    }
+    acc_t acc[FM][FN];
+    zero<T, FM, FN>(acc);
+    mm_gA_sB<T, FM, FN, KCH>(acc, L1, a.L1.ld, r0, sX, ld, c0, NP, lane);
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
+          T v = acc[f][j][r];
+          const bool in = row < nm && a0 + col < na;
+          if (a.phi) v *= ph[f][j][r];
+          if (keep) sT[row * ld + col] = in ? v : T(0);
+          else if (in) Y[static_cast<int64_t>(row) * na + a0 + col] = v;
+        }
+  }
+  if (!keep) return;
+  __syncthreads();
+
+  // 3. second product of the sandwich (into LDS for the plane tail)
+  if (a.sandwich) {
+    const T* L2 = factor_of<T>(a.L2, s);
+    for (int sub = wave; sub < nsub; sub += 4) {
+      const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+      acc_t acc[FM][FN];
+      zero<T, FM, FN>(acc);
+      mm_gA_sB<T, FM, FN, KCH>(acc, L2, a.L2.ld, r0, sT, ld, c0, NP, lane);
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
+            const T v = acc[f][j][r];
+            const bool in = row < nm && a0 + col < na;
+            if (a.plane) sX[row * ld + col] = in ? v : T(0);
+            else if (in) Y[static_cast<int64_t>(row) * na + a0 + col] = v;
+          }
+    }
+    if (!a.plane) return;
+    __syncthreads();
+  }
+
+  // 4. plane tail: Z[row][i'] = sum_i T[row][i] P[i'][i];  W += alpha Z
+  const T* Tin = a.sandwich ? sX : sT;
+  const T* P = factor_of<T>(a.P, s);
+  T* W = static_cast<T*>(a.W) + base;
+  const int KP = (na + 15) / 16 * 16;
+  const T alpha = static_cast<T>(a.alpha);
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    T wv[FM][FN][4];
+    if (a.update) {  // state values of this lane, requested before the product
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = min(r0 + 16 * f + M16<T>::row(g, r), nm - 1);
+            const int col = min(c0 + 16 * j + li, na - 1);
+            wv[f][j][r] = W[static_cast<int64_t>(row) * na + col];
+          }
+    }
+    acc_t acc[FM][FN];
+    zero<T, FM, FN>(acc);
+    mm_sA_gB<T, FM, FN, KCH>(acc, Tin, ld, r0, P, a.P.ld, c0, KP, lane);
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
+          const T nv = a.update ? wv[f][j][r] + alpha * acc[f][j][r] : acc[f][j][r];
+          if (row < nm && col < na) {
+            W[static_cast<int64_t>(row) * na + col] = nv;
+            bad |= !isfinite(nv);
+          }
+        }
+    if (bad && a.flag) atomicOr(a.flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int FM, int FN, int KCH>
+__global__ __launch_bounds__(256) void first_kernel(FirstArgs a) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  using acc_t = typename M16<T>::acc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, TM = a.tm;
+  const int NP = KCH > 0 ? 16 * KCH : (nm + 16 * FN - 1) / (16 * FN) * (16 * FN);
+  const int ld = pitch_rowvec<T>(NP);
+  T* sX = reinterpret_cast<T*>(smem);
+  T* sT = sX + TM * ld;
+  const int rt0 = blockIdx.x * TM, s = blockIdx.y;
+  const int64_t base = static_cast<int64_t>(s) * a.rows * nm;
+
+  load_tile_rows<T>(static_cast<const T*>(a.X) + base, nm, a.rows, rt0, TM, NP, sX, ld, tid);
+  __syncthreads();
+
+  const int nrt = TM / (16 * FM), nct = NP / (16 * FN);
+  const int nsub = nrt * nct;
+  T* Y = static_cast<T*>(a.Y) + base;
+  const T alpha = static_cast<T>(a.alpha);
+  // final epilogue of a sub-tile: store, or add alpha * result to the target
+  auto finish = [&](int r0, int c0, const acc_t (&acc)[FM][FN], const T (&yv)[FM][FN][4]) {
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rg = rt0 + r0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
+          const T nv = a.update ? yv[f][j][r] + alpha * acc[f][j][r] : acc[f][j][r];
+          if (rg < a.rows && col < nm) {
+            Y[static_cast<int64_t>(rg) * nm + col] = nv;
+            bad |= !isfinite(nv);
+          }
+        }
+    if (bad && a.update && a.flag) atomicOr(a.flag, 1);
+  };
+  auto prefetch = [&](int r0, int c0, T (&yv)[FM][FN][4]) {
+    if (!a.update) return;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rg = min(rt0 + r0 + 16 * f + M16<T>::row(g, r), a.rows - 1);
+          const int col = min(c0 + 16 * j + li, nm - 1);
+          yv[f][j][r] = Y[static_cast<int64_t>(rg) * nm + col];
+        }
+  };
+  const T* L1 = factor_of<T>(a.L1, s);
+  const double cs = a.sandwich ? a.ph.cs[s] : 0.0;
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    T yv[FM][FN][4];
+    T ph[FM][FN][4];
+    if (a.sandwich) {
+      double fr[FM][4], fc[FN];
+      row_factors<T, FM>(fr, a.ph.pm, r0, g, a.rows - rt0, rt0);
+      col_factors<FN>(fc, a.ph.pn, c0, li, nm, 0);
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ph[f][j][r] = M16<T>::phi1(static_cast<T>(cs * fr[f][r] * fc[j]));
+    } else {
+      prefetch(r0, c0, yv);
+    }
+    acc_t acc[FM][FN];
+    zero<T, FM, FN>(acc);
+    mm_sA_gB<T, FM, FN, KCH>(acc, sX, ld, r0, L1, a.L1.ld, c0, NP, lane);
+    if (!a.sandwich) {
+      finish(r0, c0, acc, yv);
+      continue;
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
+          const bool in = col < nm && rt0 + row < a.rows;
+          const T v = acc[f][j][r] * ph[f][j][r];
+          sT[row * ld + col] = in ? v : T(0);
+        }
+  }
+  if (!a.sandwich) return;
+  __syncthreads();
+  const T* L2 = factor_of<T>(a.L2, s);
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    T yv[FM][FN][4];
+    prefetch(r0, c0, yv);
+    acc_t acc[FM][FN];
+    zero<T, FM, FN>(acc);
+    mm_sA_gB<T, FM, FN, KCH>(acc, sT, ld, r0, L2, a.L2.ld, c0, NP, lane);
+    finish(r0, c0, acc, yv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.  FM / FN are picked from the shape: FM covers the rows of
+// a wave sub-tile (16 FM), FN its columns (16 FN).
+
+// Contractions up to 128 run fully unrolled with the padded extent
+// NP = 16 KCH (KCH = 4 or 8) and FM = 2; longer ones use the runtime loop
+// with FM = 4 and NP = nm rounded up to 64.
+static int pick_kch(int nm) { return nm <= 64 ? 4 : (nm <= 128 ? 8 : 0); }
+static int strided_np(int nm) {
+  const int kch = pick_kch(nm);
+  return kch ? 16 * kch : round_up(nm, 64);
+}
+static int first_np(int nm) {
+  const int kch = pick_kch(nm);
+  return kch ? 16 * kch : round_up(nm, 32);
+}
+
+template <typename T>
+size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane) {
+  const int NP = strided_np(nm);
+  const int ld = pitch_kmajor<T>(tn);
+  const int bufs = (sandwich || plane) ? 2 : 1;
+  return static_cast<size_t>(bufs) * NP * ld * sizeof(T);
+}
+
+template <typename T>
+size_t first_lds_bytes(int nm, int tm, int sandwich) {
+  const int NP = first_np(nm);
+  const int ld = pitch_rowvec<T>(NP);
+  return static_cast<size_t>(sandwich ? 2 : 1) * tm * ld * sizeof(T);
+}
+
+static constexpr size_t kMaxLds = 160 * 1024;
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+template <typename T, int FM, int FN, int KCH>
+static hipError_t go_strided(const StridedArgs& a, size_t lds, hipStream_t s) {
+  auto k = strided_kernel<T, FM, FN, KCH>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((a.na + a.tn - 1) / a.tn, a.nb, a.nslab);
+  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_strided(const StridedArgs& a, hipStream_t s) {
+  if (a.nm <= 0 || a.na <= 0 || a.nb <= 0 || a.nslab <= 0 || a.nb > 65535 || a.nslab > 65535)
+    return hipErrorInvalidValue;
+  if (a.tn != 16 && a.tn % 32 != 0) return hipErrorInvalidValue;
+  if (a.plane && a.tn < a.na) return hipErrorInvalidValue;  // plane needs whole rows
+  const int NP = strided_np(a.nm);
+  if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP) || (a.plane && a.P.ld < round_up(a.na, 32)))
+    return hipErrorInvalidValue;
+  const size_t lds = strided_lds_bytes<T>(a.nm, a.tn, a.sandwich, a.plane);
+  if (lds > kMaxLds) return hipErrorInvalidValue;
+  const bool fn2 = a.tn % 32 == 0;
+  switch (pick_kch(a.nm) * 10 + (fn2 ? 2 : 1)) {
+    case 41: return go_strided<T, 2, 1, 4>(a, lds, s);
+    case 42: return go_strided<T, 2, 2, 4>(a, lds, s);
+    case 81: return go_strided<T, 2, 1, 8>(a, lds, s);
+    case 82: return go_strided<T, 2, 2, 8>(a, lds, s);
+    case 1: return go_strided<T, 4, 1, 0>(a, lds, s);
+    default: return go_strided<T, 4, 2, 0>(a, lds, s);
+  }
+}
+
+template <typename T, int FM, int FN, int KCH>
+static hipError_t go_first(const FirstArgs& a, size_t lds, hipStream_t s) {
+  auto k = first_kernel<T, FM, FN, KCH>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((a.rows + a.tm - 1) / a.tm, a.nslab);
+  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_first(const FirstArgs& a, hipStream_t s) {
+  if (a.nm <= 0 || a.rows <= 0 || a.nslab <= 0 || a.nslab > 65535) return hipErrorInvalidValue;
+  if (a.tm != 16 && a.tm != 32) return hipErrorInvalidValue;
+  const int NP = first_np(a.nm);
+  if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP)) return hipErrorInvalidValue;
+  const size_t lds = first_lds_bytes<T>(a.nm, a.tm, a.sandwich);
+  if (lds > kMaxLds) return hipErrorInvalidValue;
+  const int kch = pick_kch(a.nm);
+  if (a.tm == 16) {
+    if (kch == 4) return go_first<T, 1, 2, 4>(a, lds, s);
+    if (kch == 8) return go_first<T, 1, 2, 8>(a, lds, s);
+    return go_first<T, 1, 2, 0>(a, lds, s);
+  }
+  if (kch == 4) return go_first<T, 2, 2, 4>(a, lds, s);
+  if (kch == 8) return go_first<T, 2, 2, 8>(a, lds, s);
+  return go_first<T, 2, 2, 0>(a, lds, s);
+}
+
+template hipError_t launch_strided<double>(const StridedArgs&, hipStream_t);
+template hipError_t launch_strided<float>(const StridedArgs&, hipStream_t);
+template hipError_t launch_first<double>(const FirstArgs&, hipStream_t);
+template hipError_t launch_first<float>(const FirstArgs&, hipStream_t);
+template size_t strided_lds_bytes<double>(int, int, int, int);
+template size_t strided_lds_bytes<float>(int, int, int, int);
+template size_t first_lds_bytes<double>(int, int, int);
+template size_t first_lds_bytes<float>(int, int, int);
+
+}  // namespace tg

@@ -1,0 +1,84 @@
+// Fused mu-mode product kernels: the data tile of a workgroup (all of the
+// contracted index for a block of the other indices) sits in LDS for the
+// whole contraction; factors stream from L2 as 4-wide vectors along k.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace tg {
+
+// Phi argument of an eigen-basis Hadamard factor:
+// x = cs[slab] * pm[row] * pn[col] * pb[b]   (null arrays mean 1).
+struct PhiArgs {
+  const double* cs;
+  const double* pm;
+  const double* pn;
+  const double* pb;
+};
+
+// A padded factor stack: block f of fmod blocks is at L + f * fstride, row-
+// major with leading dimension ld; rows and columns beyond n are zero.
+struct Factor {
+  const void* L;
+  int ld;
+  int64_t fstride;
+  int fmod;
+};
+
+// Strided mode (mu >= 2) product over the view [nb][nm][na] of every slab:
+//   Y_b = L2 (Phi o (L1 X_b))   (sandwich)    or    Y_b = Phi? o (L1 X_b)
+// A workgroup owns `tn` consecutive columns a of one (b, slab) and all nm
+// rows.  With `stencil` set, X is not read: the tile is computed from the
+// state as F = d M W + g(W) (the first product of a step).
+// With `plane` set (na == tile width), the result is multiplied along mode 1
+// by the factor `P` and added to the state: W += alpha * (Y x_1 P).
+struct StridedArgs {
+  const void* X;
+  void* Y;
+  int nm, na, nb, nslab;
+  int tn;          // columns per workgroup (multiple of 16)
+  int sandwich;
+  int phi;         // apply the Phi factor after the first product
+  Factor L1, L2;
+  PhiArgs ph;
+  int stencil;
+  StencilArgs st;  // valid when stencil != 0 (W = state)
+  int plane;
+  Factor P;        // mode-1 factor for the plane tail
+  void* W;         // state updated by the plane tail
+  int update;      // plane tail: 1 = W += alpha * Z, 0 = W = Z
+  double alpha;
+  int* flag;
+};
+
+// First mode product over rows r (all slower points) of every slab:
+//   Y = (Phi o (X L1^T)) L2^T  (sandwich)   or   Y = X L1^T
+// epilogue: store into Y, or W += alpha * result (update).
+struct FirstArgs {
+  const void* X;
+  void* Y;
+  int nm, rows, nslab;
+  int tm;          // rows per workgroup (multiple of 16)
+  int sandwich;
+  Factor L1, L2;
+  PhiArgs ph;      // x = cs[s] pm[row] pn[col]
+  int update;
+  double alpha;
+  int* flag;
+};
+
+template <typename T>
+hipError_t launch_strided(const StridedArgs& a, hipStream_t s);
+template <typename T>
+hipError_t launch_first(const FirstArgs& a, hipStream_t s);
+// LDS bytes a launch would need (0 if the shape is not supported).
+template <typename T>
+size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane);
+template <typename T>
+size_t first_lds_bytes(int nm, int tm, int sandwich);
+
+}  // namespace tg

@@ -1,6 +1,7 @@
 // Device kernels: MFMA mu-mode products with fused epilogues, and the
 // stencil + reaction stage of the split exponential Euler step.
 #include "kernels.hpp"
+#include "stencil_dev.hpp"
 
 #include <cstdio>
 
@@ -174,85 +175,77 @@ template hipError_t launch_mode_gemm<float>(const GemmArgs&, hipStream_t);
 // ---------------------------------------------------------------------------
 // Stencil + reaction: one thread per grid point of one instance; all species
 // of the point are handled together because the reaction couples them.
-// The state holds deviations p = w - w_ref from a reference state; the
-// polynomial reactions are expanded around w_ref so that no O(1) terms cancel.
 template <typename T>
 __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
-  const int64_t npts = static_cast<int64_t>(n1) * n2 * n3;
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int npts = n1 * n2 * n3;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int inst = blockIdx.y;
   if (p >= npts) return;
-  const int i = static_cast<int>(p % n1);
-  const int j = static_cast<int>((p / n1) % n2);
-  const int k = static_cast<int>(p / (static_cast<int64_t>(n1) * n2));
-  const int idx[3] = {i, j, k};
-  const int64_t stride[3] = {1, n1, static_cast<int64_t>(n1) * n2};
+  const int i = p % n1;
+  const int j = (p / n1) % n2;
+  const int k = p / (n1 * n2);
   const int ns = a.nspecies;
-  const T* W = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * ns * npts;
+  const T* Wi = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * ns * npts;
   T* F = static_cast<T*>(a.F) + static_cast<int64_t>(inst) * ns * npts;
-
-  double w[3] = {0, 0, 0};
-  for (int sp = 0; sp < ns && sp < 3; ++sp) w[sp] = static_cast<double>(W[sp * npts + p]);
-
   double G[3] = {0, 0, 0};
   if (a.what != 1 && a.reaction != 0) {
-    const double* rp = a.rparams + inst * 4;
-    const double* wr = a.wref + inst * ns;
-    const double* g0 = a.g0 + inst * ns;
-    const double ur = wr[0], vr = wr[1];
-    const double dp = w[0], dq = w[1];
-    // u^2 v - ur^2 vr expanded in the deviations (dp, dq)
-    const double N = ur * ur * dq + 2.0 * ur * vr * dp + 2.0 * ur * dp * dq + vr * dp * dp +
-                     dp * dp * dq;
-    if (a.reaction == 1) {  // Schnakenberg: a - u + u^2 v,  b - u^2 v
-      G[0] = g0[0] - dp + N;
-      G[1] = g0[1] - N;
-    } else {  // a - u + u^2 v - kappa u w,  b - u^2 v,  mu (u - w)
-      const double kap = rp[2], mu = rp[3];
-      const double wrr = wr[2], dr = w[2];
-      G[0] = g0[0] - dp + N - kap * (ur * dr + wrr * dp + dp * dr);
-      G[1] = g0[1] - N;
-      G[2] = g0[2] + mu * (dp - dr);
-    }
+    double w[3] = {0, 0, 0};
+    for (int sp = 0; sp < ns && sp < 3; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
+    reaction_dev(a, inst, w, G);
   }
-
-  const int nm = a.nmax;
   for (int sp = 0; sp < ns; ++sp) {
-    double f = 0.0;
-    const T* Ws = W + sp * npts;
-    if (a.what != 2) {
-      double acc = 0.0;
-      for (int mu = 0; mu < a.ndim; ++mu) {
-        const int x = idx[mu];
-        const int nmu = a.n[mu];
-        const double* cf = a.coef + mu * 3 * nm;
-        const double lo = cf[x], dg = cf[nm + x], up = cf[2 * nm + x];
-        const bool per = (a.periodic_mask >> mu) & 1;
-        int xm = x - 1, xp = x + 1;
-        if (xm < 0) xm = per ? nmu - 1 : -1;
-        if (xp >= nmu) xp = per ? 0 : -1;
-        const double w0 = static_cast<double>(Ws[p]);
-        const double wm = xm >= 0 ? static_cast<double>(Ws[p + (xm - x) * stride[mu]]) : 0.0;
-        const double wp = xp >= 0 ? static_cast<double>(Ws[p + (xp - x) * stride[mu]]) : 0.0;
-        const double* sc = a.scale + mu * 3 * nm;
-        const double scl = sc[i] * sc[nm + j] * sc[2 * nm + k];
-        acc += scl * (lo * wm + dg * w0 + up * wp);
-      }
-      f = a.diff[inst * ns + sp] * acc;
-    }
+    double f = a.what != 2 ? diffusion_dev<T>(a, Wi, inst, sp, p, i, j, k) : 0.0;
     if (a.what != 1 && sp < 3) f += G[sp];
     F[sp * npts + p] = static_cast<T>(f);
   }
 }
 
+// Same computation with the mode count and species count fixed at compile
+// time: every neighbour load of every species is issued before use.
+template <typename T, int NDIM, int NS>
+__global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
+  const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
+  const int npts = n1 * n2 * n3;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int inst = blockIdx.y;
+  if (p >= npts) return;
+  const int q = p / n1;
+  const int i = p - q * n1;
+  const int k = q / n2;
+  const int j = q - k * n2;
+  const T* Wi = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * NS * npts;
+  T* F = static_cast<T*>(a.F) + static_cast<int64_t>(inst) * NS * npts;
+  double w[3] = {0, 0, 0};
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
+  double G[3] = {0, 0, 0};
+  if (a.what != 1 && a.reaction != 0) reaction_dev(a, inst, w, G);
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) {
+    double f = a.what != 2 ? diffusion_fast<T, NDIM>(a, Wi + sp * npts, w[sp], sp, inst, p, i, j, k) : 0.0;
+    if (a.what != 1) f += G[sp];
+    F[sp * npts + p] = static_cast<T>(f);
+  }
+}
+
+template <typename T, int NDIM>
+static hipError_t go_stencil(const StencilArgs& a, dim3 grid, hipStream_t s) {
+  switch (a.nspecies) {
+    case 1: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 1>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 2>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 3>), grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
   const int64_t npts = static_cast<int64_t>(a.n[0]) * a.n[1] * a.n[2];
-  if (npts <= 0 || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
+  if (npts <= 0 || npts >= (int64_t(1) << 31) || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
   dim3 grid(static_cast<unsigned>((npts + 255) / 256), a.batch);
-  hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, s, a);
-  return hipGetLastError();
+  return a.ndim == 3 ? go_stencil<T, 3>(a, grid, s) : go_stencil<T, 2>(a, grid, s);
 }
 
 template hipError_t launch_stencil<double>(const StencilArgs&, hipStream_t);

@@ -55,6 +55,7 @@ struct StencilArgs {
   const double* scale;      // [3 modes][3 coords][nmax]: per-coordinate scale factors
   int nmax;
   int periodic_mask;        // bit mu-1 set: mode mu wraps around
+  int scale_mask;           // bit 3 mu + c set: scale[mu][c] is not all ones
   const double* diff;       // [batch][nspecies]
   int reaction;             // 0 none, 1 Schnakenberg, 2 AIS3
   const double* rparams;    // [batch][4]

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "hostmath.hpp"
+#include "fused.hpp"
 #include "kernels.hpp"
 
 struct tg_grid_s {
@@ -35,6 +36,19 @@ struct ChainOp {
   const double* pn = nullptr;
   const double* pb = nullptr;
   int tile = 0;
+  double flops = 0.0;
+};
+
+// One fused launch of the step (see fused.hpp).  in / out name the
+// buffers: -1 = the state, 0 / 1 = plan scratch buffers.
+struct FusedOp {
+  int kind = 0;            // 0 strided (mode >= 2), 1 first mode
+  int mode = 1;
+  StridedArgs sa{};
+  FirstArgs fa{};
+  int in = -1, out = -1;
+  bool updates_state = false;
+  double flops = 0.0;      // algorithmic flops of one launch (2 n_mu per output of each product)
 };
 
 }  // namespace tg
@@ -61,7 +75,11 @@ struct tg_plan_s {
   const double* d_cs = nullptr;
   int nmax = 0;
   int periodic_mask = 0;
-  std::vector<tg::ChainOp> chain;
+  int scale_mask = 0;
+  std::vector<tg::ChainOp> chain;   // generic route: one launch per mode product
+  std::vector<tg::FusedOp> fused;   // fused route
+  bool fused_ok = false;
+  int route = 0;                     // 0 fused (when available), 1 generic
   // captured step graphs keyed by state pointer
   std::map<void*, hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;

@@ -63,6 +63,7 @@ def test_chain_op_kernels(geometry, n, precision, tol, tau):
     diff = (1.0, 20.0)
     grid = tg.Grid(geometry, n)
     plan = tg.Plan(grid, diff, "schnakenberg", (0.1, 0.9), tau, precision)
+    plan.set_route("generic")
     shape = plan.state_shape
     X = np.random.default_rng(8).random(shape)
     x = plan.state_from_deviation(X)

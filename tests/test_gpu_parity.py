@@ -62,22 +62,28 @@ def test_reaction(geometry, n, precision):
 @pytest.mark.parametrize("geometry,n", GRIDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("tau", [5e-3, 0.3])
-def test_split_phi1(geometry, n, precision, tau):
+@pytest.mark.parametrize("route", ["fused", "generic"])
+def test_split_phi1(geometry, n, precision, tau, route):
     case = Case(geometry, n, precision, tau=tau, seed=3, amplitude=1.0)
+    case.plan.set_route(route)
     plan, x, out = _hooks(case, precision)
     plan.split_phi1(x, out)
     got = out.double().cpu().numpy()[0]
     for s in range(case.ns):
         F = case.to_species(case.pert[0])[s]
         ref = assemble.to_layout(case.oracles[0].split_phi1(F, s))
-        assert rel_err(got[s], ref) < TOL[precision], (s, rel_err(got[s], ref))
+        err = rel_err(got[s], ref)
+        assert err < TOL[precision], (s, err)
 
 
 @pytest.mark.parametrize("geometry,n", GRIDS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_steps(geometry, n, precision):
+@pytest.mark.parametrize("route", ["fused", "generic", "fused_stencil_apart"])
+def test_steps(geometry, n, precision, route):
     ns = 3 if geometry == "cylinder" else 2
     case = Case(geometry, n, precision, tau=5e-3, seed=4, n_species=ns)
+    case.plan.set_route(route)
+    assert case.plan.route == route
     x = case.device_state()
     case.plan.run(x, 10)
     got = case.full_from_device(x)
@@ -100,16 +106,19 @@ def test_batch_with_per_instance_parameters():
 
 
 def test_full_size_ball_fp64_and_fp32():
-    """The 64 x 64 x 128 ball with the benchmark's launch configuration."""
+    """The 64 x 64 x 128 ball with the benchmark's launch configuration
+    (fused route: two launches per step), all elements after 3 steps."""
     n = (64, 64, 128)
     ref = None
     for prec, tol in (("fp64", 1e-12), ("fp32", 2e-7)):
         case = Case("ball", n, prec, tau=5e-3, seed=3)
+        assert case.plan.route == "fused" and len(case.plan.chain()) == 2
         if ref is None:
             ref = case.oracle_run(3)
         x = case.device_state()
         case.plan.run(x, 3)
-        assert rel_err(case.full_from_device(x), ref) < tol, prec
+        err = rel_err(case.full_from_device(x), ref)
+        assert err < tol, (prec, err)
 
 
 def test_equilibrium_is_stationary():
