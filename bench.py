@@ -153,6 +153,19 @@ def main():
         del plan, x, xw, bufs
         torch.cuda.empty_cache()
 
+    # split-bf16 precisions of the same step (fused route)
+    bf = {}
+    for prec in ("bf16x3", "bf16x2"):
+        plan = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, prec)
+        xw = plan.state_from_deviation(pert)
+        plan.run(xw, args.warmup)
+        x = plan.state_from_deviation(pert)
+        sec = time_gpu_run(plan, x, args.steps, 0, torch)
+        full = x.double().cpu().numpy() + plan.reference[:, :, None, None, None]
+        bf[prec] = dict(sec=sec, full=full)
+        del plan, x, xw
+        torch.cuda.empty_cache()
+
     dof = w.dof
     v32 = dof / res["fp32"]["sec"]
     v64 = dof / res["fp64"]["sec"]
@@ -183,6 +196,10 @@ def main():
                    "reaction": w.reaction, "seed": w.seed},
         "fp64": {"value": v64, "ms_per_step": res["fp64"]["sec"] * 1e3, "dtype": "f64"},
         "speedup_fp32_vs_fp64": v32 / v64,
+        "split_bf16": {p: {"value": dof / bf[p]["sec"], "ms_per_step": bf[p]["sec"] * 1e3,
+                           "rel_err_vs_fp64_after_steps": float(np.abs(bf[p]["full"] - ref64).max()
+                                                                / np.abs(ref64).max())}
+                       for p in bf},
         "rel_err_fp32_vs_fp64": {"after_steps": args.steps, "vs_max_state": err_32_64,
                                  "vs_max_deviation": err_32_64_dev},
         "route": res["fp32"]["route"],

@@ -63,7 +63,12 @@ enum { TG_DISK = 0, TG_SPHERE = 1, TG_BALL = 2, TG_CYLINDER = 3 };
  * FP64 on the host and rounded to the storage type.
  *   TG_FP64   : FP64 MFMA, FP64 state.
  *   TG_FP32   : FP32 MFMA, FP32 state.
- *   TG_BF16X2 / TG_BF16X3 : reserved (bf16-split products). */
+ *   TG_BF16X2 : FP32 state; each product operand carried as two bf16 terms
+ *               (x ~ hi + lo), three bf16 MFMA products (hi.hi, hi.lo, lo.hi)
+ *               accumulated in FP32 (about 2^-16 relative per product).
+ *   TG_BF16X3 : three bf16 terms, six products (about 2^-24 relative).
+ * The split-bf16 precisions run on the fused routes only (0 and 2) and
+ * tg_plan_create returns TG_ENOTSUP where those do not fit the grid. */
 enum { TG_FP64 = 0, TG_FP32 = 1, TG_BF16X2 = 2, TG_BF16X3 = 3 };
 
 /* Reaction g(w) (explicit, evaluated at t_n).  params per instance:

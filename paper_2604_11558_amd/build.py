@@ -21,7 +21,7 @@ ARCH = os.environ.get("TGEXP_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", f"-I{os.path.join(ROOT, 'include')}"]
-SOURCES = ["hostmath.cpp", "api.cpp", "kernels.hip", "fused.hip"]
+SOURCES = ["hostmath.cpp", "api.cpp", "kernels.hip", "fused.hip", "fused_bf16.hip"]
 
 
 def _hipcc() -> str:

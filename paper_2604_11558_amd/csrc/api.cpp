@@ -70,6 +70,22 @@ struct Arena {
   }
 };
 
+// Round to the nearest bf16 (ties to even); returns the 16-bit pattern.
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+double bf16_value(uint16_t b) {
+  uint32_t u = static_cast<uint32_t>(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int bf16_terms(int precision) { return precision == TG_BF16X2 ? 2 : (precision == TG_BF16X3 ? 3 : 0); }
+
 std::vector<double> transpose(const std::vector<double>& A, int n) {
   std::vector<double> B(A.size());
   for (int r = 0; r < n; ++r)
@@ -320,6 +336,7 @@ void build_plan(tg_plan_s* P) {
     size_t off = SIZE_MAX;
     int ld = 0, fmod = 1;
   };
+  const int nterms = bf16_terms(P->precision);
   auto addpad = [&](const std::vector<double>& stack, int n, int blocks) {
     PadF f;
     f.ld = (n + 127) / 128 * 128;
@@ -329,7 +346,23 @@ void build_plan(tg_plan_s* P) {
       for (int r = 0; r < n; ++r)
         for (int c = 0; c < n; ++c)
           pad[(static_cast<size_t>(b) * f.ld + r) * f.ld + c] = stack[(static_cast<size_t>(b) * n + r) * n + c];
-    f.off = ar.add_t<T>(pad);
+    if (nterms == 0) {
+      f.off = ar.add_t<T>(pad);
+      return f;
+    }
+    // split-bf16 stack: block b, term t at (b * nterms + t) * ld * ld
+    const size_t sq = static_cast<size_t>(f.ld) * f.ld;
+    std::vector<uint16_t> bf(static_cast<size_t>(blocks) * nterms * sq);
+    for (int b = 0; b < blocks; ++b)
+      for (size_t e = 0; e < sq; ++e) {
+        double r = pad[b * sq + e];
+        for (int t = 0; t < nterms; ++t) {
+          const uint16_t h = bf16_bits(static_cast<float>(r));
+          bf[(static_cast<size_t>(b) * nterms + t) * sq + e] = h;
+          r -= bf16_value(h);
+        }
+      }
+    f.off = ar.add(bf.data(), bf.size() * sizeof(uint16_t));
     return f;
   };
   struct FSpec {
@@ -478,9 +511,16 @@ void build_plan(tg_plan_s* P) {
       tg::Factor F{};
       F.L = f.off == SIZE_MAX ? nullptr : P->dmem + f.off;
       F.ld = f.ld;
-      F.fstride = static_cast<int64_t>(f.ld) * f.ld;
+      F.fstride = static_cast<int64_t>(f.ld) * f.ld * (nterms ? nterms : 1);
       F.fmod = f.fmod;
       return F;
+    };
+    auto strided_lds = [&](int nm, int na, int tn, int sandwich, int plane) {
+      return nterms ? tg::strided_bf16_lds_bytes(nterms, nm, na, tn, sandwich, plane)
+                    : tg::strided_lds_bytes<T>(nm, tn, sandwich, plane);
+    };
+    auto first_lds = [&](int nm, int tm, int sandwich) {
+      return nterms ? tg::first_bf16_lds_bytes(nterms, nm, tm, sandwich) : tg::first_lds_bytes<T>(nm, tm, sandwich);
     };
     auto Dp = [&](size_t off) { return off == SIZE_MAX ? nullptr : D(off); };
     auto first_op = [&](int nm, int rows, const PadF& L1, const PadF& L2, int sandwich, int in) {
@@ -512,7 +552,7 @@ void build_plan(tg_plan_s* P) {
       if (f.kind == 1) {
         auto op = first_op(f.nm, f.rows, f.L1, f.L2, f.sandwich, prev);
         op.fa.ph = {P->d_cs, Dp(f.pm), Dp(f.pn), nullptr};
-        if (tg::first_lds_bytes<T>(f.nm, op.fa.tm, f.sandwich) > kLdsLimit) { ok = false; break; }
+        if (first_lds(f.nm, op.fa.tm, f.sandwich) > kLdsLimit) { ok = false; break; }
         out.push_back(op);
         prev = -1;
         continue;
@@ -537,12 +577,12 @@ void build_plan(tg_plan_s* P) {
       bool plane = f.plane != 0;
       if (plane) {
         sa.tn = (f.na + 31) / 32 * 32;
-        if (tg::strided_lds_bytes<T>(f.nm, sa.tn, f.sandwich, 1) > kLdsLimit) plane = false;
+        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 1) > kLdsLimit) plane = false;
       }
       if (!plane) {
         const int64_t wg32 = static_cast<int64_t>((f.na + 31) / 32) * f.nb * nslab;
         sa.tn = wg32 >= 512 ? 32 : 16;
-        if (tg::strided_lds_bytes<T>(f.nm, sa.tn, f.sandwich, 0) > kLdsLimit) { ok = false; break; }
+        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 0) > kLdsLimit) { ok = false; break; }
       }
       sa.plane = plane ? 1 : 0;
       if (plane) sa.P = mkF(f.Pf);
@@ -561,13 +601,15 @@ void build_plan(tg_plan_s* P) {
       out.push_back(op);
       if (f.plane && !plane) {  // split tail: mode-1 product + update
         auto t = first_op(n1, static_cast<int>(P->npts / n1), f.Pf, f.Pf, 0, prev);
-        if (tg::first_lds_bytes<T>(n1, t.fa.tm, 0) > kLdsLimit) { ok = false; break; }
+        if (first_lds(n1, t.fa.tm, 0) > kLdsLimit) { ok = false; break; }
         out.push_back(t);
         prev = -1;
       }
     }
     P->fused_ok = ok && !out.empty() && out.back().updates_state;
     if (P->fused_ok) P->fused = out;
+    TG_REQUIRE(P->fused_ok || nterms == 0, TG_ENOTSUP,
+               "tg_plan_create: split-bf16 precision needs the fused route, which does not fit this grid");
   }
   const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
   for (int i = 0; i < 2; ++i) hip_check(hipMalloc(&P->scratch[i], bytes), "hipMalloc(scratch)");
@@ -690,13 +732,15 @@ void launch_fused(const tg_plan_s* P, const tg::FusedOp& op, const void* src, vo
     } else {
       a.Y = dst;
     }
-    hip_check(tg::launch_strided<T>(a, st), "fused strided launch");
+    const int nt = bf16_terms(P->precision);
+    hip_check(nt ? tg::launch_strided_bf16(nt, a, st) : tg::launch_strided<T>(a, st), "fused strided launch");
   } else {
     tg::FirstArgs a = op.fa;
     a.X = src;
     a.Y = dst;
     a.update = update ? 1 : 0;
-    hip_check(tg::launch_first<T>(a, st), "fused first-mode launch");
+    const int nt = bf16_terms(P->precision);
+    hip_check(nt ? tg::launch_first_bf16(nt, a, st) : tg::launch_first<T>(a, st), "fused first-mode launch");
   }
 }
 
@@ -735,7 +779,10 @@ void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update,
 
 // 0: fused with the stencil in the first tile load; 2: fused products after
 // a separate stencil launch; 1: one launch per mode product.
-int active_route(const tg_plan_s* P) { return P->fused_ok && P->route != 1 ? P->route : 1; }
+int active_route(const tg_plan_s* P) {
+  if (bf16_terms(P->precision)) return P->route == 2 ? 2 : 0;  // split-bf16 runs fused only
+  return P->fused_ok && P->route != 1 ? P->route : 1;
+}
 bool use_fused(const tg_plan_s* P) { return active_route(P) != 1; }
 
 template <typename T>
@@ -799,8 +846,9 @@ int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* di
     TG_REQUIRE(g && diff && out, TG_EINVAL, "tg_plan_create: null pointer");
     TG_REQUIRE(batch >= 1 && batch <= 65535, TG_EINVAL, "tg_plan_create: batch out of range");
     TG_REQUIRE(std::isfinite(tau) && tau > 0.0, TG_EINVAL, "tg_plan_create: tau must be positive");
-    TG_REQUIRE(precision == TG_FP64 || precision == TG_FP32, TG_ENOTSUP,
-               "tg_plan_create: precision not supported");
+    TG_REQUIRE(precision == TG_FP64 || precision == TG_FP32 || precision == TG_BF16X2 ||
+                   precision == TG_BF16X3,
+               TG_EINVAL, "tg_plan_create: unknown precision");
     int need_ns = 0, need_np = 0;
     switch (reaction) {
       case TG_REACT_NONE: need_ns = -1; need_np = 0; break;
@@ -938,6 +986,8 @@ int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* st
 int tg_plan_set_route(tg_plan p, int32_t route) {
   return guarded([&] {
     TG_REQUIRE(p && route >= 0 && route <= 2, TG_EINVAL, "tg_plan_set_route: bad argument");
+    TG_REQUIRE(!(route == 1 && bf16_terms(p->precision)), TG_ENOTSUP,
+               "tg_plan_set_route: split-bf16 plans have no per-mode route");
     if (route != p->route) {
       for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
       p->graphs.clear();

@@ -81,4 +81,13 @@ size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane);
 template <typename T>
 size_t first_lds_bytes(int nm, int tm, int sandwich);
 
+// Split-bf16 variants (FP32 state and accumulation; nterms = 2 or 3 bf16
+// terms per operand).  Factors are NT-term bf16 stacks: term t of block f at
+// (bf16*) L + f * fstride + t * ld * ld.  A plane launch needs a sandwich
+// and tn == na rounded up to 32.
+hipError_t launch_strided_bf16(int nterms, const StridedArgs& a, hipStream_t s);
+hipError_t launch_first_bf16(int nterms, const FirstArgs& a, hipStream_t s);
+size_t strided_bf16_lds_bytes(int nterms, int nm, int na, int tn, int sandwich, int plane);
+size_t first_bf16_lds_bytes(int nterms, int nm, int tm, int sandwich);
+
 }  // namespace tg

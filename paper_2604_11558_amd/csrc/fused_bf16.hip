@@ -1,0 +1,507 @@
+// Split-bf16 variants of the fused mu-mode product kernels (FP32 state,
+// FP32 accumulation).  Every operand x is carried as NT bf16 terms,
+// x ~ t0 + t1 (+ t2) with t_i = bf16(x - t_0 - ... - t_{i-1}), and a product
+// keeps the term pairs (i, j) with i + j < NT:
+//   NT = 2: t0 s0 + t0 s1 + t1 s0           (3 MFMAs, ~2^-16 relative)
+//   NT = 3: adds t0 s2 + t1 s1 + t2 s0      (6 MFMAs, ~2^-24 relative)
+// Factors are split on the host; data tiles are split once when they enter
+// LDS, stored k-contiguous so that each MFMA operand (8 consecutive k) is a
+// single 16-byte read.  MFMA: v_mfma_f32_16x16x32_bf16, operand A(i, k) in
+// lane i + 16 (k / 8) element k % 8, B(k, j) in lane j + 16 (k / 8) element
+// k % 8, accumulator element r of lane l is D(4 (l / 16) + r, l % 16)
+// (checked on gfx950 with a one-wave probe).
+#include <algorithm>
+
+#include "fused.hpp"
+#include "stencil_dev.hpp"
+
+namespace tg {
+
+typedef float fx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fx4 mfma_bf16(bx8 a, bx8 b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NT>
+__device__ __forceinline__ void split_terms(float x, __bf16 (&t)[NT]) {
+  float r = x;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    t[i] = static_cast<__bf16>(r);
+    r -= static_cast<float>(t[i]);
+  }
+}
+
+__device__ __forceinline__ float phi1f(float x) { return x == 0.0f ? 1.0f : expm1f(x) / x; }
+
+// LDS pitch (bf16 elements) of a k-contiguous row of NP values: the byte
+// stride 2 NP + 16 puts 8 consecutive rows on distinct 16-byte bank groups.
+__host__ __device__ inline int pitch_k(int np) { return np + 8; }
+
+// acc[f][j] += sum_k A(r0 + 16 f + li, k) B(k, c0 + 16 j + li) over the
+// term pairs i + j < NT.  A: rows of a split factor in global memory
+// (term t at A + t * tstride, leading dimension lda).  B: LDS tile, term t
+// at sB + t * bstride, column c stored k-contiguous at c * ldb.
+template <int NT, int FM, int FN, int KB>
+__device__ __forceinline__ void gemm_fac_lds(fx4 (&acc)[FM][FN], const __bf16* __restrict__ A, int64_t tstride,
+                                             int lda, int r0, const __bf16* sB, int bstride, int ldb, int c0,
+                                             int kblocks, int lane) {
+  const int li = lane & 15, g = lane >> 4;
+  const int nkb = KB > 0 ? KB : kblocks;
+#pragma unroll
+  for (int kb = 0; kb < (KB > 0 ? KB : 1); ++kb) {
+    for (int kk = (KB > 0 ? kb : 0); kk < (KB > 0 ? kb + 1 : nkb); ++kk) {
+      const int k0 = 32 * kk + 8 * g;
+      bx8 a[FM][NT], b[FN][NT];
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          a[f][t] = *reinterpret_cast<const bx8*>(A + t * tstride + static_cast<int64_t>(r0 + 16 * f + li) * lda + k0);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          b[j][t] = *reinterpret_cast<const bx8*>(sB + t * bstride + (c0 + 16 * j + li) * ldb + k0);
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < NT - ta; ++tb)
+#pragma unroll
+          for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[f][j] = mfma_bf16(a[f][ta], b[j][tb], acc[f][j]);
+    }
+  }
+}
+
+// acc[f][j] += sum_k sA(r0 + 16 f + li, k) B(c0 + 16 j + li, k): A from an
+// LDS tile (rows k-contiguous), B = rows of a split factor (output columns).
+template <int NT, int FM, int FN, int KB>
+__device__ __forceinline__ void gemm_lds_fac(fx4 (&acc)[FM][FN], const __bf16* sA, int astride, int lda, int r0,
+                                             const __bf16* __restrict__ B, int64_t tstride, int ldb, int c0,
+                                             int kblocks, int lane) {
+  const int li = lane & 15, g = lane >> 4;
+  const int nkb = KB > 0 ? KB : kblocks;
+#pragma unroll
+  for (int kb = 0; kb < (KB > 0 ? KB : 1); ++kb) {
+    for (int kk = (KB > 0 ? kb : 0); kk < (KB > 0 ? kb + 1 : nkb); ++kk) {
+      const int k0 = 32 * kk + 8 * g;
+      bx8 a[FM][NT], b[FN][NT];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          b[j][t] = *reinterpret_cast<const bx8*>(B + t * tstride + static_cast<int64_t>(c0 + 16 * j + li) * ldb + k0);
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          a[f][t] = *reinterpret_cast<const bx8*>(sA + t * astride + (r0 + 16 * f + li) * lda + k0);
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < NT - ta; ++tb)
+#pragma unroll
+          for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[f][j] = mfma_bf16(a[f][ta], b[j][tb], acc[f][j]);
+    }
+  }
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void zero_acc(fx4 (&acc)[FM][FN]) {
+#pragma unroll
+  for (int f = 0; f < FM; ++f)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[f][j] = fx4{0, 0, 0, 0};
+}
+
+__device__ __forceinline__ const __bf16* bf_factor(const Factor& F, int s) {
+  return static_cast<const __bf16*>(F.L) + static_cast<int64_t>(s % F.fmod) * F.fstride;
+}
+
+// Stores NT split terms of 4 values that are consecutive along k of LDS
+// column `col` starting at k = k0 (8-byte stores).
+template <int NT>
+__device__ __forceinline__ void put4_kcontig(__bf16* s, int stride, int ld, int col, int k0, const float (&v)[4]) {
+  __bf16 t[4][NT];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) split_terms<NT>(v[r], t[r]);
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    bx4 w = {t[0][q], t[1][q], t[2][q], t[3][q]};
+    *reinterpret_cast<bx4*>(s + q * stride + col * ld + k0) = w;
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void put1(__bf16* s, int stride, int off, float v) {
+  __bf16 t[NT];
+  split_terms<NT>(v, t);
+#pragma unroll
+  for (int q = 0; q < NT; ++q) s[q * stride + off] = t[q];
+}
+
+// ---------------------------------------------------------------------------
+// Strided mode (mu >= 2): data tile column c (k-contiguous) of NT terms.
+template <int NT, int FM, int FN, int KB>
+__global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, na = a.na, TN = a.tn;
+  const int NP = KB > 0 ? 32 * KB : (nm + 63) / 64 * 64;
+  const int ldk = pitch_k(NP);
+  const int tstr = TN * ldk;                 // one term of one tile
+  // plane tail operand: NP rows (i contiguous) per term, in the data
+  // tile's space once the first product has consumed it
+  const int ldr = pitch_k((na + 31) / 32 * 32);
+  const int rstr = NP * ldr;
+  const int xsz = a.plane ? max(NT * tstr, NT * rstr) : NT * tstr;
+  __bf16* sX = reinterpret_cast<__bf16*>(smem);
+  __bf16* sT = sX + xsz;
+  const int a0 = blockIdx.x * TN, b = blockIdx.y, s = blockIdx.z;
+  const int64_t slab = static_cast<int64_t>(nm) * na * a.nb;
+  const int64_t base = static_cast<int64_t>(s) * slab + static_cast<int64_t>(b) * nm * na;
+
+  // 1. data tile (k < NP rows, zero beyond nm), split into terms
+  if (a.stencil) {
+    const int inst = s / a.st.nspecies, sp = s % a.st.nspecies;
+    const int n1 = a.st.n[0];
+    const bool three = a.st.ndim == 3;
+    for (int e = tid; e < NP * TN; e += 256) {
+      const int k = e / TN, c = e % TN;
+      const int aa = a0 + c;
+      float v = 0.0f;
+      if (k < nm && aa < na) {
+        const int i = three ? aa % n1 : aa;
+        const int j = three ? aa / n1 : k;
+        const int kk = three ? k : 0;
+        v = static_cast<float>(stencil_point_ijk<float>(a.st, inst, sp, k * na + aa, i, j, kk));
+      }
+      put1<NT>(sX, tstr, c * ldk + k, v);
+    }
+  } else {
+    const float* X = static_cast<const float*>(a.X) + base;
+    for (int e = tid; e < NP * TN; e += 256) {
+      const int k = e / TN, c = e % TN;
+      const float v = (k < nm && a0 + c < na) ? X[static_cast<int64_t>(k) * na + a0 + c] : 0.0f;
+      put1<NT>(sX, tstr, c * ldk + k, v);
+    }
+  }
+  __syncthreads();
+
+  const int nrt = NP / (16 * FM), nct = TN / (16 * FN);
+  const int nsub = nrt * nct;
+  const bool keep = a.sandwich || a.plane;
+  const __bf16* L1 = bf_factor(a.L1, s);
+  const int64_t t1 = static_cast<int64_t>(a.L1.ld) * a.L1.ld;
+  float* Y = static_cast<float*>(a.Y) + base;
+  const double cb = a.phi ? a.ph.cs[s] * (a.ph.pb ? a.ph.pb[b] : 1.0) : 0.0;
+  const int kblocks = NP / 32;
+
+  // 2. first product and the phi_1 factor
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    float ph[FM][FN][4];
+    if (a.phi) {
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = min(r0 + 16 * f + 4 * g + r, nm - 1), col = min(a0 + c0 + 16 * j + li, na - 1);
+            double x = cb;
+            if (a.ph.pm) x *= a.ph.pm[row];
+            if (a.ph.pn) x *= a.ph.pn[col];
+            ph[f][j][r] = phi1f(static_cast<float>(x));
+          }
+    }
+    fx4 acc[FM][FN];
+    zero_acc<FM, FN>(acc);
+    gemm_fac_lds<NT, FM, FN, KB>(acc, L1, t1, a.L1.ld, r0, sX, tstr, ldk, c0, kblocks, lane);
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int col = c0 + 16 * j + li;
+        const int rb = r0 + 16 * f + 4 * g;
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const bool in = rb + r < nm && a0 + col < na;
+          v[r] = acc[f][j][r] * (a.phi ? ph[f][j][r] : 1.0f);
+          if (!in) v[r] = 0.0f;
+          if (!keep && in) Y[static_cast<int64_t>(rb + r) * na + a0 + col] = v[r];
+        }
+        if (keep) put4_kcontig<NT>(sT, tstr, ldk, col, rb, v);
+      }
+  }
+  if (!keep) return;
+  __syncthreads();
+
+  // 3. second product of the sandwich; for the plane tail the result goes
+  //    to LDS rows (row-major, i contiguous) for the mode-1 product
+  if (a.sandwich) {
+    const __bf16* L2 = bf_factor(a.L2, s);
+    const int64_t t2 = static_cast<int64_t>(a.L2.ld) * a.L2.ld;
+    for (int sub = wave; sub < nsub; sub += 4) {
+      const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+      fx4 acc[FM][FN];
+      zero_acc<FM, FN>(acc);
+      gemm_fac_lds<NT, FM, FN, KB>(acc, L2, t2, a.L2.ld, r0, sT, tstr, ldk, c0, kblocks, lane);
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 16 * f + 4 * g + r, col = c0 + 16 * j + li;
+            const bool in = row < nm && a0 + col < na;
+            const float v = in ? acc[f][j][r] : 0.0f;
+            if (a.plane) put1<NT>(sX, rstr, row * ldr + col, v);
+            else if (in) Y[static_cast<int64_t>(row) * na + a0 + col] = v;
+          }
+    }
+    if (!a.plane) return;
+    __syncthreads();
+  }
+
+  // 4. plane tail: Z[row][i'] = sum_i T[row][i] P[i'][i];  W += alpha Z
+  //    (a plane launch always has a sandwich, so T is in sX as rows)
+  const __bf16* P = bf_factor(a.P, s);
+  const int64_t tp = static_cast<int64_t>(a.P.ld) * a.P.ld;
+  float* W = static_cast<float*>(a.W) + base;
+  const int kbt = (na + 31) / 32;
+  const float alpha = static_cast<float>(a.alpha);
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    float wv[FM][FN][4];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(r0 + 16 * f + 4 * g + r, nm - 1), col = min(c0 + 16 * j + li, na - 1);
+          wv[f][j][r] = a.update ? W[static_cast<int64_t>(row) * na + col] : 0.0f;
+        }
+    fx4 acc[FM][FN];
+    zero_acc<FM, FN>(acc);
+    gemm_lds_fac<NT, FM, FN, 0>(acc, sX, rstr, ldr, r0, P, tp, a.P.ld, c0, kbt, lane);
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * f + 4 * g + r, col = c0 + 16 * j + li;
+          const float nv = a.update ? wv[f][j][r] + alpha * acc[f][j][r] : acc[f][j][r];
+          if (row < nm && col < na) {
+            W[static_cast<int64_t>(row) * na + col] = nv;
+            bad |= !isfinite(nv);
+          }
+        }
+    if (bad && a.flag) atomicOr(a.flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First mode: data tile rows (k-contiguous) of NT terms.
+template <int NT, int FM, int FN, int KB>
+__global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, TM = a.tm;
+  const int NP = KB > 0 ? 32 * KB : (nm + 31) / 32 * 32;
+  const int ldk = pitch_k(NP);
+  const int tstr = TM * ldk;
+  __bf16* sX = reinterpret_cast<__bf16*>(smem);
+  __bf16* sT = sX + NT * tstr;
+  const int rt0 = blockIdx.x * TM, s = blockIdx.y;
+  const int64_t base = static_cast<int64_t>(s) * a.rows * nm;
+  const float* X = static_cast<const float*>(a.X) + base;
+  for (int e = tid; e < TM * NP; e += 256) {
+    const int r = e / NP, c = e % NP;
+    const float v = (c < nm && rt0 + r < a.rows) ? X[static_cast<int64_t>(rt0 + r) * nm + c] : 0.0f;
+    put1<NT>(sX, tstr, r * ldk + c, v);
+  }
+  __syncthreads();
+
+  const int nrt = TM / (16 * FM), nct = NP / (16 * FN);
+  const int nsub = nrt * nct;
+  float* Y = static_cast<float*>(a.Y) + base;
+  const float alpha = static_cast<float>(a.alpha);
+  const int kblocks = NP / 32;
+  auto finish = [&](int r0, int c0, const fx4 (&acc)[FM][FN]) {
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rg = rt0 + r0 + 16 * f + 4 * g + r, col = c0 + 16 * j + li;
+          if (rg < a.rows && col < nm) {
+            float* dst = Y + static_cast<int64_t>(rg) * nm + col;
+            const float nv = a.update ? *dst + alpha * acc[f][j][r] : acc[f][j][r];
+            *dst = nv;
+            bad |= !isfinite(nv);
+          }
+        }
+    if (bad && a.update && a.flag) atomicOr(a.flag, 1);
+  };
+  const __bf16* L1 = bf_factor(a.L1, s);
+  const int64_t t1 = static_cast<int64_t>(a.L1.ld) * a.L1.ld;
+  const double cs = a.sandwich ? a.ph.cs[s] : 0.0;
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    float ph[FM][FN][4];
+    if (a.sandwich) {
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rg = min(rt0 + r0 + 16 * f + 4 * g + r, a.rows - 1), col = min(c0 + 16 * j + li, nm - 1);
+            double x = cs;
+            if (a.ph.pm) x *= a.ph.pm[rg];
+            if (a.ph.pn) x *= a.ph.pn[col];
+            ph[f][j][r] = phi1f(static_cast<float>(x));
+          }
+    }
+    fx4 acc[FM][FN];
+    zero_acc<FM, FN>(acc);
+    gemm_lds_fac<NT, FM, FN, KB>(acc, sX, tstr, ldk, r0, L1, t1, a.L1.ld, c0, kblocks, lane);
+    if (!a.sandwich) {
+      finish(r0, c0, acc);
+      continue;
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * f + 4 * g + r, col = c0 + 16 * j + li;
+          const bool in = col < nm && rt0 + row < a.rows;
+          put1<NT>(sT, tstr, row * ldk + col, in ? acc[f][j][r] * ph[f][j][r] : 0.0f);
+        }
+  }
+  if (!a.sandwich) return;
+  __syncthreads();
+  const __bf16* L2 = bf_factor(a.L2, s);
+  const int64_t t2 = static_cast<int64_t>(a.L2.ld) * a.L2.ld;
+  for (int sub = wave; sub < nsub; sub += 4) {
+    const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+    fx4 acc[FM][FN];
+    zero_acc<FM, FN>(acc);
+    gemm_lds_fac<NT, FM, FN, KB>(acc, sT, tstr, ldk, r0, L2, t2, a.L2.ld, c0, kblocks, lane);
+    finish(r0, c0, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+static int bf_np_strided(int nm) { return nm <= 64 ? 64 : (nm <= 128 ? 128 : (nm + 63) / 64 * 64); }
+static int bf_np_first(int nm) { return nm <= 64 ? 64 : (nm <= 128 ? 128 : (nm + 31) / 32 * 32); }
+static int bf_kb(int nm) { return nm <= 64 ? 2 : (nm <= 128 ? 4 : 0); }
+
+size_t strided_bf16_lds_bytes(int nterms, int nm, int na, int tn, int sandwich, int plane) {
+  const int NP = bf_np_strided(nm);
+  const size_t tile = static_cast<size_t>(nterms) * tn * pitch_k(NP);
+  const size_t rows = plane ? static_cast<size_t>(nterms) * NP * pitch_k((na + 31) / 32 * 32) : 0;
+  const size_t x = std::max(tile, rows);
+  return 2 * ((sandwich || plane) ? x + tile : x);
+}
+
+size_t first_bf16_lds_bytes(int nterms, int nm, int tm, int sandwich) {
+  const int NP = bf_np_first(nm);
+  return static_cast<size_t>(sandwich ? 2 : 1) * nterms * tm * pitch_k(NP) * 2;
+}
+
+template <typename K>
+static hipError_t bf_allow(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes));
+}
+
+template <int NT, int FM, int FN, int KB>
+static hipError_t go_sbf(const StridedArgs& a, size_t lds, hipStream_t s) {
+  auto k = strided_bf16_kernel<NT, FM, FN, KB>;
+  hipError_t e = bf_allow(k, lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((a.na + a.tn - 1) / a.tn, a.nb, a.nslab);
+  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t sbf_dispatch(const StridedArgs& a, size_t lds, hipStream_t s) {
+  const int kb = bf_kb(a.nm);
+  const bool fn2 = a.tn % 32 == 0;
+  if (kb == 2) return fn2 ? go_sbf<NT, 2, 2, 2>(a, lds, s) : go_sbf<NT, 2, 1, 2>(a, lds, s);
+  if (kb == 4) return fn2 ? go_sbf<NT, 2, 2, 4>(a, lds, s) : go_sbf<NT, 2, 1, 4>(a, lds, s);
+  return fn2 ? go_sbf<NT, 4, 2, 0>(a, lds, s) : go_sbf<NT, 4, 1, 0>(a, lds, s);
+}
+
+hipError_t launch_strided_bf16(int nterms, const StridedArgs& a, hipStream_t s) {
+  if (a.nm <= 0 || a.na <= 0 || a.nb <= 0 || a.nslab <= 0 || a.nb > 65535 || a.nslab > 65535)
+    return hipErrorInvalidValue;
+  if (a.tn != 16 && a.tn % 32 != 0) return hipErrorInvalidValue;
+  if (a.plane && (a.tn != (a.na + 31) / 32 * 32 || !a.sandwich)) return hipErrorInvalidValue;
+  const int NP = bf_np_strided(a.nm);
+  if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP) || (a.plane && a.P.ld < (a.na + 31) / 32 * 32))
+    return hipErrorInvalidValue;
+  const size_t lds = strided_bf16_lds_bytes(nterms, a.nm, a.na, a.tn, a.sandwich, a.plane);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (nterms == 2) return sbf_dispatch<2>(a, lds, s);
+  if (nterms == 3) return sbf_dispatch<3>(a, lds, s);
+  return hipErrorInvalidValue;
+}
+
+template <int NT, int FM, int FN, int KB>
+static hipError_t go_fbf(const FirstArgs& a, size_t lds, hipStream_t s) {
+  auto k = first_bf16_kernel<NT, FM, FN, KB>;
+  hipError_t e = bf_allow(k, lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((a.rows + a.tm - 1) / a.tm, a.nslab);
+  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t fbf_dispatch(const FirstArgs& a, size_t lds, hipStream_t s) {
+  const int kb = bf_kb(a.nm);
+  if (a.tm == 16) {
+    if (kb == 2) return go_fbf<NT, 1, 2, 2>(a, lds, s);
+    if (kb == 4) return go_fbf<NT, 1, 2, 4>(a, lds, s);
+    return go_fbf<NT, 1, 2, 0>(a, lds, s);
+  }
+  if (kb == 2) return go_fbf<NT, 2, 2, 2>(a, lds, s);
+  if (kb == 4) return go_fbf<NT, 2, 2, 4>(a, lds, s);
+  return go_fbf<NT, 2, 2, 0>(a, lds, s);
+}
+
+hipError_t launch_first_bf16(int nterms, const FirstArgs& a, hipStream_t s) {
+  if (a.nm <= 0 || a.rows <= 0 || a.nslab <= 0 || a.nslab > 65535) return hipErrorInvalidValue;
+  if (a.tm != 16 && a.tm != 32) return hipErrorInvalidValue;
+  const int NP = bf_np_first(a.nm);
+  if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP)) return hipErrorInvalidValue;
+  const size_t lds = first_bf16_lds_bytes(nterms, a.nm, a.tm, a.sandwich);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (nterms == 2) return fbf_dispatch<2>(a, lds, s);
+  if (nterms == 3) return fbf_dispatch<3>(a, lds, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tg

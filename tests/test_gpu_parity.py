@@ -126,3 +126,50 @@ def test_equilibrium_is_stationary():
     x = case.device_state()
     case.plan.run(x, 5)
     assert float(x.abs().max()) < 1e-14
+
+
+# split-bf16 precisions: operand representation error 2^-17 per term pair
+# (two terms) or 2^-25 (three terms), times the chain length and the
+# eigenvector conditioning; bounds below hold with a margin of about 5x
+# over the measured errors (parity table).
+BF16_TOL = {"bf16x2": {"split": 6e-5, "steps": 1.5e-6}, "bf16x3": {"split": 3.5e-6, "steps": 3e-8}}
+BF16_GRIDS = [("disk", (37, 70)), ("sphere", (70, 45)), ("ball", (20, 24, 37)),
+              ("cylinder", (27, 30, 19)), ("ball", (64, 64, 128))]
+
+
+@pytest.mark.parametrize("geometry,n", BF16_GRIDS)
+@pytest.mark.parametrize("precision", ["bf16x2", "bf16x3"])
+def test_bf16_split_phi1(geometry, n, precision):
+    case = Case(geometry, n, precision, tau=5e-3, seed=3, amplitude=1.0)
+    assert case.plan.route == "fused"
+    plan, x, out = _hooks(case, precision)
+    plan.split_phi1(x, out)
+    got = out.double().cpu().numpy()[0]
+    errs = []
+    for s in range(case.ns):
+        F = case.to_species(case.pert[0])[s]
+        ref = assemble.to_layout(case.oracles[0].split_phi1(F, s))
+        errs.append(rel_err(got[s], ref))
+    print(geometry, n, precision, "split errors", errs)
+    assert max(errs) < BF16_TOL[precision]["split"], errs
+
+
+@pytest.mark.parametrize("geometry,n", BF16_GRIDS[:4])
+@pytest.mark.parametrize("precision", ["bf16x2", "bf16x3"])
+@pytest.mark.parametrize("route", ["fused", "fused_stencil_apart"])
+def test_bf16_steps(geometry, n, precision, route):
+    ns = 3 if geometry == "cylinder" else 2
+    case = Case(geometry, n, precision, tau=5e-3, seed=4, n_species=ns)
+    case.plan.set_route(route)
+    x = case.device_state()
+    case.plan.run(x, 10)
+    err = rel_err(case.full_from_device(x), case.oracle_run(10))
+    print(geometry, n, precision, route, "10-step error", err)
+    assert err < BF16_TOL[precision]["steps"], err
+
+
+def test_bf16_rejects_generic_route():
+    import paper_2604_11558_amd as tg
+    case = Case("disk", (12, 16), "bf16x3")
+    with pytest.raises(tg.TGError):
+        case.plan.set_route("generic")
