@@ -114,16 +114,27 @@ def apply_chain_dd(ops, X):
 
 
 def param_derivative(kind, U, params):
-    """dG_r/dp_q pointwise, list over r of list over q (Schnakenberg: p=(a,b))."""
+    """dG_r/dp_q pointwise, list over r of list over q.
+
+    Schnakenberg p = (a, b); AIS3 p = (a, b, kappa, mu) with
+    G = (a - u + u^2 v - kappa u w, b - u^2 v, mu (u - w)).
+    """
     one = np.ones_like(U[0])
     zero = np.zeros_like(U[0])
     if kind == "schnakenberg":
         return [[one, zero], [zero, one]]
+    if kind == "ais3":
+        u, _, w = U
+        return [[one, zero, -u * w, zero], [zero, one, zero, zero], [zero, zero, zero, u - w]]
     raise NotImplementedError(kind)
 
 
-def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None):
-    """L and dL/d(W0, d_s, params) for species-list W0s (arrays [i,j,..])."""
+def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None, w_dirichlet=None):
+    """L and dL/d(W0, d_s, params) for species-list W0s (arrays [i,j,..]).
+
+    ``w_dirichlet`` (per species) is the boundary value at z_* of the
+    cylinder; the lifted term d_s r w_D then enters F and dL/dd_s.
+    """
     diff = list(workload.diff if diff is None else diff)
     params = tuple(workload.params if params is None else params)
     n = tuple(workload.n if n is None else n)
@@ -132,7 +143,7 @@ def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None):
     # forward, storing all states (oracle sizes are small)
     states = [list(W0s)]
     for _ in range(steps):
-        states.append(se.step(states[-1], react))
+        states.append(se.step(states[-1], react, w_dirichlet=w_dirichlet))
     resid = states[-1][0] - target
     L = 0.5 * float(np.sum(resid * resid))
     lam = [resid] + [np.zeros_like(W) for W in W0s[1:]]
@@ -149,7 +160,8 @@ def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None):
         mus = [se.tau * apply_chain_T(ops[s], lam[s]) for s in range(ns)]
         new = []
         for s in range(ns):
-            MW = assemble.unvec(se.M @ assemble.vec(Ws[s]), n)
+            wd = 0.0 if w_dirichlet is None else w_dirichlet[s]
+            MW = assemble.unvec(se.M @ assemble.vec(Ws[s]) + se.lift * wd, n)
             F = diff[s] * MW + G[s]
             g_d[s] += se.tau * float(np.sum(lam[s] * apply_chain_dd(ops[s], F)))
             g_d[s] += float(np.sum(mus[s] * MW))
@@ -165,7 +177,7 @@ def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None):
     return L, lam, g_d, g_p
 
 
-def loss(workload, W0s, target, steps, n=None, diff=None, params=None):
+def loss(workload, W0s, target, steps, n=None, diff=None, params=None, w_dirichlet=None):
     diff = list(workload.diff if diff is None else diff)
     params = tuple(workload.params if params is None else params)
     n = tuple(workload.n if n is None else n)
@@ -173,6 +185,6 @@ def loss(workload, W0s, target, steps, n=None, diff=None, params=None):
     react = lambda U: reactions.reaction(workload.reaction, U, params)  # noqa: E731
     Ws = list(W0s)
     for _ in range(steps):
-        Ws = se.step(Ws, react)
+        Ws = se.step(Ws, react, w_dirichlet=w_dirichlet)
     r = Ws[0] - target
     return 0.5 * float(np.sum(r * r))

@@ -73,3 +73,37 @@ def test_gradient_vs_central_differences():
             return adjoint.loss(w, W0, target, w.steps, params=p)
         rich, _ = _richardson(fp, h)
         assert abs(rich - gp[q]) < 1e-6 * abs(gp[q]) + 1e-7 * scale
+
+
+def test_gradient_cylinder_dirichlet_ais3_vs_central_differences():
+    """Three species (AIS3) on the cylinder with the lifted Dirichlet data at z_*:
+    the lift term enters F and dL/dd_s; kappa and mu enter through dG/dp."""
+    w = workloads.scaled(workloads.WORKLOADS["cylinder_100x100x100"], (4, 5, 3), steps=4)
+    pert = workloads.perturbation(w)
+    W0 = splitee.initial_state(w, pert)
+    # boundary data away from equilibrium, so the lift term does not vanish
+    wd = [W0[s].mean() + 0.05 * (s + 1) for s in range(3)]
+    target = W0[0] + 1e-3 * np.random.default_rng(11).random(w.n)
+    L, lam0, gd, gp = adjoint.loss_and_grad(w, W0, target, w.steps, w_dirichlet=wd)
+    h = 1e-4
+    dirs = [np.random.default_rng(12 + s).standard_normal(w.n) for s in range(3)]
+    ic = lambda e: adjoint.loss(w, [W0[s] + e * dirs[s] for s in range(3)], target, w.steps,  # noqa
+                                w_dirichlet=wd)
+    an = sum(np.sum(lam0[s] * dirs[s]) for s in range(3))
+    rich, _ = _richardson(ic, h)
+    assert abs(rich - an) < 1e-8 * abs(an)
+    scale = max(np.abs(gd).max(), np.abs(gp).max())
+    for s in range(3):
+        def fd(e, s=s):
+            d = list(w.diff)
+            d[s] += e
+            return adjoint.loss(w, W0, target, w.steps, diff=d, w_dirichlet=wd)
+        rich, _ = _richardson(fd, h)
+        assert abs(rich - gd[s]) < 1e-6 * abs(gd[s]) + 1e-7 * scale
+    for q in range(4):
+        def fp(e, q=q):
+            p = list(w.params)
+            p[q] += e
+            return adjoint.loss(w, W0, target, w.steps, params=p, w_dirichlet=wd)
+        rich, _ = _richardson(fp, h)
+        assert abs(rich - gp[q]) < 1e-6 * abs(gp[q]) + 1e-7 * scale
