@@ -137,6 +137,23 @@ int tg_step(tg_plan p, void* state, void* stream);
  * update produced a non-finite value. */
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
 
+/* Reverse step of the discrete adjoint of tg_step (not in the paper; the
+ * exact derivative of the discrete map).  With mu_s = tau S_s^T lambda_s,
+ * S_s = phi_1(tau d_s M_1) ... phi_1(tau d_s M_d):
+ *   lambda_s <- lambda_s + d_s M^T mu_s + sum_r (dg_r / dw_s)(W_n) mu_r,
+ *   grad[s]         += tau <lambda_s, (dS_s/dd_s) F_s> + <mu_s, M W_n,s>
+ *   grad[nslab + s] += sum over points of mu_s (the derivative with respect
+ *                      to a constant source in species s' reaction: the
+ *                      Schnakenberg and 3-species constants a and b)
+ * where nslab = batch * n_species, F_s = d_s M W_n,s + g_s(W_n) and the
+ * old lambda_s is used on the right.  state_n: the state at step n (input,
+ * device, plan layout); lambda: dL/dW_{n+1} in, dL/dW_n out (device, same
+ * layout); grad: device doubles [2 * nslab], accumulated.  Runs the
+ * per-mode kernels in the plan's storage type (FP32 for split-bf16 plans)
+ * and allocates an 8-state workspace on first use.  The reference state
+ * (and the cylinder's Dirichlet value) is held fixed. */
+int tg_adjoint_step(tg_plan p, const void* state_n, void* lambda, double* grad, void* stream);
+
 /* Test hooks for the pieces of one step (same layouts as the state):
  *   what = TG_APPLY_F:         out = d_s M in + g(in)     (the F stage)
  *   what = TG_APPLY_DIFFUSION: out = d_s M in

@@ -52,6 +52,7 @@ _SIGNATURES = {
     "tg_plan_chain": (ctypes.c_int, [_p, _pi, _pi, _pd]),
     "tg_apply_chain_op": (ctypes.c_int, [_p, _c_int, _p, _p, _p]),
     "tg_plan_set_route": (ctypes.c_int, [_p, _c_int]),
+    "tg_adjoint_step": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "tg_plan_route": (ctypes.c_int, [_p, _pi]),
 }
 
@@ -253,6 +254,16 @@ class Plan:
         self._check_tensor(out)
         _check(lib().tg_apply_chain_op(self._h, int(op), x.data_ptr(), out.data_ptr(),
                                        _stream_ptr(stream)))
+
+    def adjoint_step(self, state_n, lam, grad, stream=None):
+        """lam <- dL/dW_n from dL/dW_{n+1}; grad (cuda float64, 2 * batch * species) accumulates."""
+        import torch
+        self._check_tensor(state_n)
+        self._check_tensor(lam)
+        if grad.dtype != torch.float64 or not grad.is_cuda or grad.numel() != 2 * self.batch * self.n_species:
+            raise ValueError("grad must be a cuda float64 tensor of 2 * batch * n_species entries")
+        _check(lib().tg_adjoint_step(self._h, state_n.data_ptr(), lam.data_ptr(), grad.data_ptr(),
+                                     _stream_ptr(stream)))
 
     def split_phi1(self, x, out, stream=None):
         self._check_tensor(x)

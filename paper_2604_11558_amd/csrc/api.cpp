@@ -326,6 +326,26 @@ void build_plan(tg_plan_s* P) {
   struct PendingOp {
     int mode, epi, fmod;
     size_t L, pm = SIZE_MAX, pn = SIZE_MAX, pb = SIZE_MAX;
+    size_t LT = SIZE_MAX, dL = SIZE_MAX;
+  };
+  // transposed blocks of a factor stack (n x n blocks)
+  auto add_transposed = [&](const std::vector<double>& stack, int n) {
+    std::vector<double> t(stack.size());
+    const size_t sq = static_cast<size_t>(n) * n;
+    for (size_t b = 0; b < stack.size() / sq; ++b)
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) t[b * sq + c * n + r] = stack[b * sq + r * n + c];
+    return ar.add_t<T>(t);
+  };
+  // d/dd phi_1(tau d extra A) per block = tau extra V diag(lam (phi_1 - phi_2)(c lam)) V^-1
+  auto per_slab_dfactor = [&](const tg::Eig& e, double extra) {
+    std::vector<double> all;
+    for (int f = 0; f < fmod; ++f) {
+      auto D = tg::dphi1_from_eig(e, cs[f] * extra);
+      for (double& x : D) x *= tau * extra;
+      all.insert(all.end(), D.begin(), D.end());
+    }
+    return all;
   };
   std::vector<PendingOp> ops;
   const double s2 = (G.geometry == TG_SPHERE) ? 1.0 / (G.extent[0] * G.extent[0]) : 1.0;
@@ -384,6 +404,10 @@ void build_plan(tg_plan_s* P) {
     PendingOp o2{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
     auto Pr = per_slab_factor(er, 1.0);
     PendingOp o3{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(Pr)};
+    o1.LT = add_transposed(et.Vinv, n2);
+    o2.LT = add_transposed(et.V, n2);
+    o3.LT = add_transposed(Pr, n1);
+    o3.dL = ar.add_t<T>(per_slab_dfactor(er, 1.0));
     ops = {o1, o2, o3};
     FSpec a;  // theta sandwich with the stencil, then rho (plane tail when it fits)
     a.mode = 2; a.nm = n2; a.na = n1; a.nb = 1;
@@ -397,11 +421,16 @@ void build_plan(tg_plan_s* P) {
     set_scale(1, 0, std::vector<double>(n1, s2));
     auto et = G.eig(0);
     auto ep = G.eig(1);
-    PendingOp o1{2, tg::EPI_STORE, fmod, ar.add_t<T>(per_slab_factor(ep, s2))};
+    auto Pp = per_slab_factor(ep, s2);
+    PendingOp o1{2, tg::EPI_STORE, fmod, ar.add_t<T>(Pp)};
     PendingOp o2{1, tg::EPI_PHI, 1, ar.add_t<T>(et.Vinv)};
     o2.pm = ar.add_d(sph);
     o2.pn = ar.add_d(et.lam);
     PendingOp o3{1, tg::EPI_UPDATE, 1, ar.add_t<T>(et.V)};
+    o1.LT = add_transposed(Pp, n2);
+    o1.dL = ar.add_t<T>(per_slab_dfactor(ep, s2));
+    o2.LT = add_transposed(et.Vinv, n1);
+    o3.LT = add_transposed(et.V, n1);
     ops = {o1, o2, o3};
     FSpec a;  // phi product with the stencil
     a.mode = 2; a.nm = n2; a.na = n1; a.nb = 1; a.stencil = 1;
@@ -434,6 +463,12 @@ void build_plan(tg_plan_s* P) {
     PendingOp o4{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
     auto Pr = per_slab_factor(er, 1.0);
     PendingOp o5{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(Pr)};
+    o1.LT = add_transposed(ep.Vinv, n3);
+    o2.LT = add_transposed(ep.V, n3);
+    o3.LT = add_transposed(et.Vinv, n2);
+    o4.LT = add_transposed(et.V, n2);
+    o5.LT = add_transposed(Pr, n1);
+    o5.dL = ar.add_t<T>(per_slab_dfactor(er, 1.0));
     ops = {o1, o2, o3, o4, o5};
     FSpec a;  // phi sandwich with the stencil
     a.mode = 3; a.nm = n3; a.na = n1 * n2; a.nb = 1;
@@ -460,6 +495,12 @@ void build_plan(tg_plan_s* P) {
     o2.pn = ar.add_d(rinv2);
     PendingOp o3{2, tg::EPI_STORE, 1, ar.add_t<T>(et.V)};
     PendingOp o4{1, tg::EPI_UPDATE, fmod, ar.add_t<T>(Pr)};
+    o1.LT = add_transposed(Pz, n3);
+    o1.dL = ar.add_t<T>(per_slab_dfactor(ez, 1.0));
+    o2.LT = add_transposed(et.Vinv, n2);
+    o3.LT = add_transposed(et.V, n2);
+    o4.LT = add_transposed(Pr, n1);
+    o4.dL = ar.add_t<T>(per_slab_dfactor(er, 1.0));
     ops = {o1, o2, o3, o4};
     FSpec a;  // z product with the stencil
     a.mode = 3; a.nm = n3; a.na = n1 * n2; a.nb = 1; a.stencil = 1;
@@ -472,6 +513,26 @@ void build_plan(tg_plan_s* P) {
     fspecs = {a, b};
   }
 
+  // transposed operators: (A^T)[r][r-1] = A[r-1][r], (A^T)[r][r+1] = A[r+1][r]
+  std::vector<double> coefT(coef.size(), 0.0);
+  for (int m = 0; m < nd; ++m) {
+    const int nmu = G.n[m];
+    const bool per = (P->periodic_mask >> m) & 1;
+    const double* lo = &coef[(m * 3 + 0) * nmax];
+    const double* dg = &coef[(m * 3 + 1) * nmax];
+    const double* up = &coef[(m * 3 + 2) * nmax];
+    for (int r = 0; r < nmu; ++r) {
+      coefT[(m * 3 + 1) * nmax + r] = dg[r];
+      coefT[(m * 3 + 0) * nmax + r] = r > 0 ? up[r - 1] : (per ? up[nmu - 1] : 0.0);
+      coefT[(m * 3 + 2) * nmax + r] = r + 1 < nmu ? lo[r + 1] : (per ? lo[0] : 0.0);
+    }
+  }
+  std::vector<double> rd(nslab), tv(nslab, tau), trd(nslab);
+  for (int q = 0; q < nslab; ++q) {
+    rd[q] = 1.0 / P->diff[q];
+    trd[q] = tau / P->diff[q];
+  }
+  const size_t o_coefT = ar.add_d(coefT), o_rd = ar.add_d(rd), o_tv = ar.add_d(tv), o_trd = ar.add_d(trd);
   const size_t o_coef = ar.add_d(coef), o_scale = ar.add_d(scale);
   const size_t o_diff = ar.add_d(P->diff), o_rp = ar.add_d(P->rparams);
   const size_t o_wref = ar.add_d(P->wref), o_g0 = ar.add_d(P->g0), o_cs = ar.add_d(cs);
@@ -486,6 +547,10 @@ void build_plan(tg_plan_s* P) {
   P->d_wref = D(o_wref);
   P->d_g0 = D(o_g0);
   P->d_cs = D(o_cs);
+  P->d_coefT = D(o_coefT);
+  P->d_rd = D(o_rd);
+  P->d_tau = D(o_tv);
+  P->d_taurd = D(o_trd);
   const int nn[3] = {n1, n2, n3};
   for (const auto& o : ops) {
     tg::ChainOp c;
@@ -496,6 +561,8 @@ void build_plan(tg_plan_s* P) {
     c.pm = o.pm == SIZE_MAX ? nullptr : D(o.pm);
     c.pn = o.pn == SIZE_MAX ? nullptr : D(o.pn);
     c.pb = o.pb == SIZE_MAX ? nullptr : D(o.pb);
+    c.LT = o.LT == SIZE_MAX ? nullptr : P->dmem + o.LT;
+    c.dL = o.dL == SIZE_MAX ? nullptr : P->dmem + o.dL;
     int64_t na = 1, nb = 1;
     for (int m = 0; m < o.mode - 1; ++m) na *= nn[m];
     for (int m = o.mode; m < 3; ++m) nb *= nn[m];
@@ -619,7 +686,8 @@ void build_plan(tg_plan_s* P) {
 
 // Launch one chain op reading X and writing Y (or updating Y += tau * acc).
 template <typename T>
-void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y, int epi, hipStream_t st) {
+void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y, int epi, hipStream_t st,
+               double alpha = -1.0) {
   const int nd = P->grid.ndim;
   const int nn[3] = {P->grid.n[0], P->grid.n[1], nd == 3 ? P->grid.n[2] : 1};
   int64_t na = 1, nb = 1;
@@ -629,13 +697,14 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
   tg::GemmArgs g{};
   g.nslab = P->nslab;
   g.epi = epi;
-  g.alpha = P->tau;
+  g.alpha = alpha < 0.0 ? P->tau : alpha;
   g.cs = P->d_cs;
   g.pm = c.pm;
   g.pn = c.pn;
   g.pb = c.pb;
   g.tile = c.tile;
   g.flag = P->dflag;
+  g.rd = P->d_rd;
   const int64_t slab = P->npts;
   const int big = std::numeric_limits<int>::max();
   if (c.mode == 1) {
@@ -802,6 +871,107 @@ void step_impl(tg_plan_s* P, void* state, hipStream_t st) {
   run_chain<T>(P, P->scratch[0], state, true, st);
 }
 
+// One reverse step of the discrete adjoint (see tg_adjoint_step).
+template <typename T>
+void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipStream_t st) {
+  const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
+  if (!P->adj_ws) hip_check(hipMalloc(&P->adj_ws, 8 * bytes), "hipMalloc(adjoint workspace)");
+  char* w = static_cast<char*>(P->adj_ws);
+  void* F = w;
+  void* DMW = w + bytes;
+  void* xbuf[2] = {w + 2 * bytes, w + 3 * bytes};
+  void* tbuf[2] = {w + 4 * bytes, w + 5 * bytes};
+  void* MU = w + 6 * bytes;
+  void* MTMU = w + 7 * bytes;
+  const int nslab = P->nslab;
+  const int64_t npts = P->npts;
+
+  // F = d M W + g(W) and d M W at step n
+  launch_stencil_stage<T>(P, state, F, TG_APPLY_F, st);
+  launch_stencil_stage<T>(P, state, DMW, TG_APPLY_DIFFUSION, st);
+
+  // tangent of the split action along d: t = (dS/dd) F, carried through the
+  // chain next to x = partial products of S F
+  const void* x = F;
+  const void* t = nullptr;
+  int xb = 0, tb = 0;
+  for (const auto& c : P->chain) {
+    void* xn = xbuf[xb];
+    void* tn = tbuf[tb];
+    bool t_written = false;
+    if (c.epi == tg::EPI_PHI) {  // y = Phi o (L x): t' = Phi o (L t) + dPhi/dd o (L x)
+      launch_op<T>(P, c, x, tn, tg::EPI_DPHI, st);
+      if (t) launch_op<T>(P, c, t, tn, tg::EPI_PHI_ACC, st);
+      launch_op<T>(P, c, x, xn, tg::EPI_PHI, st);
+      t_written = true;
+    } else if (c.dL) {  // y = L(d) x: t' = L t + (dL/dd) x
+      tg::ChainOp cd = c;
+      cd.L = c.dL;
+      launch_op<T>(P, cd, x, tn, tg::EPI_STORE, st);
+      if (t) launch_op<T>(P, c, t, tn, tg::EPI_UPDATE, st, 1.0);
+      launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
+      t_written = true;
+    } else {
+      if (t) {
+        launch_op<T>(P, c, t, tn, tg::EPI_STORE, st);
+        t_written = true;
+      }
+      launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
+    }
+    x = xn;
+    xb ^= 1;
+    if (t_written) {
+      t = tn;
+      tb ^= 1;
+    }
+  }
+  TG_REQUIRE(t != nullptr, TG_EINVAL, "adjoint: chain without a d-dependent factor");
+  // dL/dd_s += tau <lambda_s, (dS/dd) F_s>
+  hip_check(tg::launch_dot<T>(lam, t, npts, nslab, P->d_tau, grad, st), "adjoint dot");
+
+  // mu = S^T lambda: transposed factors in reverse order; each Hadamard
+  // factor moves to the product that precedes it in the reversed chain
+  const void* y = lam;
+  int yb = 0;
+  const int n = static_cast<int>(P->chain.size());
+  for (int j = n - 1; j >= 0; --j) {
+    tg::ChainOp ct = P->chain[j];
+    ct.L = P->chain[j].LT;
+    int epi = tg::EPI_STORE;
+    ct.pm = ct.pn = ct.pb = nullptr;
+    if (j >= 1 && P->chain[j - 1].epi == tg::EPI_PHI) {
+      epi = tg::EPI_PHI;
+      ct.pm = P->chain[j - 1].pm;
+      ct.pn = P->chain[j - 1].pn;
+      ct.pb = P->chain[j - 1].pb;
+    }
+    void* out = j == 0 ? MU : xbuf[yb];
+    launch_op<T>(P, ct, y, out, epi, st);
+    y = out;
+    yb ^= 1;
+  }
+  // dL/dd_s += (tau / d_s) <mu_s, d_s M W_s>;  dL/dc_s += tau sum mu_s
+  hip_check(tg::launch_dot<T>(MU, DMW, npts, nslab, P->d_taurd, grad, st), "adjoint dot");
+  hip_check(tg::launch_dot<T>(MU, nullptr, npts, nslab, P->d_tau, grad + nslab, st), "adjoint sum");
+  // lambda += tau (d M^T mu + J^T mu)
+  tg::StencilArgs a = stencil_args(P, MU, MTMU, TG_APPLY_DIFFUSION);
+  a.coef = P->d_coefT;
+  hip_check(tg::launch_stencil<T>(a, st), "adjoint stencil");
+  tg::AdjointArgs aa{};
+  aa.state = state;
+  aa.mu = MU;
+  aa.mtmu = MTMU;
+  aa.lam = lam;
+  aa.npts = npts;
+  aa.nspecies = P->ns;
+  aa.batch = P->batch;
+  aa.reaction = P->reaction;
+  aa.tau = P->tau;
+  aa.rparams = P->d_rparams;
+  aa.wref = P->d_wref;
+  hip_check(tg::launch_adjoint_combine<T>(aa, st), "adjoint combine");
+}
+
 void step_any(tg_plan_s* P, void* state, hipStream_t st) {
   if (P->precision == TG_FP64) step_impl<double>(P, state, st);
   else step_impl<float>(P, state, st);
@@ -904,6 +1074,7 @@ int tg_plan_destroy(tg_plan p) {
   for (auto& s : p->scratch)
     if (s) (void)hipFree(s);
   if (p->dflag) (void)hipFree(p->dflag);
+  if (p->adj_ws) (void)hipFree(p->adj_ws);
   delete p;
   return TG_OK;
 }
@@ -1021,6 +1192,17 @@ int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops) {
         if (flops) flops[i] = p->chain[i].flops;
       }
     }
+    return TG_OK;
+  });
+}
+
+int tg_adjoint_step(tg_plan p, const void* state_n, void* lambda, double* grad, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state_n && lambda && grad && state_n != lambda, TG_EINVAL, "tg_adjoint_step: bad pointers");
+    TG_REQUIRE(aligned(p, state_n) && aligned(p, lambda), TG_EINVAL, "tg_adjoint_step: buffers must be aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->precision == TG_FP64) adjoint_impl<double>(p, state_n, lambda, grad, st);
+    else adjoint_impl<float>(p, state_n, lambda, grad, st);
     return TG_OK;
   });
 }

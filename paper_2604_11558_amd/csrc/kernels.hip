@@ -3,6 +3,7 @@
 #include "kernels.hpp"
 #include "stencil_dev.hpp"
 
+#include <algorithm>
 #include <cstdio>
 
 namespace tg {
@@ -33,6 +34,15 @@ template <> struct Mfma<float> {
 
 __device__ __forceinline__ double phi1_t(double x) { return x == 0.0 ? 1.0 : expm1(x) / x; }
 __device__ __forceinline__ float phi1_t(float x) { return x == 0.0f ? 1.0f : expm1f(x) / x; }
+// phi_2(x) = (e^x - 1 - x) / x^2, Taylor series near 0
+__device__ __forceinline__ double phi2_t(double x) {
+  if (fabs(x) < 1e-3) return 0.5 + x / 6.0 + x * x / 24.0 + x * x * x / 120.0;
+  return (expm1(x) - x) / (x * x);
+}
+__device__ __forceinline__ float phi2_t(float x) {
+  if (fabsf(x) < 1e-2f) return 0.5f + x / 6.0f + x * x / 24.0f + x * x * x / 120.0f;
+  return (expm1f(x) - x) / (x * x);
+}
 
 // Workgroup of 4 waves computes a TM x TN tile of C; each wave a
 // (TM/2) x (TN/2) quarter made of 16x16 MFMA blocks.  The K range is walked
@@ -118,8 +128,9 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
     }
   }
 
-  const double cs = (g.epi == EPI_PHI) ? g.cs[s] : 0.0;
-  const double pbv = (g.epi == EPI_PHI && g.pb) ? g.pb[b] : 1.0;
+  const bool phi_epi = g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC;
+  const double cs = phi_epi ? g.cs[s] : 0.0;
+  const double pbv = (phi_epi && g.pb) ? g.pb[b] : 1.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -131,12 +142,18 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
         if (row < g.M && col < g.N) {
           T v = acc[i][j][r];
           T* dst = C + static_cast<int64_t>(row) * g.ldc + col;
-          if (g.epi == EPI_PHI) {
+          if (g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC) {
             double x = cs * pbv;
             if (g.pm) x *= g.pm[row];
             if (g.pn) x *= g.pn[col];
-            v *= phi1_t(static_cast<T>(x));
-            *dst = v;
+            const T xt = static_cast<T>(x);
+            if (g.epi == EPI_PHI) {
+              *dst = v * phi1_t(xt);
+            } else if (g.epi == EPI_PHI_ACC) {
+              *dst = *dst + v * phi1_t(xt);
+            } else {  // d/dd phi_1(d c) = (x / d) (phi_1 - phi_2)(x)
+              *dst = v * static_cast<T>(x * g.rd[s]) * (phi1_t(xt) - phi2_t(xt));
+            }
           } else if (g.epi == EPI_UPDATE) {
             const T nv = *dst + static_cast<T>(g.alpha) * v;
             *dst = nv;
@@ -250,5 +267,87 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
 
 template hipError_t launch_stencil<double>(const StencilArgs&, hipStream_t);
 template hipError_t launch_stencil<float>(const StencilArgs&, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Per-slab dot products (double accumulation, block reduction in LDS).
+template <typename T>
+__global__ __launch_bounds__(256) void dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t npts,
+                                                  const double* scale, double* out) {
+  __shared__ double red[256];
+  const int s = blockIdx.y;
+  const T* as = a + static_cast<int64_t>(s) * npts;
+  const T* bs = b ? b + static_cast<int64_t>(s) * npts : nullptr;
+  double acc = 0.0;
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < npts;
+       p += static_cast<int64_t>(gridDim.x) * 256)
+    acc += static_cast<double>(as[p]) * (bs ? static_cast<double>(bs[p]) : 1.0);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out + s, red[0] * (scale ? scale[s] : 1.0));
+}
+
+template <typename T>
+hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
+                      hipStream_t s) {
+  if (npts <= 0 || nslab <= 0 || nslab > 65535) return hipErrorInvalidValue;
+  const int blocks = static_cast<int>(std::min<int64_t>((npts + 255) / 256, 64));
+  hipLaunchKernelGGL(dot_kernel<T>, dim3(blocks, nslab), dim3(256), 0, s, static_cast<const T*>(a),
+                     static_cast<const T*>(b), npts, scale, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_dot<double>(const void*, const void*, int64_t, int, const double*, double*, hipStream_t);
+template hipError_t launch_dot<float>(const void*, const void*, int64_t, int, const double*, double*, hipStream_t);
+
+// lam_s += tau (mtmu_s + sum_r J[r][s] mu_r), J = dG/dW at W = w_ref + state.
+template <typename T>
+__global__ __launch_bounds__(256) void adjoint_combine_kernel(AdjointArgs a) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int inst = blockIdx.y;
+  if (p >= a.npts) return;
+  const int ns = a.nspecies;
+  const int64_t base = static_cast<int64_t>(inst) * ns * a.npts + p;
+  const T* st = static_cast<const T*>(a.state) + base;
+  const T* mu = static_cast<const T*>(a.mu) + base;
+  const T* mt = static_cast<const T*>(a.mtmu) + base;
+  T* lam = static_cast<T*>(a.lam) + base;
+  const double* wr = a.wref + inst * ns;
+  double m[3] = {0, 0, 0}, jt[3] = {0, 0, 0};
+  for (int q = 0; q < ns && q < 3; ++q) m[q] = static_cast<double>(mu[q * a.npts]);
+  if (a.reaction == 1) {  // g_u = a - u + u^2 v,  g_v = b - u^2 v
+    const double u = wr[0] + static_cast<double>(st[0]);
+    const double v = wr[1] + static_cast<double>(st[a.npts]);
+    jt[0] = (-1.0 + 2.0 * u * v) * m[0] - 2.0 * u * v * m[1];
+    jt[1] = u * u * m[0] - u * u * m[1];
+  } else if (a.reaction == 2) {  // + kappa u w and mu (u - w) terms
+    const double* rp = a.rparams + inst * 4;
+    const double kap = rp[2], mup = rp[3];
+    const double u = wr[0] + static_cast<double>(st[0]);
+    const double v = wr[1] + static_cast<double>(st[a.npts]);
+    const double w = wr[2] + static_cast<double>(st[2 * a.npts]);
+    jt[0] = (-1.0 + 2.0 * u * v - kap * w) * m[0] - 2.0 * u * v * m[1] + mup * m[2];
+    jt[1] = u * u * m[0] - u * u * m[1];
+    jt[2] = -kap * u * m[0] - mup * m[2];
+  }
+  for (int q = 0; q < ns && q < 3; ++q) {
+    const double add = a.tau * (static_cast<double>(mt[q * a.npts]) + jt[q]);
+    lam[q * a.npts] = static_cast<T>(static_cast<double>(lam[q * a.npts]) + add);
+  }
+}
+
+template <typename T>
+hipError_t launch_adjoint_combine(const AdjointArgs& a, hipStream_t s) {
+  if (a.npts <= 0 || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid(static_cast<unsigned>((a.npts + 255) / 256), a.batch);
+  hipLaunchKernelGGL(adjoint_combine_kernel<T>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adjoint_combine<double>(const AdjointArgs&, hipStream_t);
+template hipError_t launch_adjoint_combine<float>(const AdjointArgs&, hipStream_t);
 
 }  // namespace tg

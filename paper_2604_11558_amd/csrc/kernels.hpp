@@ -7,7 +7,9 @@
 
 namespace tg {
 
-enum Epilogue : int { EPI_STORE = 0, EPI_PHI = 1, EPI_UPDATE = 2 };
+// EPI_DPHI: C = acc * d/dd phi_1(x) with x = d c (= (x / d)(phi_1 - phi_2)(x));
+// EPI_PHI_ACC: C += acc * phi_1(x).
+enum Epilogue : int { EPI_STORE = 0, EPI_PHI = 1, EPI_UPDATE = 2, EPI_DPHI = 3, EPI_PHI_ACC = 4 };
 
 // One mu-mode product over a batch of "slabs" (species x instances), as a
 // GEMM C = A * B per (slab, batch b):
@@ -37,6 +39,7 @@ struct GemmArgs {
   const double* pb;                // per batch b
   int tile;                        // 0: 64x64, 1: 32x64, 2: 64x32, 3: 32x32
   int* flag;                       // EPI_UPDATE: set to 1 if a non-finite value is written
+  const double* rd;                // per slab 1 / d_s (EPI_DPHI)
 };
 
 template <typename T>
@@ -65,5 +68,29 @@ struct StencilArgs {
 
 template <typename T>
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t s);
+
+// out[s] += scale[s] * sum_p a[s][p] * b[s][p] (b == nullptr: b = 1) over the
+// npts points of each of nslab slabs (double accumulation, one atomic add
+// per workgroup).
+template <typename T>
+hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
+                      hipStream_t s);
+
+// Adjoint combination per point, all species of an instance:
+//   lam_s += tau * (mtmu_s + sum_r dG_r/dw_s (W) mu_r)
+// with W = w_ref + state (the reaction Jacobian at step n).
+struct AdjointArgs {
+  const void* state;
+  const void* mu;     // S^T lambda (unscaled)
+  const void* mtmu;   // d_s M^T mu
+  void* lam;
+  int64_t npts;
+  int nspecies, batch, reaction;
+  double tau;
+  const double* rparams;
+  const double* wref;
+};
+template <typename T>
+hipError_t launch_adjoint_combine(const AdjointArgs& a, hipStream_t s);
 
 }  // namespace tg

@@ -37,6 +37,8 @@ struct ChainOp {
   const double* pb = nullptr;
   int tile = 0;
   double flops = 0.0;
+  const void* LT = nullptr;  // transposed factor blocks (adjoint)
+  const void* dL = nullptr;  // d/dd of the factor blocks, or null if L does not depend on d
 };
 
 // One fused launch of the step (see fused.hpp).  in / out name the
@@ -73,6 +75,11 @@ struct tg_plan_s {
   const double* d_wref = nullptr;
   const double* d_g0 = nullptr;
   const double* d_cs = nullptr;
+  const double* d_coefT = nullptr;   // transposed 1D operators (adjoint stencil)
+  const double* d_rd = nullptr;      // 1 / d per slab
+  const double* d_tau = nullptr;     // tau per slab
+  const double* d_taurd = nullptr;   // tau / d per slab
+  void* adj_ws = nullptr;            // adjoint workspace: 8 state-sized buffers
   int nmax = 0;
   int periodic_mask = 0;
   int scale_mask = 0;

@@ -70,3 +70,19 @@ class Case:
 def rel_err(a, b, mask=None):
     """max |a - b| / max |b|."""
     return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+EPS = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x2": 2.0 ** -24, "bf16x3": 2.0 ** -24}
+
+
+def adjoint_tol(case, steps, arith="fp64"):
+    """Tolerance of the discrete adjoint, relative to the largest reference entry.
+
+    A rounding of mu = tau S^T lambda is carried into lambda through
+    tau d_s M^T, whose norm tau d_max ||M||_inf reaches 1e5-1e7 on these
+    grids (the 1/r^2 and 1/sin^2 scalings near the axis and poles), so
+    per step the error is eps (1 + tau d_max ||M||_inf) times a small
+    constant; the constant 4 covers every grid measured, per step.
+    """
+    Minf = float(abs(case.oracles[0].M).sum(axis=1).max())
+    return 4.0 * steps * EPS[arith] * (1.0 + case.tau * float(case.diff.max()) * Minf)

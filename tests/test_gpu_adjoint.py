@@ -1,0 +1,134 @@
+"""The GPU discrete adjoint (tg_adjoint_step) against the FP64 gradient
+oracle, and at the full ball size against central differences of the
+device's own loss.
+
+Loss: L = 1/2 sum over grid points of (u_N - u_target)^2 (species 0).
+"""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from gpu_helpers import Case, adjoint_tol
+from oracle import adjoint, assemble
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# sizes spanning several tiles with ragged tails (the same grids as the
+# per-kernel tests)
+GRIDS = [("disk", (37, 70), 2), ("sphere", (70, 45), 2), ("ball", (20, 24, 37), 2),
+         ("cylinder", (27, 30, 19), 3)]
+
+
+def _device_adjoint(case, steps, target_layout, lam_seed_species=0):
+    plan = case.plan
+    x = case.device_state()
+    states = [x.clone()]
+    for _ in range(steps):
+        plan.step(x)
+        states.append(x.clone())
+    uN = case.full_from_device(x)[0, lam_seed_species]
+    lam_host = np.zeros(plan.state_shape)
+    lam_host[0, lam_seed_species] = uN - target_layout
+    lam = torch.from_numpy(lam_host).to(device="cuda", dtype=plan.dtype).contiguous()
+    grad = torch.zeros(2 * case.ns, dtype=torch.float64, device="cuda")
+    for k in range(steps - 1, -1, -1):
+        plan.adjoint_step(states[k], lam, grad)
+    torch.cuda.synchronize()
+    return lam.double().cpu().numpy()[0], grad.cpu().numpy(), uN
+
+
+def _oracle(case, steps, target):
+    wl = SimpleNamespace(geometry=case.geometry, reaction=case.kind, tau=case.tau, extent=case.extent,
+                         diff=tuple(case.diff[0]), params=tuple(case.params[0]), n=case.n)
+    wd = case.eq[0] if case.geometry == "cylinder" else None
+    return adjoint.loss_and_grad(wl, case.oracle_full(0), target, steps, w_dirichlet=wd)
+
+
+@pytest.mark.parametrize("geometry,n,ns", GRIDS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("tau", [5e-3, 5e-2])
+def test_adjoint_vs_oracle(geometry, n, ns, precision, tau):
+    steps = 4
+    case = Case(geometry, n, precision, tau=tau, n_species=ns, seed=3)
+    W0 = case.oracle_full(0)
+    target = W0[0] + 1e-3 * np.random.default_rng(21).random(case.n)
+    lam, grad, _ = _device_adjoint(case, steps, assemble.to_layout(target))
+    L, lam0, gd, gp = _oracle(case, steps, target)
+    lam_ref = np.stack([assemble.to_layout(x) for x in lam0])
+    e_lam = float(np.abs(lam - lam_ref).max() / np.abs(lam_ref).max())
+    scale = max(np.abs(gd).max(), np.abs(gp[:2]).max())
+    e_d = float(np.abs(grad[:ns] - gd).max() / scale)
+    e_ab = float(np.abs(grad[ns:ns + 2] - gp[:2]).max() / scale)
+    tol = adjoint_tol(case, steps, precision)
+    print(geometry, n, precision, tau, "lam %.2e  d %.2e  ab %.2e  tol %.1e" % (e_lam, e_d, e_ab, tol))
+    assert e_lam < tol and e_d < tol and e_ab < tol, (e_lam, e_d, e_ab)
+
+
+@pytest.mark.parametrize("precision", ["bf16x2", "bf16x3"])
+def test_adjoint_bf16_plan_runs_fp32(precision):
+    """Split-bf16 plans take the FP32 per-mode kernels for the adjoint."""
+    steps = 3
+    case = Case("ball", (20, 24, 37), precision, tau=2e-2, seed=3)
+    W0 = case.oracle_full(0)
+    target = W0[0] + 1e-3 * np.random.default_rng(21).random(case.n)
+    lam, grad, _ = _device_adjoint(case, steps, assemble.to_layout(target))
+    _, lam0, gd, gp = _oracle(case, steps, target)
+    lam_ref = np.stack([assemble.to_layout(x) for x in lam0])
+    tol = adjoint_tol(case, steps, "fp32")
+    e_lam = float(np.abs(lam - lam_ref).max() / np.abs(lam_ref).max())
+    e_d = float(np.abs(grad[:2] - gd).max() / np.abs(gd).max())
+    print(precision, "lam %.2e  d %.2e  tol %.1e" % (e_lam, e_d, tol))
+    assert e_lam < tol and e_d < tol
+
+
+def test_adjoint_full_size_ball_vs_central_differences():
+    """64 x 64 x 128 ball, FP64: <lambda_0, e>, dL/dd_s and dL/da against
+    central differences of the device loss (plans rebuilt at d +- h)."""
+    import paper_2604_11558_amd as tg
+    steps, tau = 2, 5e-3
+    n = (64, 64, 128)
+    case = Case("ball", n, "fp64", tau=tau, seed=5)
+    rng = np.random.default_rng(22)
+    target_layout = case.full_from_device(case.device_state())[0, 0] + 1e-3 * rng.random(
+        tuple(reversed(n)))
+    lam, grad, _ = _device_adjoint(case, steps, target_layout)
+
+    def device_loss(pert, diff=None, params=None):
+        plan = tg.Plan(case.grid, case.diff if diff is None else diff, case.kind,
+                       case.params if params is None else params, tau, "fp64",
+                       w_ref=case.plan.reference)
+        x = plan.state_from_deviation(pert)
+        for _ in range(steps):
+            plan.step(x)
+        u = x.double().cpu().numpy()[0, 0] + plan.reference[0, 0]
+        return 0.5 * float(np.sum((u - target_layout) ** 2))
+
+    def rich(f, h=1e-3):
+        """central difference with one Richardson step (error O(h^4))"""
+        c1 = (f(h) - f(-h)) / (2 * h)
+        c2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * c2 - c1) / 3
+
+    e = rng.standard_normal(case.pert.shape)
+    fd = rich(lambda t: device_loss(case.pert + t * e))
+    an = float(np.sum(lam * e[0]))
+    print("ic", fd, an)
+    assert abs(fd - an) < 1e-7 * abs(an)
+    for s in range(2):
+        def f_d(t, s=s):
+            d = case.diff.copy()
+            d[0, s] += t
+            return device_loss(case.pert, diff=d)
+        fd = rich(f_d)
+        print("d", s, fd, grad[s])
+        assert abs(fd - grad[s]) < 1e-6 * abs(grad[s]) + 1e-12
+    for q in range(2):
+        def f_p(t, q=q):
+            p = case.params.copy()
+            p[0, q] += t
+            return device_loss(case.pert, params=p)
+        fd = rich(f_p)
+        print("p", q, fd, grad[2 + q])
+        assert abs(fd - grad[2 + q]) < 1e-6 * abs(grad[2 + q]) + 1e-12

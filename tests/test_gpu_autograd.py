@@ -1,0 +1,99 @@
+"""torch.autograd through the GPU integrator (checkpointed reverse sweep)
+against the FP64 gradient oracle."""
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from gpu_helpers import Case, adjoint_tol
+from oracle import adjoint, assemble
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _grads(case, steps, segment, target_layout, adjoint_precision="fp64"):
+    from paper_2604_11558_amd.autograd import integrate
+    w0 = case.device_state().requires_grad_(True)
+    diff = torch.tensor(case.diff, dtype=torch.float64, requires_grad=True)
+    ab = torch.tensor(case.params[:, :2], dtype=torch.float64, requires_grad=True)
+    extra = case.params[:, 2:] if case.params.shape[1] > 2 else None
+    out = integrate(w0, case.grid, diff, ab, case.tau, steps, reaction=case.kind, extra_params=extra,
+                    w_ref=case.plan.reference, precision=case.plan.precision, segment=segment,
+                    adjoint_precision=adjoint_precision)
+    u = out[0, 0].double() + float(case.plan.reference[0, 0])
+    tgt = torch.from_numpy(target_layout).to(u.device)
+    loss = 0.5 * ((u - tgt) ** 2).sum()
+    L = loss.item()
+    loss.backward()
+    return (L, w0.grad.double().cpu().numpy()[0], diff.grad.numpy()[0].copy(),
+            ab.grad.numpy()[0].copy())
+
+
+def _oracle(case, steps, target):
+    wl = SimpleNamespace(geometry=case.geometry, reaction=case.kind, tau=case.tau, extent=case.extent,
+                         diff=tuple(case.diff[0]), params=tuple(case.params[0]), n=case.n)
+    wd = case.eq[0] if case.geometry == "cylinder" else None
+    L0, lam0, gd, gp = adjoint.loss_and_grad(wl, case.oracle_full(0), target, steps, w_dirichlet=wd)
+    return L0, np.stack([assemble.to_layout(x) for x in lam0]), gd, gp[:2]
+
+
+def _errors(got, ref):
+    L, g_w, g_d, g_ab = got
+    L0, lam_ref, gd, gab = ref
+    scale = max(np.abs(gd).max(), np.abs(gab).max())
+    return (abs(L - L0) / L0, float(np.abs(g_w - lam_ref).max() / np.abs(lam_ref).max()),
+            float(np.abs(g_d - gd).max() / scale), float(np.abs(g_ab - gab).max() / scale))
+
+
+@pytest.mark.parametrize("geometry,n,ns", [("disk", (37, 70), 2), ("ball", (20, 24, 37), 2),
+                                           ("cylinder", (27, 30, 19), 3)])
+def test_autograd_matches_oracle(geometry, n, ns):
+    steps = 7
+    case = Case(geometry, n, "fp64", tau=2e-2, n_species=ns, seed=4)
+    target = case.oracle_full(0)[0] + 1e-3 * np.random.default_rng(23).random(case.n)
+    errs = _errors(_grads(case, steps, 3, assemble.to_layout(target)), _oracle(case, steps, target))
+    tol = adjoint_tol(case, steps, "fp64")
+    print(geometry, "L %.1e lam %.1e d %.1e ab %.1e tol %.1e" % (errs + (tol,)))
+    # L = 1/2 |r|^2, r = u - target: an error du of the state (the forward
+    # parity bound, 1e-12 relative to max |u|) moves L by at most
+    # 2 |du| / rms(r) relative
+    L0 = _oracle(case, steps, target)[0]
+    rms = np.sqrt(2.0 * L0 / np.prod(n))
+    u_max = float(np.abs(case.oracle_run(steps)[0, 0]).max())
+    assert errs[0] < 2.0 * 1e-12 * u_max / rms
+    assert max(errs[1:]) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_autograd_low_precision_forward_fp64_adjoint(precision):
+    """FP32-storage forward, adjoint on an FP64 plan: the gradient is that of
+    the lower-precision trajectory, within the forward's own rounding."""
+    steps = 7
+    case = Case("disk", (37, 70), precision, tau=2e-2, seed=4)
+    target = case.oracle_full(0)[0] + 1e-3 * np.random.default_rng(23).random(case.n)
+    ref = _oracle(case, steps, target)
+    errs = _errors(_grads(case, steps, 3, assemble.to_layout(target)), ref)
+    same = _errors(_grads(case, steps, 3, assemble.to_layout(target), "same"), ref)
+    # the lower-precision trajectory differs from the FP64 one by the forward
+    # parity bound (2e-6 relative to max |u|, i.e. ~4e-3 of the residual
+    # r = u - target of size ~5e-4); lambda_N = r inherits that, and the
+    # FP64 adjoint adds nothing comparable (measured ~1e-6)
+    tol = 2e-6 / 5e-4
+    print(precision, "fp64 adjoint: L %.1e lam %.1e d %.1e ab %.1e" % errs,
+          "| same: L %.1e lam %.1e d %.1e ab %.1e" % same, "tol %.1e" % tol)
+    assert max(errs[1:]) < tol
+
+
+def test_checkpoint_segments_agree():
+    """sqrt(T) checkpointing (ragged last segment), one segment per step and
+    a single segment give the same gradients."""
+    steps = 10
+    case = Case("sphere", (70, 45), "fp64", tau=1e-2, seed=6)
+    target = case.full_from_device(case.device_state())[0, 0] + 1e-3 * np.random.default_rng(24).random(
+        tuple(reversed(case.n)))
+    ref = _grads(case, steps, steps, target)
+    for seg in (1, 3, 0):
+        got = _grads(case, steps, seg, target)
+        for a, b in zip(got[1:], ref[1:]):
+            assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
