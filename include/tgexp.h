@@ -186,6 +186,41 @@ int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops);
  * update is replaced by a store. */
 int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream);
 
+/* ---- batching ----------------------------------------------------------
+ * Grouped run (not in the paper; it batches many instances of the problem
+ * of Section 2, e.g. parameter sweeps on grids of different sizes).
+ * plans[0 .. n_plans), 1 <= n_plans <= 4, each with its own distinct state
+ * (device, plan layout, updated in place): n_steps steps of every plan.
+ * When all plans share the precision (FP64 or FP32), the route (0 or 2)
+ * and the kinds of their fused launches, launch k of a step covers the
+ * tiles of every plan in ONE persistent launch (grid = occupancy x CUs,
+ * tiles remapped so each XCD walks a contiguous range); otherwise the
+ * plans' launches follow each other.  Steps are replayed from a graph
+ * captured on first use per (plans, configurations, states) and kept by
+ * plans[0] until it is destroyed.  Synchronises the stream at the end;
+ * TG_ENONFINITE if any plan produced a non-finite value. */
+int tg_group_run(const tg_plan* plans, int32_t n_plans, void* const* states, int64_t n_steps,
+                 void* stream);
+/* For the same arguments: whether the launches are grouped (1) or per
+ * plan (0), and the kernel launches per step.  Builds the group if needed. */
+int tg_group_info(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t* grouped,
+                  int32_t* launches_per_step);
+
+/* ---- autotuning ----------------------------------------------------------
+ * Times `iters` steps (after 2 warm-up steps) of each candidate launch
+ * configuration on a private copy of `state` (device, plan layout; not
+ * modified) and keeps the fastest: the route (0, 2, and 1 except for
+ * split-bf16 plans) and, per fused launch, the tile width (16 / 32 / 64
+ * columns for strided launches that do not cover whole planes, 16 / 32
+ * rows for first-mode launches), by coordinate descent.  Every candidate
+ * computes the same step.  *best_us: time per step of the choice.
+ * Allocates one state-sized buffer for the duration of the call;
+ * synchronous.  Captured graphs of the plan are dropped. */
+int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, double* best_us);
+/* Tile width of each fused launch (columns for strided launches, rows for
+ * first-mode launches); *n_ops = number of fused launches. */
+int tg_plan_tiles(tg_plan p, int32_t* n_ops, int32_t* tiles);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,10 @@ _SIGNATURES = {
     "tg_plan_set_route": (ctypes.c_int, [_p, _c_int]),
     "tg_adjoint_step": (ctypes.c_int, [_p, _p, _p, _p, _p]),
     "tg_plan_route": (ctypes.c_int, [_p, _pi]),
+    "tg_group_run": (ctypes.c_int, [ctypes.POINTER(_p), _c_int, ctypes.POINTER(_p), _c_i64, _p]),
+    "tg_group_info": (ctypes.c_int, [ctypes.POINTER(_p), _c_int, ctypes.POINTER(_p), _pi, _pi]),
+    "tg_plan_autotune": (ctypes.c_int, [_p, _p, _c_int, _p, _pd]),
+    "tg_plan_tiles": (ctypes.c_int, [_p, _pi, _pi]),
 }
 
 _lib = None
@@ -270,5 +274,44 @@ class Plan:
         self._check_tensor(out)
         _check(lib().tg_apply_split_phi1(self._h, x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
 
+    def tiles(self):
+        """Tile width of each fused launch (columns / rows)."""
+        n = ctypes.c_int32()
+        t = (ctypes.c_int32 * 16)()
+        _check(lib().tg_plan_tiles(self._h, ctypes.byref(n), t))
+        return [t[i] for i in range(n.value)]
 
-__all__ = ["Grid", "Plan", "TGError", "lib", "GEOMETRY", "PRECISION", "REACTION"]
+    def autotune(self, state, iters: int = 20, stream=None) -> dict:
+        """Time the launch configurations on a copy of ``state``; keep the fastest."""
+        self._check_tensor(state)
+        best = ctypes.c_double()
+        _check(lib().tg_plan_autotune(self._h, state.data_ptr(), int(iters), _stream_ptr(stream),
+                                      ctypes.byref(best)))
+        return {"route": self.route, "tiles": self.tiles(), "us_per_step": best.value}
+
+
+def _group_args(plans, states):
+    if len(plans) != len(states):
+        raise ValueError("one state per plan")
+    for p, s in zip(plans, states):
+        p._check_tensor(s)
+    hp = (_p * len(plans))(*[p._h.value if isinstance(p._h, _p) else p._h for p in plans])
+    hs = (_p * len(states))(*[s.data_ptr() for s in states])
+    return hp, hs
+
+
+def group_run(plans, states, n_steps: int, stream=None):
+    """``n_steps`` steps of every plan; fused launches shared across plans when possible."""
+    hp, hs = _group_args(plans, states)
+    _check(lib().tg_group_run(hp, len(plans), hs, int(n_steps), _stream_ptr(stream)))
+
+
+def group_info(plans, states) -> dict:
+    hp, hs = _group_args(plans, states)
+    g, n = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().tg_group_info(hp, len(plans), hs, ctypes.byref(g), ctypes.byref(n)))
+    return {"grouped": bool(g.value), "launches_per_step": n.value}
+
+
+__all__ = ["Grid", "Plan", "TGError", "lib", "group_run", "group_info", "GEOMETRY", "PRECISION",
+           "REACTION"]

@@ -1,6 +1,9 @@
 // C interface: grids, plans (FP64 factor precompute + upload) and the step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -779,38 +782,63 @@ tg::StencilArgs stencil_args(const tg_plan_s* P, const void* W, void* F, int wha
   return a;
 }
 
-// Launch one fused op.  src: input tile data (or, for the stencil op, the
-// state W it is computed from); dst: output buffer, or the state / target
-// of the final product; update: add tau * result to dst instead of storing.
+// Concrete arguments of one fused op.  src: input tile data (or, for the
+// stencil op, the state W it is computed from); dst: output buffer, or the
+// state / target of the final product; update: add tau * result to dst
+// instead of storing.
+tg::StridedArgs strided_args_for(const tg_plan_s* P, const tg::FusedOp& op, const void* src, void* dst,
+                                 bool update, bool from_state) {
+  tg::StridedArgs a = op.sa;
+  if (!from_state) a.stencil = 0;
+  if (a.stencil) {
+    a.st = stencil_args(P, src, nullptr, TG_APPLY_F);
+    a.X = nullptr;
+  } else {
+    a.X = src;
+  }
+  if (a.plane) {
+    a.W = dst;
+    a.Y = nullptr;
+    a.update = update ? 1 : 0;
+  } else {
+    a.Y = dst;
+  }
+  return a;
+}
+
+tg::FirstArgs first_args_for(const tg::FusedOp& op, const void* src, void* dst, bool update) {
+  tg::FirstArgs a = op.fa;
+  a.X = src;
+  a.Y = dst;
+  a.update = update ? 1 : 0;
+  return a;
+}
+
 template <typename T>
 void launch_fused(const tg_plan_s* P, const tg::FusedOp& op, const void* src, void* dst, bool update,
                   bool from_state, hipStream_t st) {
+  const int nt = bf16_terms(P->precision);
   if (op.kind == 0) {
-    tg::StridedArgs a = op.sa;
-    if (!from_state) a.stencil = 0;
-    if (a.stencil) {
-      a.st = stencil_args(P, src, nullptr, TG_APPLY_F);
-      a.X = nullptr;
-    } else {
-      a.X = src;
-    }
-    if (a.plane) {
-      a.W = dst;
-      a.Y = nullptr;
-      a.update = update ? 1 : 0;
-    } else {
-      a.Y = dst;
-    }
-    const int nt = bf16_terms(P->precision);
+    const tg::StridedArgs a = strided_args_for(P, op, src, dst, update, from_state);
     hip_check(nt ? tg::launch_strided_bf16(nt, a, st) : tg::launch_strided<T>(a, st), "fused strided launch");
   } else {
-    tg::FirstArgs a = op.fa;
-    a.X = src;
-    a.Y = dst;
-    a.update = update ? 1 : 0;
-    const int nt = bf16_terms(P->precision);
+    const tg::FirstArgs a = first_args_for(op, src, dst, update);
     hip_check(nt ? tg::launch_first_bf16(nt, a, st) : tg::launch_first<T>(a, st), "fused first-mode launch");
   }
+}
+
+// in / out buffers of fused op i of a step on `state` (route 0 or 2)
+struct FusedIO {
+  const void* in;
+  void* out;
+  bool update;
+  bool from_state;
+};
+FusedIO fused_io(const tg_plan_s* P, size_t i, void* state, int route) {
+  const auto& op = P->fused[i];
+  const void* src = route == 0 ? state : P->scratch[1];
+  const bool last = i + 1 == P->fused.size();
+  return FusedIO{op.in < 0 ? src : P->scratch[op.in], last ? state : P->scratch[op.out], last, route == 0};
 }
 
 // Run the fused chain: the first op reads `src` (the state when it carries
@@ -1004,6 +1032,198 @@ hipGraphExec_t step_graph(tg_plan_s* P, void* state, int steps) {
   return ex;
 }
 
+// Device buffers are read and written as 4-element vectors.
+bool aligned(const tg_plan_s* p, const void* ptr) {
+  return reinterpret_cast<uintptr_t>(ptr) % (4u * static_cast<unsigned>(p->esize)) == 0;
+}
+
+void drop_graphs(tg_plan_s* P) {
+  for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+  P->graphs.clear();
+  ++P->version;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Grouped runs: several plans (e.g. batches on different grids) stepped
+// together.  With equal precision (FP64 or FP32), route and fused-op
+// structure, fused op k of every member runs in ONE persistent launch
+// (tg::launch_*_group); otherwise each member's launches follow each other.
+// Either way, steps are replayed from one captured graph.
+struct tg_group_s {
+  std::vector<tg_plan_s*> plans;
+  std::vector<void*> states;
+  bool grouped = false;
+  int route = 0;
+  std::vector<int> kind;                  // per fused op
+  std::vector<tg::GroupLaunch> launch;    // per fused op
+  std::vector<size_t> offset;             // byte offset of op k's group in dev
+  void* dev = nullptr;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t capture = nullptr;
+  ~tg_group_s() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (capture) (void)hipStreamDestroy(capture);
+    if (dev) (void)hipFree(dev);
+  }
+  int launches_per_step() const {
+    if (!grouped) {
+      int n = 0;
+      for (auto* P : plans) n += active_route(P) == 1 ? static_cast<int>(P->chain.size()) + 1
+                                                       : static_cast<int>(P->fused.size()) + (active_route(P) == 2);
+      return n;
+    }
+    return static_cast<int>(kind.size()) + (route == 2 ? static_cast<int>(plans.size()) : 0);
+  }
+};
+
+namespace {
+
+template <typename T>
+bool build_group_launches(tg_group_s* G) {
+  const size_t nops = G->plans[0]->fused.size();
+  std::vector<tg::StridedGroup> sg(nops);
+  std::vector<tg::FirstGroup> fg(nops);
+  G->kind.assign(nops, 0);
+  G->launch.assign(nops, tg::GroupLaunch{});
+  const int n = static_cast<int>(G->plans.size());
+  for (size_t k = 0; k < nops; ++k) {
+    G->kind[k] = G->plans[0]->fused[k].kind;
+    if (G->kind[k] == 0) {
+      tg::StridedGroup& g = sg[k];
+      g = tg::StridedGroup{};
+      g.map.n = n;
+      bool wide = false;
+      for (int q = 0; q < n; ++q) {
+        const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->route);
+        g.a[q] = strided_args_for(G->plans[q], G->plans[q]->fused[k], io.in, io.out, io.update, io.from_state);
+        wide |= g.a[q].tn % 32 == 0;
+      }
+      // one variant for all members: 32-wide (or wider) column tiles
+      if (wide)
+        for (int q = 0; q < n; ++q)
+          if (g.a[q].tn == 16) g.a[q].tn = 32;
+      if (tg::plan_strided_group<T>(g, G->launch[k]) != hipSuccess) return false;
+    } else {
+      tg::FirstGroup& g = fg[k];
+      g = tg::FirstGroup{};
+      g.map.n = n;
+      int tm = 16;
+      for (int q = 0; q < n; ++q) {
+        const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->route);
+        g.a[q] = first_args_for(G->plans[q]->fused[k], io.in, io.out, io.update);
+        tm = std::max(tm, g.a[q].tm);
+      }
+      for (int q = 0; q < n; ++q) g.a[q].tm = tm;
+      if (tg::plan_first_group<T>(g, G->launch[k]) != hipSuccess) return false;
+    }
+  }
+  // one device block with every op's group descriptor
+  size_t bytes = 0;
+  G->offset.assign(nops, 0);
+  for (size_t k = 0; k < nops; ++k) {
+    G->offset[k] = bytes;
+    bytes += ((G->kind[k] == 0 ? sizeof(tg::StridedGroup) : sizeof(tg::FirstGroup)) + 255) / 256 * 256;
+  }
+  std::vector<unsigned char> host(bytes, 0);
+  for (size_t k = 0; k < nops; ++k) {
+    if (G->kind[k] == 0) std::memcpy(host.data() + G->offset[k], &sg[k], sizeof(tg::StridedGroup));
+    else std::memcpy(host.data() + G->offset[k], &fg[k], sizeof(tg::FirstGroup));
+  }
+  hip_check(hipMalloc(&G->dev, bytes), "hipMalloc(group)");
+  hip_check(hipMemcpy(G->dev, host.data(), bytes, hipMemcpyHostToDevice), "group upload");
+  return true;
+}
+
+bool groupable(const std::vector<tg_plan_s*>& plans) {
+  const tg_plan_s* P0 = plans[0];
+  if (bf16_terms(P0->precision) || !use_fused(P0)) return false;
+  for (const auto* P : plans) {
+    if (P->precision != P0->precision || active_route(P) != active_route(P0)) return false;
+    if (P->fused.size() != P0->fused.size()) return false;
+    for (size_t k = 0; k < P->fused.size(); ++k)
+      if (P->fused[k].kind != P0->fused[k].kind) return false;
+  }
+  return true;
+}
+
+template <typename T>
+void group_step(tg_group_s* G, hipStream_t st) {
+  if (!G->grouped) {
+    for (size_t q = 0; q < G->plans.size(); ++q) step_any(G->plans[q], G->states[q], st);
+    return;
+  }
+  if (G->route == 2)
+    for (size_t q = 0; q < G->plans.size(); ++q)
+      launch_stencil_stage<T>(G->plans[q], G->states[q], G->plans[q]->scratch[1], TG_APPLY_F, st);
+  for (size_t k = 0; k < G->kind.size(); ++k) {
+    const void* d = static_cast<char*>(G->dev) + G->offset[k];
+    if (G->kind[k] == 0)
+      hip_check(tg::launch_strided_group<T>(G->launch[k], static_cast<const tg::StridedGroup*>(d), st),
+                "grouped strided launch");
+    else
+      hip_check(tg::launch_first_group<T>(G->launch[k], static_cast<const tg::FirstGroup*>(d), st),
+                "grouped first-mode launch");
+  }
+}
+
+void group_step_any(tg_group_s* G, hipStream_t st) {
+  if (G->plans[0]->precision == TG_FP64) group_step<double>(G, st);
+  else group_step<float>(G, st);
+}
+
+tg_group_s* find_group(const tg_plan* plans, int32_t n_plans, void* const* states) {
+  TG_REQUIRE(plans && states && n_plans >= 1 && n_plans <= tg::kMaxGroup, TG_EINVAL,
+             "group: 1 to 4 plans and their states");
+  std::vector<tg_plan_s*> ps(plans, plans + n_plans);
+  std::vector<void*> ss(states, states + n_plans);
+  std::vector<uint64_t> key;
+  for (int q = 0; q < n_plans; ++q) {
+    TG_REQUIRE(ps[q] && ss[q], TG_EINVAL, "group: null plan or state");
+    TG_REQUIRE(aligned(ps[q], ss[q]), TG_EINVAL, "group: states must be aligned to 4 elements");
+    for (int r = 0; r < q; ++r) TG_REQUIRE(ss[r] != ss[q], TG_EINVAL, "group: states must be distinct");
+    key.push_back(ps[q]->serial);
+    key.push_back(ps[q]->version);
+    key.push_back(reinterpret_cast<uintptr_t>(ss[q]));
+  }
+  tg_plan_s* P0 = ps[0];
+  auto it = P0->groups.find(key);
+  if (it != P0->groups.end()) return it->second;
+  auto* G = new tg_group_s();
+  try {
+    G->plans = ps;
+    G->states = ss;
+    G->route = active_route(P0);
+    if (groupable(ps)) {
+      G->grouped = P0->precision == TG_FP64 ? build_group_launches<double>(G) : build_group_launches<float>(G);
+      if (!G->grouped && G->dev) {
+        (void)hipFree(G->dev);
+        G->dev = nullptr;
+      }
+    }
+    hip_check(hipStreamCreateWithFlags(&G->capture, hipStreamNonBlocking), "capture stream");
+    hipGraph_t graph = nullptr;
+    hip_check(hipStreamBeginCapture(G->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      for (int i = 0; i < kStepsPerGraph; ++i) group_step_any(G, G->capture);
+    } catch (...) {
+      (void)hipStreamEndCapture(G->capture, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    hip_check(hipStreamEndCapture(G->capture, &graph), "end capture");
+    hipError_t e = hipGraphInstantiate(&G->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(e, "graph instantiate");
+  } catch (...) {
+    delete G;
+    throw;
+  }
+  P0->groups[key] = G;
+  return G;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1030,6 +1250,8 @@ int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* di
     TG_REQUIRE(need_ns < 0 || n_species == need_ns, TG_EINVAL, "tg_plan_create: species count does not match reaction");
     TG_REQUIRE(n_params >= need_np && (n_params == 0 || params), TG_EINVAL, "tg_plan_create: missing reaction parameters");
     P = new tg_plan_s();
+    static std::atomic<uint64_t> next_serial{1};
+    P->serial = next_serial++;
     P->grid = *g;
     P->ns = n_species;
     P->batch = batch;
@@ -1068,6 +1290,7 @@ int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* di
 
 int tg_plan_destroy(tg_plan p) {
   if (!p) return TG_OK;
+  for (auto& kv : p->groups) delete kv.second;
   for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   if (p->dmem) (void)hipFree(p->dmem);
@@ -1096,10 +1319,6 @@ int tg_plan_reference(tg_plan p, double* w_ref) {
   });
 }
 
-// Device buffers are read and written as 4-element vectors.
-static bool aligned(const tg_plan_s* p, const void* ptr) {
-  return reinterpret_cast<uintptr_t>(ptr) % (4u * static_cast<unsigned>(p->esize)) == 0;
-}
 
 int tg_step(tg_plan p, void* state, void* stream) {
   return guarded([&] {
@@ -1160,8 +1379,7 @@ int tg_plan_set_route(tg_plan p, int32_t route) {
     TG_REQUIRE(!(route == 1 && bf16_terms(p->precision)), TG_ENOTSUP,
                "tg_plan_set_route: split-bf16 plans have no per-mode route");
     if (route != p->route) {
-      for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-      p->graphs.clear();
+      drop_graphs(p);
       p->route = route;
     }
     return TG_OK;
@@ -1232,6 +1450,166 @@ int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream) {
     }
     return TG_OK;
   });
+}
+
+int tg_group_run(const tg_plan* plans, int32_t n_plans, void* const* states, int64_t n_steps, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(n_steps >= 0, TG_EINVAL, "tg_group_run: negative step count");
+    tg_group_s* G = find_group(plans, n_plans, states);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t full = n_steps / kStepsPerGraph;
+    for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(G->graph, st), "tg_group_run: graph launch");
+    for (int64_t it = full * kStepsPerGraph; it < n_steps; ++it) group_step_any(G, st);
+    std::vector<int> flags(G->plans.size(), 0);
+    for (size_t q = 0; q < G->plans.size(); ++q)
+      hip_check(hipMemcpyAsync(&flags[q], G->plans[q]->dflag, sizeof(int), hipMemcpyDeviceToHost, st),
+                "tg_group_run: flag copy");
+    hip_check(hipStreamSynchronize(st), "tg_group_run: synchronize");
+    bool bad = false;
+    for (size_t q = 0; q < G->plans.size(); ++q)
+      if (flags[q]) {
+        hip_check(hipMemset(G->plans[q]->dflag, 0, sizeof(int)), "tg_group_run: flag reset");
+        bad = true;
+      }
+    if (bad) throw Fail(TG_ENONFINITE, "tg_group_run: non-finite value in a state");
+    return TG_OK;
+  });
+}
+
+int tg_group_info(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t* grouped,
+                  int32_t* launches_per_step) {
+  return guarded([&] {
+    tg_group_s* G = find_group(plans, n_plans, states);
+    if (grouped) *grouped = G->grouped ? 1 : 0;
+    if (launches_per_step) *launches_per_step = G->launches_per_step();
+    return TG_OK;
+  });
+}
+
+int tg_plan_tiles(tg_plan p, int32_t* n_ops, int32_t* tiles) {
+  return guarded([&] {
+    TG_REQUIRE(p && n_ops, TG_EINVAL, "tg_plan_tiles: null pointer");
+    *n_ops = static_cast<int32_t>(p->fused.size());
+    if (tiles)
+      for (size_t k = 0; k < p->fused.size(); ++k)
+        tiles[k] = p->fused[k].kind == 0 ? p->fused[k].sa.tn : p->fused[k].fa.tm;
+    return TG_OK;
+  });
+}
+
+int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, double* best_us) {
+  void* tmp = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = guarded([&] {
+    TG_REQUIRE(p && state && iters >= 1 && iters <= 10000, TG_EINVAL, "tg_plan_autotune: bad argument");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_plan_autotune: state must be aligned to 4 elements");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = static_cast<size_t>(p->state_elems) * p->esize;
+    hip_check(hipMalloc(&tmp, bytes), "hipMalloc(autotune state)");
+    hip_check(hipMemcpyAsync(tmp, state, bytes, hipMemcpyDeviceToDevice, st), "autotune copy");
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    const int nt = bf16_terms(p->precision);
+    auto lds_ok = [&](const tg::FusedOp& op) {
+      size_t b;
+      if (op.kind == 0) {
+        const auto& a = op.sa;
+        b = nt ? tg::strided_bf16_lds_bytes(nt, a.nm, a.na, a.tn, a.sandwich, a.plane)
+               : (p->precision == TG_FP64 ? tg::strided_lds_bytes<double>(a.nm, a.tn, a.sandwich, a.plane)
+                                          : tg::strided_lds_bytes<float>(a.nm, a.tn, a.sandwich, a.plane));
+      } else {
+        const auto& a = op.fa;
+        b = nt ? tg::first_bf16_lds_bytes(nt, a.nm, a.tm, a.sandwich)
+               : (p->precision == TG_FP64 ? tg::first_lds_bytes<double>(a.nm, a.tm, a.sandwich)
+                                          : tg::first_lds_bytes<float>(a.nm, a.tm, a.sandwich));
+      }
+      return b > 0 && b <= kLdsLimit;
+    };
+    // time `iters` steps of the current configuration (+inf if it cannot run)
+    auto measure = [&]() {
+      try {
+        for (int w = 0; w < 2; ++w) step_any(p, tmp, st);
+        hip_check(hipEventRecord(e0, st), "event record");
+        for (int it = 0; it < iters; ++it) step_any(p, tmp, st);
+        hip_check(hipEventRecord(e1, st), "event record");
+        hip_check(hipEventSynchronize(e1), "event sync");
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+        return 1e3 * static_cast<double>(ms) / iters;
+      } catch (const Fail&) {
+        (void)hipStreamSynchronize(st);
+        return std::numeric_limits<double>::infinity();
+      }
+    };
+    std::vector<int> routes;
+    if (p->fused_ok) routes = {0, 2};
+    if (!nt) routes.push_back(1);
+    const int saved_route = p->route;
+    double best = std::numeric_limits<double>::infinity();
+    int best_route = saved_route;
+    std::vector<int> best_tiles;
+    auto tiles_now = [&]() {
+      std::vector<int> t;
+      for (const auto& op : p->fused) t.push_back(op.kind == 0 ? op.sa.tn : op.fa.tm);
+      return t;
+    };
+    auto set_tiles = [&](const std::vector<int>& t) {
+      for (size_t k = 0; k < p->fused.size(); ++k) {
+        if (p->fused[k].kind == 0) p->fused[k].sa.tn = t[k];
+        else p->fused[k].fa.tm = t[k];
+      }
+    };
+    const std::vector<int> start_tiles = tiles_now();
+    for (int r : routes) {
+      p->route = r;
+      set_tiles(start_tiles);
+      double cur = measure();
+      if (r != 1) {
+        // coordinate descent over the fused ops' tile sizes
+        for (size_t k = 0; k < p->fused.size(); ++k) {
+          tg::FusedOp& op = p->fused[k];
+          std::vector<int> cand;
+          if (op.kind == 1) cand = {16, 32};
+          else if (op.sa.plane) cand = {op.sa.tn};  // whole planes: fixed width
+          else cand = {16, 32, 64};
+          int keep = op.kind == 0 ? op.sa.tn : op.fa.tm;
+          for (int c : cand) {
+            if (c == keep) continue;
+            const int old = keep;
+            if (op.kind == 0) op.sa.tn = c;
+            else op.fa.tm = c;
+            double t = lds_ok(op) ? measure() : std::numeric_limits<double>::infinity();
+            if (t < cur) {
+              cur = t;
+              keep = c;
+            } else {
+              if (op.kind == 0) op.sa.tn = old;
+              else op.fa.tm = old;
+            }
+          }
+        }
+      }
+      if (cur < best) {
+        best = cur;
+        best_route = r;
+        best_tiles = tiles_now();
+      }
+    }
+    p->route = best_route;
+    set_tiles(best_tiles.empty() ? start_tiles : best_tiles);
+    (void)saved_route;
+    drop_graphs(p);
+    if (best_us) *best_us = best;
+    TG_REQUIRE(std::isfinite(best), TG_EHIP, "tg_plan_autotune: no configuration ran");
+    return TG_OK;
+  });
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (tmp) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(tmp);
+  }
+  return rc;
 }
 
 }  // extern "C"

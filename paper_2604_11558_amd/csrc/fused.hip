@@ -7,6 +7,7 @@
 // time; to make that a single vector load the k index of MFMA step t in
 // lane group g is k0 + 4 g + t instead of k0 + 4 t + g (any assignment of
 // k to (step, group) is valid as long as both operands use the same one).
+#include <algorithm>
 #include <cstdio>
 
 #include "fused.hpp"
@@ -329,9 +330,9 @@ __device__ __forceinline__ void col_factors(double (&fc)[FN], const double* pn, 
 }
 
 // ---------------------------------------------------------------------------
+// One tile of a strided launch: columns bx * tn .., view row block by, slab bz.
 template <typename T, int FM, int FN, int KCH>
-__global__ __launch_bounds__(256) void strided_kernel(StridedArgs a) {
-  extern __shared__ __align__(256) unsigned char smem[];
+__device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int by, int bz, unsigned char* smem) {
   using acc_t = typename M16<T>::acc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(256) void strided_kernel(StridedArgs a) {
   const int ld = pitch_kmajor<T>(TN);
   T* sX = reinterpret_cast<T*>(smem);
   T* sT = sX + NP * ld;
-  const int a0 = blockIdx.x * TN, b = blockIdx.y, s = blockIdx.z;
+  const int a0 = bx * TN, b = by, s = bz;
   const int64_t slab = static_cast<int64_t>(nm) * na * a.nb;
   const int64_t base = static_cast<int64_t>(s) * slab + static_cast<int64_t>(b) * nm * na;
 
@@ -480,10 +481,16 @@ __global__ __launch_bounds__(256) void strided_kernel(StridedArgs a) {
   }
 }
 
-// ---------------------------------------------------------------------------
 template <typename T, int FM, int FN, int KCH>
-__global__ __launch_bounds__(256) void first_kernel(FirstArgs a) {
+__global__ __launch_bounds__(256) void strided_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
+  strided_tile<T, FM, FN, KCH>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+}
+
+// ---------------------------------------------------------------------------
+// One tile of a first-mode launch: rows bx * tm .., slab by.
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, unsigned char* smem) {
   using acc_t = typename M16<T>::acc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
@@ -492,7 +499,7 @@ __global__ __launch_bounds__(256) void first_kernel(FirstArgs a) {
   const int ld = pitch_rowvec<T>(NP);
   T* sX = reinterpret_cast<T*>(smem);
   T* sT = sX + TM * ld;
-  const int rt0 = blockIdx.x * TM, s = blockIdx.y;
+  const int rt0 = bx * TM, s = by;
   const int64_t base = static_cast<int64_t>(s) * a.rows * nm;
 
   load_tile_rows<T>(static_cast<const T*>(a.X) + base, nm, a.rows, rt0, TM, NP, sX, ld, tid);
@@ -582,6 +589,56 @@ __global__ __launch_bounds__(256) void first_kernel(FirstArgs a) {
     zero<T, FM, FN>(acc);
     mm_sA_gB<T, FM, FN, KCH>(acc, sT, ld, r0, L2, a.L2.ld, c0, NP, lane);
     finish(r0, c0, acc, yv);
+  }
+}
+
+template <typename T, int FM, int FN, int KCH>
+__global__ __launch_bounds__(256) void first_kernel(FirstArgs a) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  first_tile<T, FM, FN, KCH>(a, blockIdx.x, blockIdx.y, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped persistent launches: the tiles of up to kMaxGroup launches of the
+// same kind (e.g. the same chain op of plans on different grids) in one
+// grid.  Workgroups are dispatched round-robin over the 8 XCDs, so the grid
+// size is a multiple of 8 and tile t of the strided loop is remapped so that
+// each XCD walks a contiguous range of logical tiles (consecutive tiles
+// share a slab and its factors, which then stay in that XCD's L2).
+__device__ __forceinline__ int group_member(const GroupMap& m, int L, int& local) {
+  int q = 0;
+  while (q + 1 < m.n && L >= m.start[q + 1]) ++q;
+  local = L - m.start[q];
+  return q;
+}
+
+template <typename T, int FM, int FN, int KCH>
+__global__ __launch_bounds__(256) void strided_group_kernel(const StridedGroup* __restrict__ grp) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  const GroupMap& m = grp->map;
+  for (int t = blockIdx.x; t < m.span; t += gridDim.x) {
+    const int L = (t & 7) * m.per_xcd + (t >> 3);
+    if (L >= m.total) continue;
+    int local;
+    const int q = group_member(m, L, local);
+    const int nbx = m.nbx[q], nby = m.nby[q];
+    strided_tile<T, FM, FN, KCH>(grp->a[q], local % nbx, (local / nbx) % nby, local / (nbx * nby), smem);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
+template <typename T, int FM, int FN, int KCH>
+__global__ __launch_bounds__(256) void first_group_kernel(const FirstGroup* __restrict__ grp) {
+  extern __shared__ __align__(256) unsigned char smem[];
+  const GroupMap& m = grp->map;
+  for (int t = blockIdx.x; t < m.span; t += gridDim.x) {
+    const int L = (t & 7) * m.per_xcd + (t >> 3);
+    if (L >= m.total) continue;
+    int local;
+    const int q = group_member(m, L, local);
+    const int nbx = m.nbx[q];
+    first_tile<T, FM, FN, KCH>(grp->a[q], local % nbx, local / nbx, smem);
+    __syncthreads();
   }
 }
 
@@ -686,6 +743,152 @@ hipError_t launch_first(const FirstArgs& a, hipStream_t s) {
   if (kch == 8) return go_first<T, 2, 2, 8>(a, lds, s);
   return go_first<T, 2, 2, 0>(a, lds, s);
 }
+
+// ---------------------------------------------------------------------------
+// Grouped launches
+static int round8(int x) { return (x + 7) / 8 * 8; }
+
+template <typename K>
+static hipError_t group_grid(K kernel, size_t lds, int span, int& grid) {
+  hipError_t e = allow_lds(kernel, lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, dev = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidValue;
+  grid = std::min(round8(per_cu * cus), span);  // span is a multiple of 8
+  return hipSuccess;
+}
+
+// strided variants: 0 (2,1,4) 1 (2,2,4) 2 (2,1,8) 3 (2,2,8) 4 (4,1,0) 5 (4,2,0)
+template <typename T>
+hipError_t plan_strided_group(StridedGroup& g, GroupLaunch& L) {
+  GroupMap& m = g.map;
+  if (m.n < 1 || m.n > kMaxGroup) return hipErrorInvalidValue;
+  int kch = pick_kch(g.a[0].nm);
+  const bool fn2 = g.a[0].tn % 32 == 0;
+  for (int q = 0; q < m.n; ++q) {
+    const StridedArgs& a = g.a[q];
+    if (a.nm <= 0 || a.na <= 0 || a.nb <= 0 || a.nslab <= 0) return hipErrorInvalidValue;
+    if (a.tn != 16 && a.tn % 32 != 0) return hipErrorInvalidValue;
+    if ((a.tn % 32 == 0) != fn2) return hipErrorInvalidValue;
+    if (a.plane && a.tn < a.na) return hipErrorInvalidValue;
+    if (pick_kch(a.nm) != kch) kch = 0;
+  }
+  size_t lds = 0;
+  for (int q = 0; q < m.n; ++q) {
+    const StridedArgs& a = g.a[q];
+    const int NP = kch ? 16 * kch : round_up(a.nm, 64);
+    if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP) || (a.plane && a.P.ld < round_up(a.na, 32)))
+      return hipErrorInvalidValue;
+    const size_t b = static_cast<size_t>((a.sandwich || a.plane) ? 2 : 1) * NP * pitch_kmajor<T>(a.tn) * sizeof(T);
+    lds = std::max(lds, b);
+    m.nbx[q] = (a.na + a.tn - 1) / a.tn;
+    m.nby[q] = a.nb;
+    const int64_t tiles = static_cast<int64_t>(m.nbx[q]) * a.nb * a.nslab;
+    if (tiles > (1 << 30)) return hipErrorInvalidValue;
+  }
+  if (lds > kMaxLds) return hipErrorInvalidValue;
+  m.start[0] = 0;
+  for (int q = 0; q < m.n; ++q) m.start[q + 1] = m.start[q] + m.nbx[q] * m.nby[q] * g.a[q].nslab;
+  m.total = m.start[m.n];
+  m.per_xcd = (m.total + 7) / 8;
+  m.span = 8 * m.per_xcd;
+  L.variant = kch == 4 ? (fn2 ? 1 : 0) : kch == 8 ? (fn2 ? 3 : 2) : (fn2 ? 5 : 4);
+  L.lds = lds;
+  switch (L.variant) {
+    case 0: return group_grid(strided_group_kernel<T, 2, 1, 4>, lds, m.span, L.grid);
+    case 1: return group_grid(strided_group_kernel<T, 2, 2, 4>, lds, m.span, L.grid);
+    case 2: return group_grid(strided_group_kernel<T, 2, 1, 8>, lds, m.span, L.grid);
+    case 3: return group_grid(strided_group_kernel<T, 2, 2, 8>, lds, m.span, L.grid);
+    case 4: return group_grid(strided_group_kernel<T, 4, 1, 0>, lds, m.span, L.grid);
+    default: return group_grid(strided_group_kernel<T, 4, 2, 0>, lds, m.span, L.grid);
+  }
+}
+
+template <typename T>
+hipError_t launch_strided_group(const GroupLaunch& L, const StridedGroup* dev, hipStream_t s) {
+  if (!dev || L.grid <= 0 || L.grid % 8 != 0) return hipErrorInvalidValue;
+  const dim3 grid(L.grid), block(256);
+  switch (L.variant) {
+    case 0: hipLaunchKernelGGL((strided_group_kernel<T, 2, 1, 4>), grid, block, L.lds, s, dev); break;
+    case 1: hipLaunchKernelGGL((strided_group_kernel<T, 2, 2, 4>), grid, block, L.lds, s, dev); break;
+    case 2: hipLaunchKernelGGL((strided_group_kernel<T, 2, 1, 8>), grid, block, L.lds, s, dev); break;
+    case 3: hipLaunchKernelGGL((strided_group_kernel<T, 2, 2, 8>), grid, block, L.lds, s, dev); break;
+    case 4: hipLaunchKernelGGL((strided_group_kernel<T, 4, 1, 0>), grid, block, L.lds, s, dev); break;
+    case 5: hipLaunchKernelGGL((strided_group_kernel<T, 4, 2, 0>), grid, block, L.lds, s, dev); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// first-mode variants: 0 (1,2,4) 1 (1,2,8) 2 (1,2,0) 3 (2,2,4) 4 (2,2,8) 5 (2,2,0)
+template <typename T>
+hipError_t plan_first_group(FirstGroup& g, GroupLaunch& L) {
+  GroupMap& m = g.map;
+  if (m.n < 1 || m.n > kMaxGroup) return hipErrorInvalidValue;
+  int kch = pick_kch(g.a[0].nm);
+  const int tm = g.a[0].tm;
+  if (tm != 16 && tm != 32) return hipErrorInvalidValue;
+  for (int q = 0; q < m.n; ++q) {
+    const FirstArgs& a = g.a[q];
+    if (a.nm <= 0 || a.rows <= 0 || a.nslab <= 0 || a.tm != tm) return hipErrorInvalidValue;
+    if (pick_kch(a.nm) != kch) kch = 0;
+  }
+  size_t lds = 0;
+  for (int q = 0; q < m.n; ++q) {
+    const FirstArgs& a = g.a[q];
+    const int NP = kch ? 16 * kch : round_up(a.nm, 32);
+    if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP)) return hipErrorInvalidValue;
+    lds = std::max(lds, static_cast<size_t>(a.sandwich ? 2 : 1) * tm * pitch_rowvec<T>(NP) * sizeof(T));
+    m.nbx[q] = (a.rows + tm - 1) / tm;
+    m.nby[q] = 1;
+    if (static_cast<int64_t>(m.nbx[q]) * a.nslab > (1 << 30)) return hipErrorInvalidValue;
+  }
+  if (lds > kMaxLds) return hipErrorInvalidValue;
+  m.start[0] = 0;
+  for (int q = 0; q < m.n; ++q) m.start[q + 1] = m.start[q] + m.nbx[q] * g.a[q].nslab;
+  m.total = m.start[m.n];
+  m.per_xcd = (m.total + 7) / 8;
+  m.span = 8 * m.per_xcd;
+  L.variant = (tm == 16 ? 0 : 3) + (kch == 4 ? 0 : kch == 8 ? 1 : 2);
+  L.lds = lds;
+  switch (L.variant) {
+    case 0: return group_grid(first_group_kernel<T, 1, 2, 4>, lds, m.span, L.grid);
+    case 1: return group_grid(first_group_kernel<T, 1, 2, 8>, lds, m.span, L.grid);
+    case 2: return group_grid(first_group_kernel<T, 1, 2, 0>, lds, m.span, L.grid);
+    case 3: return group_grid(first_group_kernel<T, 2, 2, 4>, lds, m.span, L.grid);
+    case 4: return group_grid(first_group_kernel<T, 2, 2, 8>, lds, m.span, L.grid);
+    default: return group_grid(first_group_kernel<T, 2, 2, 0>, lds, m.span, L.grid);
+  }
+}
+
+template <typename T>
+hipError_t launch_first_group(const GroupLaunch& L, const FirstGroup* dev, hipStream_t s) {
+  if (!dev || L.grid <= 0 || L.grid % 8 != 0) return hipErrorInvalidValue;
+  const dim3 grid(L.grid), block(256);
+  switch (L.variant) {
+    case 0: hipLaunchKernelGGL((first_group_kernel<T, 1, 2, 4>), grid, block, L.lds, s, dev); break;
+    case 1: hipLaunchKernelGGL((first_group_kernel<T, 1, 2, 8>), grid, block, L.lds, s, dev); break;
+    case 2: hipLaunchKernelGGL((first_group_kernel<T, 1, 2, 0>), grid, block, L.lds, s, dev); break;
+    case 3: hipLaunchKernelGGL((first_group_kernel<T, 2, 2, 4>), grid, block, L.lds, s, dev); break;
+    case 4: hipLaunchKernelGGL((first_group_kernel<T, 2, 2, 8>), grid, block, L.lds, s, dev); break;
+    case 5: hipLaunchKernelGGL((first_group_kernel<T, 2, 2, 0>), grid, block, L.lds, s, dev); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t plan_strided_group<double>(StridedGroup&, GroupLaunch&);
+template hipError_t plan_strided_group<float>(StridedGroup&, GroupLaunch&);
+template hipError_t plan_first_group<double>(FirstGroup&, GroupLaunch&);
+template hipError_t plan_first_group<float>(FirstGroup&, GroupLaunch&);
+template hipError_t launch_strided_group<double>(const GroupLaunch&, const StridedGroup*, hipStream_t);
+template hipError_t launch_strided_group<float>(const GroupLaunch&, const StridedGroup*, hipStream_t);
+template hipError_t launch_first_group<double>(const GroupLaunch&, const FirstGroup*, hipStream_t);
+template hipError_t launch_first_group<float>(const GroupLaunch&, const FirstGroup*, hipStream_t);
 
 template hipError_t launch_strided<double>(const StridedArgs&, hipStream_t);
 template hipError_t launch_strided<float>(const StridedArgs&, hipStream_t);

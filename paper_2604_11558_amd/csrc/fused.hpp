@@ -71,6 +71,44 @@ struct FirstArgs {
   int* flag;
 };
 
+// Grouped persistent launch of up to kMaxGroup launches of one kind (the
+// same chain op of plans on grids of different sizes).  Member q owns the
+// logical tiles start[q] .. start[q+1]; its tile index decomposes as
+// x + nbx[q] * (y + nby[q] * z).  span = 8 * per_xcd >= total.
+constexpr int kMaxGroup = 4;
+struct GroupMap {
+  int n, total, span, per_xcd;
+  int start[kMaxGroup + 1];
+  int nbx[kMaxGroup], nby[kMaxGroup];
+};
+struct StridedGroup {
+  GroupMap map;
+  StridedArgs a[kMaxGroup];
+};
+struct FirstGroup {
+  GroupMap map;
+  FirstArgs a[kMaxGroup];
+};
+// One kernel variant, its LDS bytes and the persistent grid size.
+struct GroupLaunch {
+  int variant = -1;
+  size_t lds = 0;
+  int grid = 0;
+};
+// Host side: check the members a[0 .. map.n), fill the tile map and pick
+// one kernel variant for all of them (the runtime-K one when their
+// contraction lengths need different unrolled ones).  hipErrorInvalidValue
+// when they cannot share a launch.  Queries the current device's occupancy.
+template <typename T>
+hipError_t plan_strided_group(StridedGroup& g, GroupLaunch& L);
+template <typename T>
+hipError_t plan_first_group(FirstGroup& g, GroupLaunch& L);
+// `dev` holds a copy of the planned group in device memory.
+template <typename T>
+hipError_t launch_strided_group(const GroupLaunch& L, const StridedGroup* dev, hipStream_t s);
+template <typename T>
+hipError_t launch_first_group(const GroupLaunch& L, const FirstGroup* dev, hipStream_t s);
+
 template <typename T>
 hipError_t launch_strided(const StridedArgs& a, hipStream_t s);
 template <typename T>

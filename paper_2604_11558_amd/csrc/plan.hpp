@@ -55,6 +55,8 @@ struct FusedOp {
 
 }  // namespace tg
 
+struct tg_group_s;  // grouped runs of several plans (api.cpp)
+
 struct tg_plan_s {
   tg_grid_s grid;
   int ns = 0, batch = 0, nslab = 0;
@@ -90,4 +92,10 @@ struct tg_plan_s {
   // captured step graphs keyed by state pointer
   std::map<void*, hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;
+  // unique id, and a counter bumped whenever the launch configuration
+  // (route, tiles) changes; grouped runs are keyed on both
+  uint64_t serial = 0;
+  uint64_t version = 0;
+  // grouped runs led by this plan, keyed by (serial, version, state) of members
+  std::map<std::vector<uint64_t>, tg_group_s*> groups;
 };

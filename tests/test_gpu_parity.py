@@ -90,7 +90,7 @@ def test_steps(geometry, n, precision, route):
     ref = case.oracle_run(10)
     err = rel_err(got, ref)
     assert err < (1e-12 if precision == "fp64" else 2e-7), err
-    # relative to the deviation from equilibrium too (FP64 only: FP32 is stated in DESIGN)
+    # relative to the deviation from equilibrium too (FP64 only; FP32 is checked against the full state)
     dev_ref = ref - case.plan.reference.reshape(ref.shape[:2] + (1,) * (ref.ndim - 2))
     dev_err = np.abs(got - ref).max() / np.abs(dev_ref).max()
     assert dev_err < (1e-9 if precision == "fp64" else 1e-3), dev_err
@@ -131,7 +131,7 @@ def test_equilibrium_is_stationary():
 # split-bf16 precisions: operand representation error 2^-17 per term pair
 # (two terms) or 2^-25 (three terms), times the chain length and the
 # eigenvector conditioning; bounds below hold with a margin of about 5x
-# over the measured errors (parity table).
+# over the measured errors.
 BF16_TOL = {"bf16x2": {"split": 6e-5, "steps": 1.5e-6}, "bf16x3": {"split": 3.5e-6, "steps": 3e-8}}
 BF16_GRIDS = [("disk", (37, 70)), ("sphere", (70, 45)), ("ball", (20, 24, 37)),
               ("cylinder", (27, 30, 19)), ("ball", (64, 64, 128))]
