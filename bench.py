@@ -30,6 +30,14 @@ import workloads  # noqa: E402
 METRIC = "dof-steps/s per GPU (FP32-MFMA vs FP64) at stated rel. error vs FP64 oracle"
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}  # dense MFMA FLOP/s, MI355X
 HBM_PEAK = 8.0e12
+KERNEL_SOURCES = ("fused.hip", "fused.hpp", "stencil_dev.hpp", "kernels.hpp")
+COPY_BYTES = 256 << 20
+# HBM traffic per launch (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
+# the copy calibration), keyed "route:launch:tiles", from the rocprofv3
+# counter runs of `bench.py --profile` summarised under profiles/; valid
+# only while the kernel sources hash to TRAFFIC_DIGEST.
+TRAFFIC = None
+TRAFFIC_DIGEST = None
 
 
 def cpu_model() -> str:
@@ -62,35 +70,120 @@ def time_gpu_run(plan, x, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def time_chain_op(plan, op, x, y, reps, torch):
-    """Average duration of one chain product, HIP events on its stream."""
-    stream = torch.cuda.current_stream()
-    for _ in range(5):
-        plan.apply_chain_op(op, x, y, stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        plan.apply_chain_op(op, x, y, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e-3 / reps
-
-
-def cpu_baseline(w, pert, steps):
-    """Oracle steps on the host (set-up and one warm-up step excluded)."""
+def cpu_baseline(w, pert, budget_s):
+    """Oracle steps on the host for about ``budget_s`` seconds (set-up and
+    one warm-up step excluded; at least 3 steps)."""
     from oracle import reactions, splitee
     se = splitee.make(w)
     Ws = splitee.initial_state(w, pert)
     react = lambda U: reactions.reaction(w.reaction, U, w.params)  # noqa: E731
     wd = reactions.equilibrium(w.reaction, w.params) if w.geometry == "cylinder" else None
     Ws = se.step(Ws, react, w_dirichlet=wd)
+    n = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    while n < 3 or time.perf_counter() - t0 < budget_s:
         Ws = se.step(Ws, react, w_dirichlet=wd)
-    per_step = (time.perf_counter() - t0) / steps
-    return w.dof / per_step, per_step, splitee.stack_layout(Ws)
+        n += 1
+    per_step = (time.perf_counter() - t0) / n
+    return w.dof / per_step, per_step, n, splitee.stack_layout(Ws)
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 of the HIP sources the fused launches are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_11558_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def other_workloads(tg, torch, steps):
+    """Throughput of the other benchmark-shaped workloads (context lines)."""
+    out = {}
+    # 64 x (256 x 512) + 32 x (128 x 256) sphere instances, FP32, grouped launches
+    big, small = workloads.WORKLOADS["sphere_256x512"], workloads.WORKLOADS["sphere_128x256"]
+    prm = workloads.sphere_batch_params(big.batch + small.batch)
+    plans, states = [], []
+    for wl, rows in ((big, prm[:big.batch]), (small, prm[big.batch:])):
+        diff = np.stack([np.ones(wl.batch), rows[:, 2]], axis=1)
+        plan = tg.Plan(tg.Grid("sphere", wl.n), diff, "schnakenberg", rows[:, :2], wl.tau, "fp32", wl.batch)
+        plans.append(plan)
+        states.append(plan.state_from_deviation(workloads.batch_perturbations(wl)))
+    info = tg.group_info(plans, states)
+    tg.group_run(plans, states, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tg.group_run(plans, states, steps)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    dof = big.dof + small.dof
+    out["sphere_64x256x512_32x128x256_fp32_grouped"] = {
+        "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
+        "launches_per_step": info["launches_per_step"], "grouped": info["grouped"]}
+    del plans, states
+    torch.cuda.empty_cache()
+    # 100^3 cylinder, 3 species, split-bf16
+    wl = workloads.WORKLOADS["cylinder_100x100x100"]
+    grid = tg.Grid(wl.geometry, wl.n, wl.extent)
+    for prec in ("bf16x2", "bf16x3"):
+        plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, prec)
+        x = plan.state_from_deviation(workloads.perturbation(wl)[None])
+        plan.run(x, 16)
+        sec = time_gpu_run(plan, x, steps, 0, torch)
+        out[f"cylinder_100x100x100_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s",
+                                               "ms_per_step": sec * 1e3, "dof": wl.dof}
+        del plan, x
+    # 256 x 512 disk: FP32 forward + checkpointed reverse sweep, 400 steps
+    from paper_2604_11558_amd.autograd import integrate
+    wl = workloads.WORKLOADS["disk_256x512"]
+    grid = tg.Grid("disk", wl.n)
+    plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, "fp32")
+    x0 = plan.state_from_deviation(workloads.perturbation(wl)[None])
+    tgt = torch.from_numpy(workloads.target_pattern(wl)).to("cuda", torch.float32)
+    res = {}
+    for adj in ("fp64", "same"):
+        w0 = x0.clone().requires_grad_(True)
+        diff = torch.tensor([wl.diff], dtype=torch.float64, requires_grad=True)
+        ab = torch.tensor([wl.params], dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outx = integrate(w0, grid, diff, ab, wl.tau, wl.steps, precision="fp32",
+                         w_ref=plan.reference, adjoint_precision=adj)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * ((outx[0, 0] - tgt) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[adj] = {"forward_ms_per_step": (t1 - t0) * 1e3 / wl.steps,
+                    "gradient_ms_per_step": (t2 - t1) * 1e3 / wl.steps}
+    out["disk_256x512_gradient_400_steps"] = {
+        "checkpoint_segment": int(math.ceil(math.sqrt(wl.steps))),
+        "fp32_forward_fp64_adjoint": res["fp64"], "fp32_forward_fp32_adjoint": res["same"]}
+    return out
+
+
+def profile_mode(tg, torch, w, pert, steps, route, tiles):
+    """Direct launches of the FP32 step in a given launch configuration (for
+    rocprofv3) and a copy of known size that calibrates the HBM byte counters."""
+    grid = tg.Grid(w.geometry, w.n, w.extent)
+    plan = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, "fp32")
+    if route:
+        plan.set_route(route)
+    if tiles:
+        plan.set_tiles([int(t) for t in tiles.split(",")])
+    print(f"configuration {plan.route}:{','.join(map(str, plan.tiles()))}", flush=True)
+    x = plan.state_from_deviation(pert)
+    for _ in range(steps):
+        plan.step(x)
+    torch.cuda.synchronize()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"profiled {steps} steps of {w.name} (fp32) and 5 copies of {COPY_BYTES} bytes", flush=True)
 
 
 def main():
@@ -99,8 +192,13 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="ball_64x64x128")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the other workloads' lines")
+    ap.add_argument("--profile", action="store_true",
+                    help="only launch --steps FP32 steps and a calibration copy (for rocprofv3)")
+    ap.add_argument("--route", default="", help="--profile: launch route (default: the plan's)")
+    ap.add_argument("--tiles", default="", help="--profile: comma-separated tile widths")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -114,6 +212,9 @@ def main():
     torch.cuda.set_device(0)
     w = workloads.WORKLOADS[args.workload]
     pert = workloads.perturbation(w)
+    if args.profile:
+        profile_mode(tg, torch, w, pert, args.steps, args.route, args.tiles)
+        return
     grid = tg.Grid(w.geometry, w.n, w.extent)
 
     res = {}
@@ -123,34 +224,41 @@ def main():
         plan = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, prec)
         setup = time.perf_counter() - t0
         x = plan.state_from_deviation(pert)
-        xw = plan.state_from_deviation(pert)
-        plan.run(xw, args.warmup)  # warm-up on a separate state (graph capture, clocks)
-        torch.cuda.synchronize()
-        sec = time_gpu_run(plan, x, args.steps, 0, torch)
-        states[prec] = x.double().cpu().numpy()
-        # per-launch timing of the step's kernels (HIP events on the launch stream)
-        chain = plan.chain()
-        bufs = [x, torch.empty_like(x), torch.empty_like(x)]
-        op_times = []
-        for i in range(len(chain)):
-            src = bufs[0] if i == 0 else bufs[1 + (i - 1) % 2]
-            dst = bufs[1 + i % 2]
-            op_times.append(time_chain_op(plan, i, src, dst, 200, torch))
-        dom = int(np.argmax(op_times))
+        # launch configuration: route and tile widths chosen by the autotuner
+        tune = plan.autotune(x, iters=20)
         route = plan.route
+        # timed region: W warm-up steps, then K steps replayed from the
+        # captured graph (tg_run), synchronised on both sides
+        sec = time_gpu_run(plan, x, args.steps, args.warmup, torch)
+        states[prec] = x.double().cpu().numpy()
+        # per-launch durations: the same steps with direct launches and a HIP
+        # event on the launch stream before every launch (tg_run_timed)
+        xw = plan.state_from_deviation(pert)
+        plan.run_timed(xw, args.warmup)
+        torch.cuda.synchronize()
+        launch_us = plan.run_timed(xw, args.steps)
+        sec_direct = sum(launch_us) * 1e-6
+        chain = plan.chain()
+        # launches of a step: route 2 starts with the separate stencil launch
+        off = 1 if route == "fused_stencil_apart" else (1 if route == "generic" else 0)
+        flops = [0.0] * off + [f for _, f in chain]
+        modes = [0] * off + [m for m, _ in chain]
+        dom = int(np.argmax(launch_us))
         # the other routes for comparison
         other = {}
-        for rname in ("generic", "fused_stencil_apart"):
+        for rname in ("fused", "generic", "fused_stencil_apart"):
+            if rname == route:
+                continue
             plan.set_route(rname)
             xg = plan.state_from_deviation(pert)
             plan.run(xg, args.warmup)
             other[rname] = time_gpu_run(plan, xg, min(args.steps, 200), 0, torch)
             del xg
         plan.set_route(route)
-        res[prec] = dict(sec=sec, setup=setup, op_times=op_times, dom=dom,
-                         flops=[f for _, f in chain], modes=[m for m, _ in chain],
-                         ref=plan.reference.copy(), route=route, other=other)
-        del plan, x, xw, bufs
+        res[prec] = dict(sec=sec, sec_direct=sec_direct, setup=setup, op_times=[u * 1e-6 for u in launch_us],
+                         dom=dom, flops=flops, modes=modes, ref=plan.reference.copy(), route=route, other=other,
+                         tiles=tune["tiles"], tune_us=tune["us_per_step"])
+        del plan, x, xw
         torch.cuda.empty_cache()
 
     # split-bf16 precisions of the same step (fused route)
@@ -177,7 +285,21 @@ def main():
 
     r = res["fp32"]
     dom = r["dom"]
-    achieved = r["flops"][dom] / r["op_times"][dom]
+    state_bytes = dof * 4
+    if r["flops"][dom] > 0:  # a product launch: MFMA-bound
+        achieved = r["flops"][dom] / r["op_times"][dom]
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK["fp32"], "flops_per_launch": r["flops"][dom],
+                "kernel": f"launch {dom} of the {r['route']} route (leading mode {r['modes'][dom]})"}
+    else:  # the separate stencil launch: one read of the state, one write of F
+        achieved = 2 * state_bytes / r["op_times"][dom]
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "bytes_per_launch": 2 * state_bytes,
+                "kernel": f"launch {dom} (stencil) of the {r['route']} route"}
+    key = f"{r['route']}:{dom}:{','.join(map(str, r['tiles']))}"
+    roof["traffic"] = (TRAFFIC or {}).get(key) if TRAFFIC_DIGEST == kernel_sources_digest() else None
+    roof["avg_launch_us"] = r["op_times"][dom] * 1e6
+    roof["launch_key"] = key
     out = {
         "metric": METRIC,
         "value": v32,
@@ -203,33 +325,34 @@ def main():
         "rel_err_fp32_vs_fp64": {"after_steps": args.steps, "vs_max_state": err_32_64,
                                  "vs_max_deviation": err_32_64_dev},
         "route": res["fp32"]["route"],
+        "autotuned": {p: {"route": res[p]["route"], "tiles": res[p]["tiles"]} for p in res},
+        "ms_per_step_direct_launches_with_events": {p: res[p]["sec_direct"] * 1e3 for p in res},
         "launch_us": {p: [t * 1e6 for t in res[p]["op_times"]] for p in res},
         "ms_per_step_other_routes": {p: {k: v * 1e3 for k, v in res[p]["other"].items()} for p in res},
         "plan_setup_s": {p: res[p]["setup"] for p in res},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["fp32"], "traffic": None,
-                     "kernel": f"launch {dom} of the {r['route']} route (leading mode {r['modes'][dom]})",
-                     "flops_per_launch": r["flops"][dom],
-                     "avg_launch_us": r["op_times"][dom] * 1e6},
+        "roofline": roof,
     }
     # step-level roofline (whole chain's flops in one step vs MFMA peak)
-    step_flops = sum(r["flops"])
+    step_flops = sum(res["fp32"]["flops"])
     out["step_roofline"] = {"flops_per_step": step_flops,
                             "fp32_frac": step_flops / res["fp32"]["sec"] / PEAK["fp32"],
                             "fp64_frac": step_flops / res["fp64"]["sec"] / PEAK["fp64"]}
 
+    if not args.no_other:
+        out["other_workloads"] = other_workloads(tg, torch, min(args.steps, 100))
+
     if not args.no_cpu:
-        v_cpu, per_step, ws = cpu_baseline(w, pert, args.cpu_steps)
+        v_cpu, per_step, n_cpu, ws = cpu_baseline(w, pert, args.cpu_seconds)
         out["cpu_baseline"] = {"value": v_cpu, "unit": "dof-steps/s", "cores": blas_threads(),
                                "kind": "oracle", "host_cpu": cpu_model(),
-                               "sample": f"{args.cpu_steps} steps of {w.name} (FP64 NumPy/SciPy "
-                                         f"oracle), s/step = {per_step:.3f}"}
+                               "sample": f"{n_cpu} steps of {w.name} after one warm-up step (FP64 "
+                                         f"NumPy/SciPy oracle), s/step = {per_step:.3f}"}
         # FP32 GPU path against the oracle on the same sample
         g32 = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, "fp32")
         x = g32.state_from_deviation(pert)
-        g32.run(x, args.cpu_steps + 1)
+        g32.run(x, n_cpu + 1)
         got = x.double().cpu().numpy() + g32.reference[:, :, None, None, None]
-        out["rel_err_fp32_vs_oracle"] = {"after_steps": args.cpu_steps + 1,
+        out["rel_err_fp32_vs_oracle"] = {"after_steps": n_cpu + 1,
                                          "vs_max_state": float(np.abs(got[0] - ws).max() / np.abs(ws).max())}
     print(json.dumps(out))
 

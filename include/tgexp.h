@@ -186,6 +186,16 @@ int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops);
  * update is replaced by a store. */
 int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream);
 
+/* Benchmark hook: n_steps steps of tg_step (direct launches, no graph) with
+ * a HIP event recorded on the stream before every kernel launch and after
+ * each step's last one.  launch_us[l] (l < *n_launches <= max_launches) is
+ * the average time from the end of launch l-1 (or of the previous step) to
+ * the end of launch l: the kernel's duration plus its dispatch gap.
+ * Creates 1 + launches-per-step events per step for the duration of the
+ * call; synchronous. */
+int tg_run_timed(tg_plan p, void* state, int64_t n_steps, void* stream, int32_t max_launches,
+                 int32_t* n_launches, double* launch_us);
+
 /* ---- batching ----------------------------------------------------------
  * Grouped run (not in the paper; it batches many instances of the problem
  * of Section 2, e.g. parameter sweeps on grids of different sizes).
@@ -220,6 +230,11 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
 /* Tile width of each fused launch (columns for strided launches, rows for
  * first-mode launches); *n_ops = number of fused launches. */
 int tg_plan_tiles(tg_plan p, int32_t* n_ops, int32_t* tiles);
+/* Set the tile widths (n_ops = number of fused launches; 16 / 32 rows for
+ * first-mode launches, 16 or a multiple of 32 columns for strided ones;
+ * launches that cover whole planes keep theirs).  TG_EINVAL, nothing
+ * changed, if a width is not allowed or does not fit in LDS. */
+int tg_plan_set_tiles(tg_plan p, int32_t n_ops, const int32_t* tiles);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,8 @@ _SIGNATURES = {
     "tg_group_info": (ctypes.c_int, [ctypes.POINTER(_p), _c_int, ctypes.POINTER(_p), _pi, _pi]),
     "tg_plan_autotune": (ctypes.c_int, [_p, _p, _c_int, _p, _pd]),
     "tg_plan_tiles": (ctypes.c_int, [_p, _pi, _pi]),
+    "tg_run_timed": (ctypes.c_int, [_p, _p, _c_i64, _p, _c_int, _pi, _pd]),
+    "tg_plan_set_tiles": (ctypes.c_int, [_p, _c_int, _pi]),
 }
 
 _lib = None
@@ -226,6 +228,15 @@ class Plan:
         self._check_tensor(state)
         _check(lib().tg_run(self._h, state.data_ptr(), int(n_steps), _stream_ptr(stream)))
 
+    def run_timed(self, state, n_steps: int, stream=None):
+        """``n_steps`` direct-launch steps; average microseconds of each launch of a step."""
+        self._check_tensor(state)
+        n = ctypes.c_int32()
+        us = (ctypes.c_double * 32)()
+        _check(lib().tg_run_timed(self._h, state.data_ptr(), int(n_steps), _stream_ptr(stream), 32,
+                                  ctypes.byref(n), us))
+        return [us[i] for i in range(n.value)]
+
     def apply_operator(self, x, out, what: str = "F", stream=None):
         self._check_tensor(x)
         self._check_tensor(out)
@@ -280,6 +291,10 @@ class Plan:
         t = (ctypes.c_int32 * 16)()
         _check(lib().tg_plan_tiles(self._h, ctypes.byref(n), t))
         return [t[i] for i in range(n.value)]
+
+    def set_tiles(self, tiles):
+        t = (ctypes.c_int32 * len(tiles))(*[int(v) for v in tiles])
+        _check(lib().tg_plan_set_tiles(self._h, len(tiles), t))
 
     def autotune(self, state, iters: int = 20, stream=None) -> dict:
         """Time the launch configurations on a copy of ``state``; keep the fastest."""

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtgexp.so")
 
 ARCH = os.environ.get("TGEXP_OFFLOAD_ARCH", "gfx950")
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+COMMON = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", f"-I{os.path.join(ROOT, 'include')}"]
 SOURCES = ["hostmath.cpp", "api.cpp", "kernels.hip", "fused.hip", "fused_bf16.hip"]

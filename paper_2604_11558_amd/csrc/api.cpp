@@ -255,6 +255,19 @@ std::vector<double> reaction_at(int reaction, int ns, const double* rp, const do
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// Launch-timing hook (tg_run_timed): when set, an event is recorded on the
+// launch stream before every kernel launch of a step.
+struct LaunchEvents {
+  std::vector<hipEvent_t> ev;
+  size_t next = 0;
+};
+thread_local LaunchEvents* g_launch_events = nullptr;
+inline void mark_launch(hipStream_t st) {
+  if (!g_launch_events) return;
+  TG_REQUIRE(g_launch_events->next < g_launch_events->ev.size(), TG_EINVAL, "launch timing: too many launches");
+  hip_check(hipEventRecord(g_launch_events->ev[g_launch_events->next++], st), "event record");
+}
+
 // Pick the GEMM tile: the largest tile that still gives about two
 // workgroups per compute unit, else the smallest.
 int pick_tile(int M, int N, int64_t batches) {
@@ -585,9 +598,9 @@ void build_plan(tg_plan_s* P) {
       F.fmod = f.fmod;
       return F;
     };
-    auto strided_lds = [&](int nm, int na, int tn, int sandwich, int plane) {
+    auto strided_lds = [&](int nm, int na, int tn, int sandwich, int plane, int stencil) {
       return nterms ? tg::strided_bf16_lds_bytes(nterms, nm, na, tn, sandwich, plane)
-                    : tg::strided_lds_bytes<T>(nm, tn, sandwich, plane);
+                    : tg::strided_lds_bytes<T>(nm, tn, sandwich, plane, stencil);
     };
     auto first_lds = [&](int nm, int tm, int sandwich) {
       return nterms ? tg::first_bf16_lds_bytes(nterms, nm, tm, sandwich) : tg::first_lds_bytes<T>(nm, tm, sandwich);
@@ -647,12 +660,15 @@ void build_plan(tg_plan_s* P) {
       bool plane = f.plane != 0;
       if (plane) {
         sa.tn = (f.na + 31) / 32 * 32;
-        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 1) > kLdsLimit) plane = false;
+        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 1, f.stencil) > kLdsLimit) plane = false;
       }
       if (!plane) {
+        // 32-wide column tiles when that still gives ~512 workgroups, and
+        // 16-wide ones where the wider tile does not fit in LDS
         const int64_t wg32 = static_cast<int64_t>((f.na + 31) / 32) * f.nb * nslab;
         sa.tn = wg32 >= 512 ? 32 : 16;
-        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 0) > kLdsLimit) { ok = false; break; }
+        if (sa.tn == 32 && strided_lds(f.nm, f.na, 32, f.sandwich, 0, f.stencil) > kLdsLimit) sa.tn = 16;
+        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 0, f.stencil) > kLdsLimit) { ok = false; break; }
       }
       sa.plane = plane ? 1 : 0;
       if (plane) sa.P = mkF(f.Pf);
@@ -730,6 +746,7 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
     g.c_sstride = slab;
     g.b_kcontig = 0;
   }
+  mark_launch(st);
   hip_check(tg::launch_mode_gemm<T>(g, st), "mode product launch");
 }
 
@@ -755,6 +772,7 @@ void launch_stencil_stage(const tg_plan_s* P, const void* W, void* F, int what, 
   a.rparams = P->d_rparams;
   a.wref = P->d_wref;
   a.g0 = P->d_g0;
+  mark_launch(st);
   hip_check(tg::launch_stencil<T>(a, st), "stencil launch");
 }
 
@@ -820,9 +838,11 @@ void launch_fused(const tg_plan_s* P, const tg::FusedOp& op, const void* src, vo
   const int nt = bf16_terms(P->precision);
   if (op.kind == 0) {
     const tg::StridedArgs a = strided_args_for(P, op, src, dst, update, from_state);
+    mark_launch(st);
     hip_check(nt ? tg::launch_strided_bf16(nt, a, st) : tg::launch_strided<T>(a, st), "fused strided launch");
   } else {
     const tg::FirstArgs a = first_args_for(op, src, dst, update);
+    mark_launch(st);
     hip_check(nt ? tg::launch_first_bf16(nt, a, st) : tg::launch_first<T>(a, st), "fused first-mode launch");
   }
 }
@@ -1100,11 +1120,18 @@ bool build_group_launches(tg_group_s* G) {
         g.a[q] = strided_args_for(G->plans[q], G->plans[q]->fused[k], io.in, io.out, io.update, io.from_state);
         wide |= g.a[q].tn % 32 == 0;
       }
-      // one variant for all members: 32-wide (or wider) column tiles
+      // one variant for all members: 32-wide (or wider) column tiles, else
+      // all 16-wide (tiles that cover whole planes keep their width)
+      tg::StridedGroup g16 = g;
       if (wide)
         for (int q = 0; q < n; ++q)
           if (g.a[q].tn == 16) g.a[q].tn = 32;
-      if (tg::plan_strided_group<T>(g, G->launch[k]) != hipSuccess) return false;
+      if (tg::plan_strided_group<T>(g, G->launch[k]) != hipSuccess) {
+        for (int q = 0; q < n; ++q)
+          if (!g16.a[q].plane) g16.a[q].tn = 16;
+        if (tg::plan_strided_group<T>(g16, G->launch[k]) != hipSuccess) return false;
+        g = g16;
+      }
     } else {
       tg::FirstGroup& g = fg[k];
       g = tg::FirstGroup{};
@@ -1497,6 +1524,40 @@ int tg_plan_tiles(tg_plan p, int32_t* n_ops, int32_t* tiles) {
   });
 }
 
+int tg_plan_set_tiles(tg_plan p, int32_t n_ops, const int32_t* tiles) {
+  return guarded([&] {
+    TG_REQUIRE(p && tiles && n_ops == static_cast<int32_t>(p->fused.size()), TG_EINVAL,
+               "tg_plan_set_tiles: one tile width per fused launch");
+    const int nt = bf16_terms(p->precision);
+    for (int k = 0; k < n_ops; ++k) {
+      const auto& op = p->fused[k];
+      const int t = tiles[k];
+      if (op.kind == 1) {
+        TG_REQUIRE(t == 16 || t == 32, TG_EINVAL, "tg_plan_set_tiles: first-mode tiles are 16 or 32 rows");
+        const size_t b = nt ? tg::first_bf16_lds_bytes(nt, op.fa.nm, t, op.fa.sandwich)
+                            : (p->precision == TG_FP64 ? tg::first_lds_bytes<double>(op.fa.nm, t, op.fa.sandwich)
+                                                       : tg::first_lds_bytes<float>(op.fa.nm, t, op.fa.sandwich));
+        TG_REQUIRE(b > 0 && b <= kLdsLimit, TG_EINVAL, "tg_plan_set_tiles: tile does not fit in LDS");
+      } else {
+        const auto& a = op.sa;
+        TG_REQUIRE(t == 16 || (t > 0 && t % 32 == 0), TG_EINVAL, "tg_plan_set_tiles: 16 or a multiple of 32 columns");
+        TG_REQUIRE(!a.plane || t == a.tn, TG_EINVAL, "tg_plan_set_tiles: a plane launch keeps its width");
+        const size_t b = nt ? tg::strided_bf16_lds_bytes(nt, a.nm, a.na, t, a.sandwich, a.plane)
+                            : (p->precision == TG_FP64
+                                   ? tg::strided_lds_bytes<double>(a.nm, t, a.sandwich, a.plane, a.stencil)
+                                   : tg::strided_lds_bytes<float>(a.nm, t, a.sandwich, a.plane, a.stencil));
+        TG_REQUIRE(b > 0 && b <= kLdsLimit, TG_EINVAL, "tg_plan_set_tiles: tile does not fit in LDS");
+      }
+    }
+    for (int k = 0; k < n_ops; ++k) {
+      if (p->fused[k].kind == 1) p->fused[k].fa.tm = tiles[k];
+      else p->fused[k].sa.tn = tiles[k];
+    }
+    drop_graphs(p);
+    return TG_OK;
+  });
+}
+
 int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, double* best_us) {
   void* tmp = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1515,8 +1576,8 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
       if (op.kind == 0) {
         const auto& a = op.sa;
         b = nt ? tg::strided_bf16_lds_bytes(nt, a.nm, a.na, a.tn, a.sandwich, a.plane)
-               : (p->precision == TG_FP64 ? tg::strided_lds_bytes<double>(a.nm, a.tn, a.sandwich, a.plane)
-                                          : tg::strided_lds_bytes<float>(a.nm, a.tn, a.sandwich, a.plane));
+               : (p->precision == TG_FP64 ? tg::strided_lds_bytes<double>(a.nm, a.tn, a.sandwich, a.plane, a.stencil)
+                                          : tg::strided_lds_bytes<float>(a.nm, a.tn, a.sandwich, a.plane, a.stencil));
       } else {
         const auto& a = op.fa;
         b = nt ? tg::first_bf16_lds_bytes(nt, a.nm, a.tm, a.sandwich)
@@ -1609,6 +1670,49 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
     (void)hipDeviceSynchronize();
     (void)hipFree(tmp);
   }
+  return rc;
+}
+
+int tg_run_timed(tg_plan p, void* state, int64_t n_steps, void* stream, int32_t max_launches, int32_t* n_launches,
+                 double* launch_us) {
+  LaunchEvents le;
+  int rc = guarded([&] {
+    TG_REQUIRE(p && state && n_launches && launch_us && n_steps >= 1 && n_steps <= 100000 && max_launches >= 1,
+               TG_EINVAL, "tg_run_timed: bad argument");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_timed: state must be aligned to 4 elements");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int L = active_route(p) == 1 ? static_cast<int>(p->chain.size()) + 1
+                                       : static_cast<int>(p->fused.size()) + (active_route(p) == 2 ? 1 : 0);
+    TG_REQUIRE(L <= max_launches, TG_EINVAL, "tg_run_timed: more launches per step than max_launches");
+    le.ev.resize(static_cast<size_t>(n_steps) * (L + 1), nullptr);
+    for (auto& e : le.ev) hip_check(hipEventCreate(&e), "event create");
+    for (int64_t it = 0; it < n_steps; ++it) {
+      g_launch_events = &le;
+      try {
+        step_any(p, state, st);
+      } catch (...) {
+        g_launch_events = nullptr;
+        throw;
+      }
+      g_launch_events = nullptr;
+      hip_check(hipEventRecord(le.ev[le.next++], st), "event record");  // end of the step's last launch
+    }
+    hip_check(hipStreamSynchronize(st), "tg_run_timed: synchronize");
+    TG_REQUIRE(le.next == le.ev.size(), TG_EINVAL, "tg_run_timed: unexpected launch count");
+    std::vector<double> acc(L, 0.0);
+    for (int64_t it = 0; it < n_steps; ++it)
+      for (int l = 0; l < L; ++l) {
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, le.ev[it * (L + 1) + l], le.ev[it * (L + 1) + l + 1]), "event time");
+        acc[l] += ms;
+      }
+    *n_launches = L;
+    for (int l = 0; l < L; ++l) launch_us[l] = 1e3 * acc[l] / static_cast<double>(n_steps);
+    return TG_OK;
+  });
+  g_launch_events = nullptr;
+  for (auto& e : le.ev)
+    if (e) (void)hipEventDestroy(e);
   return rc;
 }
 

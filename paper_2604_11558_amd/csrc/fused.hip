@@ -42,6 +42,22 @@ template <> struct M16<float> {
 
 static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// q = x / d, r = x % d for 0 <= x < 2^24 and 0 < d < 2^12 (the quotient
+// estimate from the float reciprocal is off by at most one, then fixed):
+// integer division by a runtime divisor costs dozens of instructions.
+struct Div {
+  int d;
+  float inv;
+  __device__ __forceinline__ explicit Div(int dd) : d(dd), inv(1.0f / static_cast<float>(dd)) {}
+  __device__ __forceinline__ int quot(int x, int& r) const {
+    int q = static_cast<int>(static_cast<float>(x) * inv);
+    r = x - q * d;
+    if (r < 0) { --q; r += d; }
+    if (r >= d) { ++q; r -= d; }
+    return q;
+  }
+};
+
 // LDS row pitch (elements).  With w a multiple of 16, w + 4 puts the rows
 // read by lane groups 0 and 1 of a 16-wide access in different halves of
 // the 32 banks (FP32), and gives the 16-byte (FP32) / 32-byte (FP64) row
@@ -192,6 +208,75 @@ __device__ __forceinline__ void gemm_sA_gB_u(typename M16<T>::acc (&acc)[FM][FN]
   }
 }
 
+// Split forms of the unrolled products: the factor vectors of a wave's rows
+// (columns) are loaded by one call and consumed by another, so that the
+// loads of the next product can be issued while the current one runs.
+template <typename T, int FM, int KCH>
+__device__ __forceinline__ void load_rows_u(typename M16<T>::v4 (&av)[FM][KCH], const T* __restrict__ A, int lda,
+                                            int r0, int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int f = 0; f < FM; ++f) {
+    const T* arow = A + static_cast<int64_t>(r0 + 16 * f + li) * lda + 4 * g;
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) av[f][c] = *reinterpret_cast<const v4*>(arow + 16 * c);
+  }
+}
+
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void mma_rows_sB(typename M16<T>::acc (&acc)[FM][FN],
+                                            const typename M16<T>::v4 (&av)[FM][KCH], const T* sB, int ldb, int c0,
+                                            int lane) {
+  const int li = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int c = 0; c < KCH; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T* brow = sB + (16 * c + 4 * g + t) * ldb + c0 + li;
+      T b[FN];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = brow[16 * j];
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[f][j] = M16<T>::mac(av[f][c][t], b[j], acc[f][j]);
+    }
+}
+
+template <typename T, int FN, int KCH>
+__device__ __forceinline__ void load_cols_u(typename M16<T>::v4 (&bv)[FN][KCH], const T* __restrict__ B, int ldb,
+                                            int c0, int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const T* brow = B + static_cast<int64_t>(c0 + 16 * j + li) * ldb + 4 * g;
+#pragma unroll
+    for (int c = 0; c < KCH; ++c) bv[j][c] = *reinterpret_cast<const v4*>(brow + 16 * c);
+  }
+}
+
+template <typename T, int FM, int FN, int KCH>
+__device__ __forceinline__ void mma_sA_cols(typename M16<T>::acc (&acc)[FM][FN], const T* sA, int lda, int r0,
+                                            const typename M16<T>::v4 (&bv)[FN][KCH], int lane) {
+  using v4 = typename M16<T>::v4;
+  const int li = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int c = 0; c < KCH; ++c) {
+    v4 a[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+      a[f] = *reinterpret_cast<const v4*>(sA + (r0 + 16 * f + li) * lda + 16 * c + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[f][j] = M16<T>::mac(a[f][t], bv[j][c][t], acc[f][j]);
+  }
+}
+
 // Dispatch on the compile-time chunk count (KCH == 0: runtime K).
 template <typename T, int FM, int FN, int KCH>
 __device__ __forceinline__ void mm_gA_sB(typename M16<T>::acc (&acc)[FM][FN], const T* A, int lda, int r0,
@@ -237,70 +322,79 @@ __device__ __forceinline__ const T* factor_of(const Factor& F, int s) {
 // flight before the LDS stores.
 constexpr int kBatch = 8;
 
-// sX[k][c] = X[k * na + a0 + c] for k < nm, a0 + c < na, else 0 (k < NP, c < TN)
-template <typename T>
+// sX[k][c] = X[k * na + a0 + c] for k < nm, a0 + c < na, else 0 (k < NP, c < TN);
+// NT threads
+template <typename T, int NT>
 __device__ __forceinline__ void load_tile_kmajor(const T* __restrict__ X, int na, int nm, int a0, int NP,
                                                  int TN, T* sX, int ld, int tid) {
   using v4 = typename M16<T>::v4;
+  const Div dtn(TN);
   if (na % 4 == 0) {
     const int nvec = NP * TN / 4;
-    for (int v0 = 0; v0 < nvec; v0 += 256 * kBatch) {
+    for (int v0 = 0; v0 < nvec; v0 += NT * kBatch) {
       v4 r[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const int v = v0 + tid + 256 * q;
-        const int k = (4 * v) / TN, c = (4 * v) % TN;
+        const int v = v0 + tid + NT * q;
+        int c;
+        const int k = dtn.quot(4 * v, c);
         r[q] = v4{0, 0, 0, 0};
         if (v < nvec && k < nm && a0 + c < na)
           r[q] = *reinterpret_cast<const v4*>(X + static_cast<int64_t>(k) * na + a0 + c);
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const int v = v0 + tid + 256 * q;
+        const int v = v0 + tid + NT * q;
         if (v < nvec) {
-          const int k = (4 * v) / TN, c = (4 * v) % TN;
+          int c;
+          const int k = dtn.quot(4 * v, c);
           *reinterpret_cast<v4*>(sX + k * ld + c) = r[q];
         }
       }
     }
     return;
   }
-  for (int e = tid; e < NP * TN; e += 256) {
-    const int k = e / TN, c = e % TN;
+  for (int e = tid; e < NP * TN; e += NT) {
+    int c;
+    const int k = dtn.quot(e, c);
     sX[k * ld + c] = (k < nm && a0 + c < na) ? X[static_cast<int64_t>(k) * na + a0 + c] : T(0);
   }
 }
 
 // sX[r][c] = X[(rt0 + r) * nm + c] for rt0 + r < rows, c < nm, else 0 (r < TM, c < NP)
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void load_tile_rows(const T* __restrict__ X, int nm, int rows, int rt0, int TM,
                                                int NP, T* sX, int ld, int tid) {
   using v4 = typename M16<T>::v4;
+  const Div dnp(NP);
   if (nm % 4 == 0) {
     const int nvec = TM * NP / 4;
-    for (int v0 = 0; v0 < nvec; v0 += 256 * kBatch) {
+    for (int v0 = 0; v0 < nvec; v0 += NT * kBatch) {
       v4 r[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const int v = v0 + tid + 256 * q;
-        const int rr = (4 * v) / NP, c = (4 * v) % NP;
+        const int v = v0 + tid + NT * q;
+        int c;
+        const int rr = dnp.quot(4 * v, c);
         r[q] = v4{0, 0, 0, 0};
         if (v < nvec && c < nm && rt0 + rr < rows)
           r[q] = *reinterpret_cast<const v4*>(X + static_cast<int64_t>(rt0 + rr) * nm + c);
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const int v = v0 + tid + 256 * q;
+        const int v = v0 + tid + NT * q;
         if (v < nvec) {
-          const int rr = (4 * v) / NP, c = (4 * v) % NP;
+          int c;
+          const int rr = dnp.quot(4 * v, c);
           *reinterpret_cast<v4*>(sX + rr * ld + c) = r[q];
         }
       }
     }
     return;
   }
-  for (int e = tid; e < TM * NP; e += 256) {
-    const int r = e / NP, c = e % NP;
+  for (int e = tid; e < TM * NP; e += NT) {
+    int c;
+    const int r = dnp.quot(e, c);
     sX[r * ld + c] = (c < nm && rt0 + r < rows) ? X[static_cast<int64_t>(rt0 + r) * nm + c] : T(0);
   }
 }
@@ -330,10 +424,192 @@ __device__ __forceinline__ void col_factors(double (&fc)[FN], const double* pn, 
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// F = d_sp M W + g(W) for a stencil tile, staged through LDS.
+//
+// The tile's rows k are the slowest grid coordinate (mode 3 in 3D, mode 2
+// in 2D; all nm of them are in the tile), its columns the faster ones
+// (a = i + n1 j in 3D, a = i in 2D).  The centre values of species sp are
+// loaded as a plain tile into `stage` (row neighbours come from there);
+// the other species and the column neighbours of each element are loaded
+// into registers, eight elements per thread and pass, all requests issued
+// before any is used; the 1D operator coefficients and scale factors of
+// the tile's rows and columns are staged once in LDS (`cf`).
+// elements per thread and pass: 8 for 4-wave, 4 for 8-wave workgroups
+template <int NT>
+constexpr int stencil_batch() { return NT >= 512 ? 4 : 8; }
+
+__host__ __device__ inline int stencil_coef_doubles(int NP, int TN) { return NP * 6 + TN * 9; }
+
+template <typename T, int NT>
+__device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, int sp, int a0, int NP, int TN, int nm,
+                                             int na, T* sX, T* stage, int ld, double* cf, int tid) {
+  const int ns = st.nspecies;
+  const bool three = st.ndim == 3;
+  const int n1 = st.n[0], n2 = st.n[1];
+  const int nmx = st.nmax;
+  const int64_t plane = static_cast<int64_t>(nm) * na;
+  const T* Wi = static_cast<const T*>(st.W) + static_cast<int64_t>(inst) * ns * plane;
+  const T* Ws = Wi + sp * plane;
+  const int rmode = three ? 2 : 1;          // mode whose coordinate is the row
+  const int rslot = three ? 2 : 1;          // scale slot of the row coordinate
+  const Div dtn(TN), dn1(n1);
+  const bool per0 = st.periodic_mask & 1;
+  const bool per1 = (st.periodic_mask >> 1) & 1;
+  const bool perr = (st.periodic_mask >> rmode) & 1;
+  const int total = NP * TN;
+  constexpr int kStencilBatch = stencil_batch<NT>();
+  T oth[kStencilBatch][2], c0m[kStencilBatch], c0p[kStencilBatch], c1m[kStencilBatch], c1p[kStencilBatch];
+  // requests of the other species and the column neighbours of this
+  // thread's elements e0 + tid + NT q
+  auto request = [&](int e0) {
+#pragma unroll
+    for (int q = 0; q < kStencilBatch; ++q) {
+      const int e = e0 + tid + NT * q;
+      int c;
+      const int k = dtn.quot(e, c);
+      const int aa = a0 + c;
+      oth[q][0] = oth[q][1] = c0m[q] = c0p[q] = c1m[q] = c1p[q] = T(0);
+      if (e < total && k < nm && aa < na) {
+        const int64_t p = static_cast<int64_t>(k) * na;
+        int i = aa, j = 0;
+        if (three) j = dn1.quot(aa, i);
+        const int im = i > 0 ? aa - 1 : (per0 ? aa + n1 - 1 : aa);
+        const int ip = i + 1 < n1 ? aa + 1 : (per0 ? aa - (n1 - 1) : aa);
+        c0m[q] = Ws[p + im];
+        c0p[q] = Ws[p + ip];
+        if (three) {
+          const int jm = j > 0 ? aa - n1 : (per1 ? aa + (n2 - 1) * n1 : aa);
+          const int jp = j + 1 < n2 ? aa + n1 : (per1 ? aa - (n2 - 1) * n1 : aa);
+          c1m[q] = Ws[p + jm];
+          c1p[q] = Ws[p + jp];
+        }
+        // the other species, by value (no dynamically indexed arrays)
+        if (ns > 1) oth[q][0] = Wi[(sp == 0 ? 1 : 0) * plane + p + aa];
+        if (ns > 2) oth[q][1] = Wi[(sp == 2 ? 1 : 2) * plane + p + aa];
+      }
+    }
+  };
+  request(0);
+  // LDS layout: rows [NP][6] = lo, dg, up of the row mode, row scale of modes 0..2;
+  //             cols [TN][9] = lo, dg, up of modes 0 and 1 (column modes), column scale of modes 0..2
+  double* rc = cf;
+  double* cc = cf + NP * 6;
+  for (int k = tid; k < NP; k += NT) {
+    const int kk = min(k, nm - 1);
+    const double* c = st.coef + rmode * 3 * nmx;
+    rc[k * 6 + 0] = c[kk];
+    rc[k * 6 + 1] = c[nmx + kk];
+    rc[k * 6 + 2] = c[2 * nmx + kk];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const bool on = mu < st.ndim && ((st.scale_mask >> (3 * mu + rslot)) & 1);
+      rc[k * 6 + 3 + mu] = on ? st.scale[mu * 3 * nmx + rslot * nmx + kk] : 1.0;
+    }
+  }
+  for (int c = tid; c < TN; c += NT) {
+    const int aa = min(a0 + c, na - 1);
+    int i = aa, j = 0;
+    if (three) j = dn1.quot(aa, i);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const bool col_mode = m == 0 || three;
+      const int x = m == 0 ? i : j;
+      const double* q = st.coef + m * 3 * nmx;
+      cc[c * 9 + 3 * m + 0] = col_mode ? q[x] : 0.0;
+      cc[c * 9 + 3 * m + 1] = col_mode ? q[nmx + x] : 0.0;
+      cc[c * 9 + 3 * m + 2] = col_mode ? q[2 * nmx + x] : 0.0;
+    }
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      double f = 1.0;
+      if (mu < st.ndim) {
+        const int sm = st.scale_mask >> (3 * mu);
+        const double* sc = st.scale + mu * 3 * nmx;
+        if (sm & 1) f *= sc[i];
+        if (three && (sm & 2)) f *= sc[nmx + j];
+      }
+      cc[c * 9 + 6 + mu] = f;
+    }
+  }
+  load_tile_kmajor<T, NT>(Ws, na, nm, a0, NP, TN, stage, ld, tid);
+  __syncthreads();  // staged centres and coefficients
+  const double d = st.diff[inst * ns + sp];
+  // a thread keeps one column when NT is a multiple of TN: its column
+  // coefficients then live in registers
+  const bool colfix = NT % TN == 0;
+  double cr[9];
+  if (colfix) {
+    int cfix;
+    (void)dtn.quot(tid, cfix);
+#pragma unroll
+    for (int x = 0; x < 9; ++x) cr[x] = cc[cfix * 9 + x];
+  }
+  for (int e0 = 0; e0 < total; e0 += NT * kStencilBatch) {
+    if (e0 > 0) request(e0);
+#pragma unroll
+    for (int q = 0; q < kStencilBatch; ++q) {
+      const int e = e0 + tid + NT * q;
+      if (e >= total) break;
+      int c;
+      const int k = dtn.quot(e, c);
+      const int aa = a0 + c;
+      double v = 0.0;
+      if (k < nm && aa < na) {
+        const double w0 = static_cast<double>(stage[k * ld + c]);
+        const double* r6 = rc + k * 6;
+        double c9[9];
+#pragma unroll
+        for (int x = 0; x < 9; ++x) c9[x] = colfix ? cr[x] : cc[c * 9 + x];
+        double f = 0.0;
+        if (st.what != 2) {
+          const int km = k > 0 ? k - 1 : (perr ? nm - 1 : k);
+          const int kp = k + 1 < nm ? k + 1 : (perr ? 0 : k);
+          const double wkm = static_cast<double>(stage[km * ld + c]);
+          const double wkp = static_cast<double>(stage[kp * ld + c]);
+          // row mode
+          f += r6[3 + rmode] * c9[6 + rmode] * (r6[0] * wkm + r6[1] * w0 + r6[2] * wkp);
+          // column modes
+          f += r6[3] * c9[6] * (c9[0] * static_cast<double>(c0m[q]) + c9[1] * w0 + c9[2] * static_cast<double>(c0p[q]));
+          if (three)
+            f += r6[4] * c9[7] *
+                 (c9[3] * static_cast<double>(c1m[q]) + c9[4] * w0 + c9[5] * static_cast<double>(c1p[q]));
+          f *= d;
+        }
+        if (st.what != 1 && st.reaction != 0) {
+          const double o0 = static_cast<double>(oth[q][0]), o1 = static_cast<double>(oth[q][1]);
+          const double u = sp == 0 ? w0 : o0;
+          const double vv = sp == 1 ? w0 : (sp == 0 ? o0 : o1);
+          const double w = sp == 2 ? w0 : o1;
+          double G0, G1, G2;
+          reaction3(st, inst, u, vv, w, G0, G1, G2);
+          f += sp == 0 ? G0 : (sp == 1 ? G1 : G2);
+        }
+        v = f;
+      }
+      sX[k * ld + c] = static_cast<T>(v);
+    }
+  }
+}
+
 // One tile of a strided launch: columns bx * tn .., view row block by, slab bz.
-template <typename T, int FM, int FN, int KCH>
+//
+// Latency plan (unrolled products, KCH > 0): the factor rows of a wave's
+// first sub-tile for the first product, its phi_1 argument factors and,
+// for an update, its state values are requested before the tile load; the
+// factor rows of the next product (and of the plane tail) are requested
+// right after the MFMAs of the current one, so each product finds its
+// operands in registers after the barrier.  Waves with more than one
+// sub-tile load the later ones in place.
+template <typename T, int FM, int FN, int KCH, int NW>
 __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int by, int bz, unsigned char* smem) {
+  constexpr int NT = 64 * NW;
   using acc_t = typename M16<T>::acc;
+  using v4 = typename M16<T>::v4;
+  constexpr int KR = KCH > 0 ? KCH : 1;  // register prefetch extent
+  // cross-product prefetch only where two factor register sets fit
+  // (FP64 with 128-long contractions keeps one set, loaded per product)
+  constexpr bool kPre = KCH > 0 && NW == 4 && sizeof(T) * FM * KCH * 4 <= 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int nm = a.nm, na = a.na, TN = a.tn;
@@ -345,58 +621,58 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
   const int64_t slab = static_cast<int64_t>(nm) * na * a.nb;
   const int64_t base = static_cast<int64_t>(s) * slab + static_cast<int64_t>(b) * nm * na;
 
-  // 1. data tile: rows k < NP (zero beyond nm), columns a0 .. a0 + TN
-  if (a.stencil) {
-    // The stencil launch is always the last mode (nb == 1): the column a
-    // holds the faster coordinates, the row k the slowest one.
-    const int inst = s / a.st.nspecies, sp = s % a.st.nspecies;
-    const int n1 = a.st.n[0];
-    const bool three = a.st.ndim == 3;
-#pragma unroll 4
-    for (int e = tid; e < NP * TN; e += 256) {
-      const int k = e / TN, c = e % TN;
-      const int aa = a0 + c;
-      double v = 0.0;
-      if (k < nm && aa < na) {
-        const int i = three ? aa % n1 : aa;
-        const int j = three ? aa / n1 : k;
-        const int kk = three ? k : 0;
-        v = stencil_point_ijk<T>(a.st, inst, sp, k * na + aa, i, j, kk);
-      }
-      sX[k * ld + c] = static_cast<T>(v);
-    }
-  } else {
-    load_tile_kmajor<T>(static_cast<const T*>(a.X) + base, na, nm, a0, NP, TN, sX, ld, tid);
-  }
-  __syncthreads();
-
   const int nrt = NP / (16 * FM), nct = TN / (16 * FN);
   const int nsub = nrt * nct;
   const bool keep = a.sandwich || a.plane;  // result of the first product stays in LDS
   const T* L1 = factor_of<T>(a.L1, s);
+  const T* L2 = a.sandwich ? factor_of<T>(a.L2, s) : nullptr;
+  const T* P = a.plane ? factor_of<T>(a.P, s) : nullptr;
   T* Y = static_cast<T*>(a.Y) + base;
+  T* W = a.plane ? static_cast<T*>(a.W) + base : nullptr;
   const double cb = a.phi ? a.ph.cs[s] * (a.ph.pb ? a.ph.pb[b] : 1.0) : 0.0;
+  const int KP = (na + 15) / 16 * 16;
+  const bool plane_u = KCH > 0 && KP == 16 * KCH;  // plane tail unrolled too
+
+  // 0. requests for this wave's first sub-tile, issued before the tile load
+  const int r00 = (wave / nct) * 16 * FM, c00 = (wave % nct) * 16 * FN;
+  v4 fv[FM][KR];
+  double fr[FM][4], fc[FN];
+  if constexpr (kPre)
+    if (wave < nsub) load_rows_u<T, FM, KCH>(fv, L1, a.L1.ld, r00, lane);
+  if (a.phi) {
+    row_factors<T, FM>(fr, a.ph.pm, r00, g, nm, 0);
+    col_factors<FN>(fc, a.ph.pn, c00, li, na - a0, a0);
+  }
+
+  // 1. data tile: rows k < NP (zero beyond nm), columns a0 .. a0 + TN
+  if (a.stencil) {
+    // The stencil launch is always the last mode (nb == 1): the column a
+    // holds the faster coordinates, the row k the slowest one.
+    double* cfs = reinterpret_cast<double*>(sT + NP * ld);
+    stencil_tile<T, NT>(a.st, s / a.st.nspecies, s % a.st.nspecies, a0, NP, TN, nm, na, sX, sT, ld, cfs, tid);
+  } else {
+    load_tile_kmajor<T, NT>(static_cast<const T*>(a.X) + base, na, nm, a0, NP, TN, sX, ld, tid);
+  }
+  __syncthreads();
 
   // 2. first product (and the phi_1 factor)
-  for (int sub = wave; sub < nsub; sub += 4) {
+  for (int sub = wave; sub < nsub; sub += NW) {
     const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
-    // phi_1 factors of this lane's elements, evaluated before the product
-    // (they do not depend on it, so they overlap the MFMA latency)
-    T ph[FM][FN][4];
-    if (a.phi) {
-      double fr[FM][4], fc[FN];
+    const bool first = sub == wave;
+    if (!first && a.phi) {
       row_factors<T, FM>(fr, a.ph.pm, r0, g, nm, 0);
       col_factors<FN>(fc, a.ph.pn, c0, li, na - a0, a0);
-#pragma unroll
-      for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) ph[f][j][r] = M16<T>::phi1(static_cast<T>(cb * fr[f][r] * fc[j]));
     }
     acc_t acc[FM][FN];
     zero<T, FM, FN>(acc);
-    mm_gA_sB<T, FM, FN, KCH>(acc, L1, a.L1.ld, r0, sX, ld, c0, NP, lane);
+    if constexpr (KCH > 0) {
+      if (!first || !kPre) load_rows_u<T, FM, KCH>(fv, L1, a.L1.ld, r0, lane);
+      mma_rows_sB<T, FM, FN, KCH>(acc, fv, sX, ld, c0, lane);
+      // next product's factor rows for this wave's first sub-tile
+      if (kPre && sub + NW >= nsub && a.sandwich) load_rows_u<T, FM, KCH>(fv, L2, a.L2.ld, r00, lane);
+    } else {
+      gemm_gA_sB<T, FM, FN>(acc, L1, a.L1.ld, r0, sX, ld, c0, NP, lane);
+    }
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -406,22 +682,50 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
           const int row = r0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
           T v = acc[f][j][r];
           const bool in = row < nm && a0 + col < na;
-          if (a.phi) v *= ph[f][j][r];
+          if (a.phi) v *= M16<T>::phi1(static_cast<T>(cb * fr[f][r] * fc[j]));
           if (keep) sT[row * ld + col] = in ? v : T(0);
           else if (in) Y[static_cast<int64_t>(row) * na + a0 + col] = v;
         }
   }
   if (!keep) return;
+
+  // requests of the plane tail for this wave's first sub-tile: the state
+  // values of the update and (without a sandwich) the factor columns
+  v4 pv[FN][KR];
+  T wv[FM][FN][4];
+  auto plane_requests = [&](int r0, int c0) {
+    if constexpr (KCH > 0)
+      if (plane_u) load_cols_u<T, FN, KCH>(pv, P, a.P.ld, c0, lane);
+    if (a.update) {
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = min(r0 + 16 * f + M16<T>::row(g, r), nm - 1);
+            const int col = min(c0 + 16 * j + li, na - 1);
+            wv[f][j][r] = W[static_cast<int64_t>(row) * na + col];
+          }
+    }
+  };
+  if (kPre && a.plane && !a.sandwich && wave < nsub) plane_requests(r00, c00);
   __syncthreads();
 
   // 3. second product of the sandwich (into LDS for the plane tail)
   if (a.sandwich) {
-    const T* L2 = factor_of<T>(a.L2, s);
-    for (int sub = wave; sub < nsub; sub += 4) {
+    for (int sub = wave; sub < nsub; sub += NW) {
       const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
+      const bool first = sub == wave;
       acc_t acc[FM][FN];
       zero<T, FM, FN>(acc);
-      mm_gA_sB<T, FM, FN, KCH>(acc, L2, a.L2.ld, r0, sT, ld, c0, NP, lane);
+      if constexpr (KCH > 0) {
+        if (!first || !kPre) load_rows_u<T, FM, KCH>(fv, L2, a.L2.ld, r0, lane);
+        mma_rows_sB<T, FM, FN, KCH>(acc, fv, sT, ld, c0, lane);
+      } else {
+        gemm_gA_sB<T, FM, FN>(acc, L2, a.L2.ld, r0, sT, ld, c0, NP, lane);
+      }
+      if (kPre && a.plane && sub + NW >= nsub) plane_requests(r00, c00);
 #pragma unroll
       for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -441,28 +745,20 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
 
   // 4. plane tail: Z[row][i'] = sum_i T[row][i] P[i'][i];  W += alpha Z
   const T* Tin = a.sandwich ? sX : sT;
-  const T* P = factor_of<T>(a.P, s);
-  T* W = static_cast<T*>(a.W) + base;
-  const int KP = (na + 15) / 16 * 16;
   const T alpha = static_cast<T>(a.alpha);
-  for (int sub = wave; sub < nsub; sub += 4) {
+  for (int sub = wave; sub < nsub; sub += NW) {
     const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
-    T wv[FM][FN][4];
-    if (a.update) {  // state values of this lane, requested before the product
-#pragma unroll
-      for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = min(r0 + 16 * f + M16<T>::row(g, r), nm - 1);
-            const int col = min(c0 + 16 * j + li, na - 1);
-            wv[f][j][r] = W[static_cast<int64_t>(row) * na + col];
-          }
-    }
+    if (sub != wave || !kPre) plane_requests(r0, c0);
     acc_t acc[FM][FN];
     zero<T, FM, FN>(acc);
-    mm_sA_gB<T, FM, FN, KCH>(acc, Tin, ld, r0, P, a.P.ld, c0, KP, lane);
+    bool done = false;
+    if constexpr (KCH > 0) {
+      if (plane_u) {
+        mma_sA_cols<T, FM, FN, KCH>(acc, Tin, ld, r0, pv, lane);
+        done = true;
+      }
+    }
+    if (!done) gemm_sA_gB<T, FM, FN>(acc, Tin, ld, r0, P, a.P.ld, c0, KP, lane);
     bool bad = false;
 #pragma unroll
     for (int f = 0; f < FM; ++f)
@@ -481,10 +777,16 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
   }
 }
 
-template <typename T, int FM, int FN, int KCH>
-__global__ __launch_bounds__(256) void strided_kernel(StridedArgs a) {
+// 8-wave FP32 workgroups are held to 128 VGPRs (4 waves per SIMD), so two
+// of them share a CU.
+template <typename T, int NW>
+constexpr int waves_per_eu() { return (NW == 8 && sizeof(T) == 4) ? 4 : 1; }
+
+template <typename T, int FM, int FN, int KCH, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, NW>())))
+void strided_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
-  strided_tile<T, FM, FN, KCH>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+  strided_tile<T, FM, FN, KCH, NW>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,7 +804,7 @@ __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, u
   const int rt0 = bx * TM, s = by;
   const int64_t base = static_cast<int64_t>(s) * a.rows * nm;
 
-  load_tile_rows<T>(static_cast<const T*>(a.X) + base, nm, a.rows, rt0, TM, NP, sX, ld, tid);
+  load_tile_rows<T, 256>(static_cast<const T*>(a.X) + base, nm, a.rows, rt0, TM, NP, sX, ld, tid);
   __syncthreads();
 
   const int nrt = TM / (16 * FM), nct = NP / (16 * FN);
@@ -612,8 +914,9 @@ __device__ __forceinline__ int group_member(const GroupMap& m, int L, int& local
   return q;
 }
 
-template <typename T, int FM, int FN, int KCH>
-__global__ __launch_bounds__(256) void strided_group_kernel(const StridedGroup* __restrict__ grp) {
+template <typename T, int FM, int FN, int KCH, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, NW>())))
+void strided_group_kernel(const StridedGroup* __restrict__ grp) {
   extern __shared__ __align__(256) unsigned char smem[];
   const GroupMap& m = grp->map;
   for (int t = blockIdx.x; t < m.span; t += gridDim.x) {
@@ -622,7 +925,7 @@ __global__ __launch_bounds__(256) void strided_group_kernel(const StridedGroup* 
     int local;
     const int q = group_member(m, L, local);
     const int nbx = m.nbx[q], nby = m.nby[q];
-    strided_tile<T, FM, FN, KCH>(grp->a[q], local % nbx, (local / nbx) % nby, local / (nbx * nby), smem);
+    strided_tile<T, FM, FN, KCH, NW>(grp->a[q], local % nbx, (local / nbx) % nby, local / (nbx * nby), smem);
     __syncthreads();  // the next tile reuses the LDS
   }
 }
@@ -660,11 +963,12 @@ static int first_np(int nm) {
 }
 
 template <typename T>
-size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane) {
+size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane, int stencil) {
   const int NP = strided_np(nm);
   const int ld = pitch_kmajor<T>(tn);
-  const int bufs = (sandwich || plane) ? 2 : 1;
-  return static_cast<size_t>(bufs) * NP * ld * sizeof(T);
+  const int bufs = (sandwich || plane || stencil) ? 2 : 1;
+  return static_cast<size_t>(bufs) * NP * ld * sizeof(T) +
+         (stencil ? sizeof(double) * stencil_coef_doubles(NP, tn) : 0);
 }
 
 template <typename T>
@@ -683,14 +987,49 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
-template <typename T, int FM, int FN, int KCH>
-static hipError_t go_strided(const StridedArgs& a, size_t lds, hipStream_t s) {
-  auto k = strided_kernel<T, FM, FN, KCH>;
-  hipError_t e = allow_lds(k, lds);
-  if (e != hipSuccess) return e;
-  dim3 grid((a.na + a.tn - 1) / a.tn, a.nb, a.nslab);
-  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);
-  return hipGetLastError();
+// Strided kernel variants (FM, FN, KCH, NW).  Contractions up to 128 use
+// the unrolled products; in FP32, with at least 8 sub-tiles a workgroup
+// runs 8 waves (more waves per SIMD to overlap the latencies of loads, LDS
+// and the phi_1 epilogue), otherwise 4.
+struct SVar {
+  int fm, fn, kch, nw;
+};
+static constexpr SVar kSVar[10] = {{2, 1, 4, 4}, {2, 2, 4, 4}, {2, 1, 8, 4}, {2, 2, 8, 4}, {4, 1, 0, 4},
+                                   {4, 2, 0, 4}, {1, 1, 4, 8}, {2, 1, 4, 8}, {1, 1, 8, 8}, {2, 1, 8, 8}};
+
+static int strided_variant(int kch, int NP, int TN, bool wide_ok) {
+  if (kch > 0 && wide_ok) {
+    const int nct1 = TN / 16;
+    const int base = kch == 4 ? 0 : 2;
+    if ((NP / 32) * nct1 >= 8) return kch == 4 ? 7 : 9;
+    if ((NP / 16) * nct1 >= 8) return kch == 4 ? 6 : 8;
+    return base + (TN % 32 == 0 ? 1 : 0);
+  }
+  if (kch > 0) return (kch == 4 ? 0 : 2) + (TN % 32 == 0 ? 1 : 0);
+  return TN % 32 == 0 ? 5 : 4;
+}
+
+static bool variant_fits(int v, int NP, int TN) {
+  const SVar& x = kSVar[v];
+  return NP % (16 * x.fm) == 0 && TN % (16 * x.fn) == 0 && (x.kch == 0 || NP == 16 * x.kch);
+}
+
+// Call f.template operator()<FM, FN, KCH, NW>() for variant v.
+template <typename F>
+static hipError_t with_svar(int v, F&& f) {
+  switch (v) {
+    case 0: return f.template operator()<2, 1, 4, 4>();
+    case 1: return f.template operator()<2, 2, 4, 4>();
+    case 2: return f.template operator()<2, 1, 8, 4>();
+    case 3: return f.template operator()<2, 2, 8, 4>();
+    case 4: return f.template operator()<4, 1, 0, 4>();
+    case 5: return f.template operator()<4, 2, 0, 4>();
+    case 6: return f.template operator()<1, 1, 4, 8>();
+    case 7: return f.template operator()<2, 1, 4, 8>();
+    case 8: return f.template operator()<1, 1, 8, 8>();
+    case 9: return f.template operator()<2, 1, 8, 8>();
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
@@ -702,17 +1041,18 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t s) {
   const int NP = strided_np(a.nm);
   if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP) || (a.plane && a.P.ld < round_up(a.na, 32)))
     return hipErrorInvalidValue;
-  const size_t lds = strided_lds_bytes<T>(a.nm, a.tn, a.sandwich, a.plane);
+  const size_t lds = strided_lds_bytes<T>(a.nm, a.tn, a.sandwich, a.plane, a.stencil);
   if (lds > kMaxLds) return hipErrorInvalidValue;
-  const bool fn2 = a.tn % 32 == 0;
-  switch (pick_kch(a.nm) * 10 + (fn2 ? 2 : 1)) {
-    case 41: return go_strided<T, 2, 1, 4>(a, lds, s);
-    case 42: return go_strided<T, 2, 2, 4>(a, lds, s);
-    case 81: return go_strided<T, 2, 1, 8>(a, lds, s);
-    case 82: return go_strided<T, 2, 2, 8>(a, lds, s);
-    case 1: return go_strided<T, 4, 1, 0>(a, lds, s);
-    default: return go_strided<T, 4, 2, 0>(a, lds, s);
-  }
+  // 8-wave workgroups for FP32 only (measured: FP64 is faster with 4)
+  const int v = strided_variant(pick_kch(a.nm), NP, a.tn, sizeof(T) == 4);
+  return with_svar(v, [&]<int FM, int FN, int KCH, int NW>() -> hipError_t {
+    auto k = strided_kernel<T, FM, FN, KCH, NW>;
+    hipError_t e = allow_lds(k, lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((a.na + a.tn - 1) / a.tn, a.nb, a.nslab);
+    hipLaunchKernelGGL(k, grid, dim3(64 * NW), lds, s, a);
+    return hipGetLastError();
+  });
 }
 
 template <typename T, int FM, int FN, int KCH>
@@ -749,11 +1089,11 @@ hipError_t launch_first(const FirstArgs& a, hipStream_t s) {
 static int round8(int x) { return (x + 7) / 8 * 8; }
 
 template <typename K>
-static hipError_t group_grid(K kernel, size_t lds, int span, int& grid) {
+static hipError_t group_grid(K kernel, int block, size_t lds, int span, int& grid) {
   hipError_t e = allow_lds(kernel, lds);
   if (e != hipSuccess) return e;
   int per_cu = 0, dev = 0, cus = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds);
   if (e != hipSuccess) return e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
@@ -762,66 +1102,66 @@ static hipError_t group_grid(K kernel, size_t lds, int span, int& grid) {
   return hipSuccess;
 }
 
-// strided variants: 0 (2,1,4) 1 (2,2,4) 2 (2,1,8) 3 (2,2,8) 4 (4,1,0) 5 (4,2,0)
 template <typename T>
 hipError_t plan_strided_group(StridedGroup& g, GroupLaunch& L) {
   GroupMap& m = g.map;
   if (m.n < 1 || m.n > kMaxGroup) return hipErrorInvalidValue;
   int kch = pick_kch(g.a[0].nm);
-  const bool fn2 = g.a[0].tn % 32 == 0;
   for (int q = 0; q < m.n; ++q) {
     const StridedArgs& a = g.a[q];
     if (a.nm <= 0 || a.na <= 0 || a.nb <= 0 || a.nslab <= 0) return hipErrorInvalidValue;
     if (a.tn != 16 && a.tn % 32 != 0) return hipErrorInvalidValue;
-    if ((a.tn % 32 == 0) != fn2) return hipErrorInvalidValue;
     if (a.plane && a.tn < a.na) return hipErrorInvalidValue;
     if (pick_kch(a.nm) != kch) kch = 0;
   }
   size_t lds = 0;
+  int64_t most = -1;
+  int v = -1;
   for (int q = 0; q < m.n; ++q) {
     const StridedArgs& a = g.a[q];
     const int NP = kch ? 16 * kch : round_up(a.nm, 64);
     if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP) || (a.plane && a.P.ld < round_up(a.na, 32)))
       return hipErrorInvalidValue;
-    const size_t b = static_cast<size_t>((a.sandwich || a.plane) ? 2 : 1) * NP * pitch_kmajor<T>(a.tn) * sizeof(T);
+    const size_t b = static_cast<size_t>((a.sandwich || a.plane || a.stencil) ? 2 : 1) * NP * pitch_kmajor<T>(a.tn) *
+                         sizeof(T) + (a.stencil ? sizeof(double) * stencil_coef_doubles(NP, a.tn) : 0);
     lds = std::max(lds, b);
     m.nbx[q] = (a.na + a.tn - 1) / a.tn;
     m.nby[q] = a.nb;
     const int64_t tiles = static_cast<int64_t>(m.nbx[q]) * a.nb * a.nslab;
     if (tiles > (1 << 30)) return hipErrorInvalidValue;
+    if (tiles > most) {  // the variant the member with the most tiles prefers
+      most = tiles;
+      v = strided_variant(kch, NP, a.tn, sizeof(T) == 4);
+    }
   }
   if (lds > kMaxLds) return hipErrorInvalidValue;
+  for (int q = 0; q < m.n; ++q) {
+    const int NP = kch ? 16 * kch : round_up(g.a[q].nm, 64);
+    if (!variant_fits(v, NP, g.a[q].tn)) v = kch == 4 ? 6 : (kch == 8 ? 8 : 4);  // (1, 1) or (4, 1) fit all
+  }
+  for (int q = 0; q < m.n; ++q) {
+    const int NP = kch ? 16 * kch : round_up(g.a[q].nm, 64);
+    if (!variant_fits(v, NP, g.a[q].tn)) return hipErrorInvalidValue;
+  }
   m.start[0] = 0;
   for (int q = 0; q < m.n; ++q) m.start[q + 1] = m.start[q] + m.nbx[q] * m.nby[q] * g.a[q].nslab;
   m.total = m.start[m.n];
   m.per_xcd = (m.total + 7) / 8;
   m.span = 8 * m.per_xcd;
-  L.variant = kch == 4 ? (fn2 ? 1 : 0) : kch == 8 ? (fn2 ? 3 : 2) : (fn2 ? 5 : 4);
+  L.variant = v;
   L.lds = lds;
-  switch (L.variant) {
-    case 0: return group_grid(strided_group_kernel<T, 2, 1, 4>, lds, m.span, L.grid);
-    case 1: return group_grid(strided_group_kernel<T, 2, 2, 4>, lds, m.span, L.grid);
-    case 2: return group_grid(strided_group_kernel<T, 2, 1, 8>, lds, m.span, L.grid);
-    case 3: return group_grid(strided_group_kernel<T, 2, 2, 8>, lds, m.span, L.grid);
-    case 4: return group_grid(strided_group_kernel<T, 4, 1, 0>, lds, m.span, L.grid);
-    default: return group_grid(strided_group_kernel<T, 4, 2, 0>, lds, m.span, L.grid);
-  }
+  return with_svar(v, [&]<int FM, int FN, int KCH, int NW>() -> hipError_t {
+    return group_grid(strided_group_kernel<T, FM, FN, KCH, NW>, 64 * NW, lds, m.span, L.grid);
+  });
 }
 
 template <typename T>
 hipError_t launch_strided_group(const GroupLaunch& L, const StridedGroup* dev, hipStream_t s) {
   if (!dev || L.grid <= 0 || L.grid % 8 != 0) return hipErrorInvalidValue;
-  const dim3 grid(L.grid), block(256);
-  switch (L.variant) {
-    case 0: hipLaunchKernelGGL((strided_group_kernel<T, 2, 1, 4>), grid, block, L.lds, s, dev); break;
-    case 1: hipLaunchKernelGGL((strided_group_kernel<T, 2, 2, 4>), grid, block, L.lds, s, dev); break;
-    case 2: hipLaunchKernelGGL((strided_group_kernel<T, 2, 1, 8>), grid, block, L.lds, s, dev); break;
-    case 3: hipLaunchKernelGGL((strided_group_kernel<T, 2, 2, 8>), grid, block, L.lds, s, dev); break;
-    case 4: hipLaunchKernelGGL((strided_group_kernel<T, 4, 1, 0>), grid, block, L.lds, s, dev); break;
-    case 5: hipLaunchKernelGGL((strided_group_kernel<T, 4, 2, 0>), grid, block, L.lds, s, dev); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return with_svar(L.variant, [&]<int FM, int FN, int KCH, int NW>() -> hipError_t {
+    hipLaunchKernelGGL((strided_group_kernel<T, FM, FN, KCH, NW>), dim3(L.grid), dim3(64 * NW), L.lds, s, dev);
+    return hipGetLastError();
+  });
 }
 
 // first-mode variants: 0 (1,2,4) 1 (1,2,8) 2 (1,2,0) 3 (2,2,4) 4 (2,2,8) 5 (2,2,0)
@@ -856,12 +1196,12 @@ hipError_t plan_first_group(FirstGroup& g, GroupLaunch& L) {
   L.variant = (tm == 16 ? 0 : 3) + (kch == 4 ? 0 : kch == 8 ? 1 : 2);
   L.lds = lds;
   switch (L.variant) {
-    case 0: return group_grid(first_group_kernel<T, 1, 2, 4>, lds, m.span, L.grid);
-    case 1: return group_grid(first_group_kernel<T, 1, 2, 8>, lds, m.span, L.grid);
-    case 2: return group_grid(first_group_kernel<T, 1, 2, 0>, lds, m.span, L.grid);
-    case 3: return group_grid(first_group_kernel<T, 2, 2, 4>, lds, m.span, L.grid);
-    case 4: return group_grid(first_group_kernel<T, 2, 2, 8>, lds, m.span, L.grid);
-    default: return group_grid(first_group_kernel<T, 2, 2, 0>, lds, m.span, L.grid);
+    case 0: return group_grid(first_group_kernel<T, 1, 2, 4>, 256, lds, m.span, L.grid);
+    case 1: return group_grid(first_group_kernel<T, 1, 2, 8>, 256, lds, m.span, L.grid);
+    case 2: return group_grid(first_group_kernel<T, 1, 2, 0>, 256, lds, m.span, L.grid);
+    case 3: return group_grid(first_group_kernel<T, 2, 2, 4>, 256, lds, m.span, L.grid);
+    case 4: return group_grid(first_group_kernel<T, 2, 2, 8>, 256, lds, m.span, L.grid);
+    default: return group_grid(first_group_kernel<T, 2, 2, 0>, 256, lds, m.span, L.grid);
   }
 }
 
@@ -894,8 +1234,8 @@ template hipError_t launch_strided<double>(const StridedArgs&, hipStream_t);
 template hipError_t launch_strided<float>(const StridedArgs&, hipStream_t);
 template hipError_t launch_first<double>(const FirstArgs&, hipStream_t);
 template hipError_t launch_first<float>(const FirstArgs&, hipStream_t);
-template size_t strided_lds_bytes<double>(int, int, int, int);
-template size_t strided_lds_bytes<float>(int, int, int, int);
+template size_t strided_lds_bytes<double>(int, int, int, int, int);
+template size_t strided_lds_bytes<float>(int, int, int, int, int);
 template size_t first_lds_bytes<double>(int, int, int);
 template size_t first_lds_bytes<float>(int, int, int);
 

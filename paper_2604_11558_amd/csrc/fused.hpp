@@ -115,7 +115,7 @@ template <typename T>
 hipError_t launch_first(const FirstArgs& a, hipStream_t s);
 // LDS bytes a launch would need (0 if the shape is not supported).
 template <typename T>
-size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane);
+size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane, int stencil = 0);
 template <typename T>
 size_t first_lds_bytes(int nm, int tm, int sandwich);
 

@@ -136,3 +136,35 @@ def test_autotune_keeps_results(geometry, n, precision):
     case.plan.run(x, 5)
     tol = {"fp64": 1e-12, "fp32": 2e-7, "bf16x2": 1.5e-6}[precision]
     assert rel_err(case.full_from_device(x), case.oracle_run(5)) < tol
+
+
+def test_run_timed_matches_steps_and_counts_launches():
+    case = Case("ball", (20, 24, 37), "fp32", tau=5e-3, seed=21)
+    for route in ("fused", "fused_stencil_apart", "generic"):
+        case.plan.set_route(route)
+        x, y = case.device_state(), case.device_state()
+        us = case.plan.run_timed(x, 5)
+        for _ in range(5):
+            case.plan.step(y)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y)
+        extra = 0 if route == "fused" else 1
+        assert len(us) == len(case.plan.chain()) + extra
+        assert all(u > 0 for u in us)
+
+
+def test_set_tiles_checks_and_keeps_results():
+    case = Case("sphere", (70, 45), "fp64", tau=1e-2, seed=22)
+    tiles = case.plan.tiles()
+    strided = [k for k, t in enumerate(tiles) if t in (16, 32)]
+    new = list(tiles)
+    for k in strided:
+        new[k] = 16 if tiles[k] == 32 else 32
+    case.plan.set_tiles(new)
+    assert case.plan.tiles() == new
+    with pytest.raises(tg.TGError):
+        case.plan.set_tiles([24] * len(tiles))
+    assert case.plan.tiles() == new  # unchanged by the rejected call
+    x = case.device_state()
+    case.plan.run(x, 6)
+    assert rel_err(case.full_from_device(x), case.oracle_run(6)) < 1e-12
