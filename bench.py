@@ -70,6 +70,23 @@ def time_gpu_run(plan, x, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def time_chain_op(plan, op, x, y, reps, torch):
+    """Average duration of one launch of the step, repeated back to back
+    between two HIP events on its stream."""
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        plan.apply_chain_op(op, x, y, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.apply_chain_op(op, x, y, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
 def cpu_baseline(w, pert, budget_s):
     """Oracle steps on the host for about ``budget_s`` seconds (set-up and
     one warm-up step excluded; at least 3 steps)."""
@@ -239,11 +256,19 @@ def main():
         launch_us = plan.run_timed(xw, args.steps)
         sec_direct = sum(launch_us) * 1e-6
         chain = plan.chain()
-        # launches of a step: route 2 starts with the separate stencil launch
-        off = 1 if route == "fused_stencil_apart" else (1 if route == "generic" else 0)
-        flops = [0.0] * off + [f for _, f in chain]
-        modes = [0] * off + [m for m, _ in chain]
-        dom = int(np.argmax(launch_us))
+        flops = [f for _, f in chain]
+        modes = [m for m, _ in chain]
+        # average duration of each product launch, repeated back to back
+        # between two HIP events (as in a step, except that the final update
+        # is a store)
+        bufs = [plan.state_from_deviation(pert), torch.empty_like(x), torch.empty_like(x)]
+        op_times = []
+        for i in range(len(chain)):
+            src = bufs[0] if i == 0 else bufs[1 + (i - 1) % 2]
+            dst = bufs[1 + i % 2]
+            op_times.append(time_chain_op(plan, i, src, dst, 200, torch))
+        del bufs
+        dom = int(np.argmax(op_times))
         # the other routes for comparison
         other = {}
         for rname in ("fused", "generic", "fused_stencil_apart"):
@@ -255,7 +280,8 @@ def main():
             other[rname] = time_gpu_run(plan, xg, min(args.steps, 200), 0, torch)
             del xg
         plan.set_route(route)
-        res[prec] = dict(sec=sec, sec_direct=sec_direct, setup=setup, op_times=[u * 1e-6 for u in launch_us],
+        res[prec] = dict(sec=sec, sec_direct=sec_direct, setup=setup, op_times=op_times,
+                         step_launch_us=launch_us,
                          dom=dom, flops=flops, modes=modes, ref=plan.reference.copy(), route=route, other=other,
                          tiles=tune["tiles"], tune_us=tune["us_per_step"])
         del plan, x, xw
@@ -285,17 +311,13 @@ def main():
 
     r = res["fp32"]
     dom = r["dom"]
-    state_bytes = dof * 4
     if r["flops"][dom] > 0:  # a product launch: MFMA-bound
         achieved = r["flops"][dom] / r["op_times"][dom]
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp32"] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32"], "flops_per_launch": r["flops"][dom],
                 "kernel": f"launch {dom} of the {r['route']} route (leading mode {r['modes'][dom]})"}
-    else:  # the separate stencil launch: one read of the state, one write of F
-        achieved = 2 * state_bytes / r["op_times"][dom]
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "bytes_per_launch": 2 * state_bytes,
-                "kernel": f"launch {dom} (stencil) of the {r['route']} route"}
+    else:
+        raise RuntimeError("a product launch without flops")
     key = f"{r['route']}:{dom}:{','.join(map(str, r['tiles']))}"
     roof["traffic"] = (TRAFFIC or {}).get(key) if TRAFFIC_DIGEST == kernel_sources_digest() else None
     roof["avg_launch_us"] = r["op_times"][dom] * 1e6
@@ -327,7 +349,8 @@ def main():
         "route": res["fp32"]["route"],
         "autotuned": {p: {"route": res[p]["route"], "tiles": res[p]["tiles"]} for p in res},
         "ms_per_step_direct_launches_with_events": {p: res[p]["sec_direct"] * 1e3 for p in res},
-        "launch_us": {p: [t * 1e6 for t in res[p]["op_times"]] for p in res},
+        "launch_us_back_to_back": {p: [t * 1e6 for t in res[p]["op_times"]] for p in res},
+        "launch_us_in_direct_steps": {p: res[p]["step_launch_us"] for p in res},
         "ms_per_step_other_routes": {p: {k: v * 1e3 for k, v in res[p]["other"].items()} for p in res},
         "plan_setup_s": {p: res[p]["setup"] for p in res},
         "roofline": roof,

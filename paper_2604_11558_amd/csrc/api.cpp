@@ -1558,6 +1558,10 @@ int tg_plan_set_tiles(tg_plan p, int32_t n_ops, const int32_t* tiles) {
   });
 }
 
+// a candidate replaces the current choice only when it is at least 2%
+// faster, so that timing noise does not flip between near-equal ones
+constexpr double kTuneGain = 0.98;
+
 int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, double* best_us) {
   void* tmp = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1640,7 +1644,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
             if (op.kind == 0) op.sa.tn = c;
             else op.fa.tm = c;
             double t = lds_ok(op) ? measure() : std::numeric_limits<double>::infinity();
-            if (t < cur) {
+            if (t < kTuneGain * cur) {
               cur = t;
               keep = c;
             } else {
@@ -1650,7 +1654,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
           }
         }
       }
-      if (cur < best) {
+      if (cur < (best_tiles.empty() ? best : kTuneGain * best)) {
         best = cur;
         best_route = r;
         best_tiles = tiles_now();

@@ -786,7 +786,25 @@ template <typename T, int FM, int FN, int KCH, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, NW>())))
 void strided_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
-  strided_tile<T, FM, FN, KCH, NW>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+  // 1D grid of 8 * per_xcd workgroups, dispatched round-robin over the 8
+  // XCDs: XCD x takes logical tiles x * per_xcd .. (x + 1) * per_xcd.  The
+  // logical order runs over the species of an instance first, then the
+  // column tiles, so that a tile, its neighbours in the next-slower
+  // coordinate and the other species' tiles of the same columns (read by
+  // the in-tile stencil) share an XCD and its L2.
+  const int nbx = (a.na + a.tn - 1) / a.tn;
+  const int total = nbx * a.nb * a.nslab;
+  const int per_xcd = (total + 7) / 8;
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= total) return;
+  const int ns = a.stencil ? a.st.nspecies : 1;
+  const int sp = L % ns;
+  int rest = L / ns;
+  const int bx = rest % nbx;
+  rest /= nbx;
+  const int by = rest % a.nb;
+  const int inst = rest / a.nb;
+  strided_tile<T, FM, FN, KCH, NW>(a, bx, by, inst * ns + sp, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1049,8 +1067,10 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t s) {
     auto k = strided_kernel<T, FM, FN, KCH, NW>;
     hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
-    dim3 grid((a.na + a.tn - 1) / a.tn, a.nb, a.nslab);
-    hipLaunchKernelGGL(k, grid, dim3(64 * NW), lds, s, a);
+    const int64_t total = static_cast<int64_t>((a.na + a.tn - 1) / a.tn) * a.nb * a.nslab;
+    if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
+    const int per_xcd = static_cast<int>((total + 7) / 8);
+    hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
   });
 }
