@@ -432,18 +432,22 @@ __device__ __forceinline__ void col_factors(double (&fc)[FN], const double* pn, 
 // (a = i + n1 j in 3D, a = i in 2D).  The centre values of species sp are
 // loaded as a plain tile into `stage` (row neighbours come from there);
 // the other species and the column neighbours of each element are loaded
-// into registers, eight elements per thread and pass, all requests issued
-// before any is used; the 1D operator coefficients and scale factors of
-// the tile's rows and columns are staged once in LDS (`cf`).
-// elements per thread and pass: 8 for 4-wave, 4 for 8-wave workgroups
+// into registers, several elements per thread and pass, all requests
+// issued before any is used.  The operator is evaluated as
+//   d ( sum_m rs_m(k) (A_m w(a-) + B_m w + C_m w(a+)) + cs_r(c) (L(k) w(k-1) + D(k) w + U(k) w(k+1)) )
+// over the column modes m, with the column factors A_m = cs_m lo_m, ...
+// (cs_m the column part of mode m's scale) and the row factors L = rs_r lo_r,
+// ... (rs the row parts), all in FP64: next to the axis and the poles the
+// terms exceed F by orders of magnitude, and FP32 arithmetic there costs
+// about an order of magnitude of the FP32 path's accuracy.
 template <int NT>
 constexpr int stencil_batch() { return NT >= 512 ? 4 : 8; }
 
-__host__ __device__ inline int stencil_coef_doubles(int NP, int TN) { return NP * 6 + TN * 9; }
+__host__ __device__ inline int stencil_coef_doubles(int NP, int TN) { return NP * 5 + TN * 7; }
 
 template <typename T, int NT>
 __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, int sp, int a0, int NP, int TN, int nm,
-                                             int na, T* sX, T* stage, int ld, double* cf, int tid) {
+                                             int na, T* sX, T* stage, int ld, double* cfd, int tid) {
   const int ns = st.nspecies;
   const bool three = st.ndim == 3;
   const int n1 = st.n[0], n2 = st.n[1];
@@ -458,68 +462,96 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, in
   const bool per1 = (st.periodic_mask >> 1) & 1;
   const bool perr = (st.periodic_mask >> rmode) & 1;
   const int total = NP * TN;
-  constexpr int kStencilBatch = stencil_batch<NT>();
-  T oth[kStencilBatch][2], c0m[kStencilBatch], c0p[kStencilBatch], c1m[kStencilBatch], c1p[kStencilBatch];
-  // requests of the other species and the column neighbours of this
-  // thread's elements e0 + tid + NT q
+  constexpr int kB = stencil_batch<NT>();
+  // uniform constants first: their loads overlap everything below
+  const double d = st.diff[inst * ns + sp];
+  const ReactConst rcst = react_const(st, inst);
+  const bool react = st.what != 1 && st.reaction != 0;
+  const bool diffuse = st.what != 2;
+  // LDS: rows [NP][5] = rs_0, rs_1, L, D, U;  cols [TN][7] = A_0, B_0, C_0, A_1, B_1, C_1, cs_r
+  double* rc = cfd;
+  double* cc = rc + NP * 5;
+  // column geometry of an element: its neighbours' offsets a-, a+ (mode 1)
+  // and a-, a+ along mode 2 (3D)
+  struct Col {
+    int aa, im, ip, jm, jp;
+  };
+  auto col_of = [&](int c) {
+    Col q;
+    q.aa = a0 + c;
+    const int aa = min(q.aa, na - 1);
+    int i = aa, j = 0;
+    if (three) j = dn1.quot(aa, i);
+    q.im = i > 0 ? aa - 1 : (per0 ? aa + n1 - 1 : aa);
+    q.ip = i + 1 < n1 ? aa + 1 : (per0 ? aa - (n1 - 1) : aa);
+    q.jm = !three ? aa : (j > 0 ? aa - n1 : (per1 ? aa + (n2 - 1) * n1 : aa));
+    q.jp = !three ? aa : (j + 1 < n2 ? aa + n1 : (per1 ? aa - (n2 - 1) * n1 : aa));
+    return q;
+  };
+  // a thread keeps one column when NT is a multiple of TN
+  const bool colfix = NT % TN == 0;
+  int c_fix;
+  const int k_fix = dtn.quot(tid, c_fix);
+  const int kstep = NT / TN;  // rows between a thread's elements when colfix
+  const Col cf0 = col_of(c_fix);
+
+  T oth[kB][2], c0m[kB], c0p[kB], c1m[kB], c1p[kB];
+  auto elem = [&](int e, int& k, int& c) {
+    if (colfix) {
+      c = c_fix;
+      k = k_fix + (e - tid) / NT * kstep;  // e = e0 + tid + NT q, e0 a multiple of NT
+    } else {
+      k = dtn.quot(e, c);
+    }
+  };
   auto request = [&](int e0) {
 #pragma unroll
-    for (int q = 0; q < kStencilBatch; ++q) {
+    for (int q = 0; q < kB; ++q) {
       const int e = e0 + tid + NT * q;
-      int c;
-      const int k = dtn.quot(e, c);
-      const int aa = a0 + c;
+      int k, c;
+      elem(e, k, c);
+      const Col g = colfix ? cf0 : col_of(c);
       oth[q][0] = oth[q][1] = c0m[q] = c0p[q] = c1m[q] = c1p[q] = T(0);
-      if (e < total && k < nm && aa < na) {
+      if (e < total && k < nm && g.aa < na) {
         const int64_t p = static_cast<int64_t>(k) * na;
-        int i = aa, j = 0;
-        if (three) j = dn1.quot(aa, i);
-        const int im = i > 0 ? aa - 1 : (per0 ? aa + n1 - 1 : aa);
-        const int ip = i + 1 < n1 ? aa + 1 : (per0 ? aa - (n1 - 1) : aa);
-        c0m[q] = Ws[p + im];
-        c0p[q] = Ws[p + ip];
-        if (three) {
-          const int jm = j > 0 ? aa - n1 : (per1 ? aa + (n2 - 1) * n1 : aa);
-          const int jp = j + 1 < n2 ? aa + n1 : (per1 ? aa - (n2 - 1) * n1 : aa);
-          c1m[q] = Ws[p + jm];
-          c1p[q] = Ws[p + jp];
+        if (diffuse) {
+          c0m[q] = Ws[p + g.im];
+          c0p[q] = Ws[p + g.ip];
+          if (three) {
+            c1m[q] = Ws[p + g.jm];
+            c1p[q] = Ws[p + g.jp];
+          }
         }
-        // the other species, by value (no dynamically indexed arrays)
-        if (ns > 1) oth[q][0] = Wi[(sp == 0 ? 1 : 0) * plane + p + aa];
-        if (ns > 2) oth[q][1] = Wi[(sp == 2 ? 1 : 2) * plane + p + aa];
+        if (react) {
+          // the other species, by value (no dynamically indexed arrays)
+          if (ns > 1) oth[q][0] = Wi[(sp == 0 ? 1 : 0) * plane + p + g.aa];
+          if (ns > 2) oth[q][1] = Wi[(sp == 2 ? 1 : 2) * plane + p + g.aa];
+        }
       }
     }
   };
   request(0);
-  // LDS layout: rows [NP][6] = lo, dg, up of the row mode, row scale of modes 0..2;
-  //             cols [TN][9] = lo, dg, up of modes 0 and 1 (column modes), column scale of modes 0..2
-  double* rc = cf;
-  double* cc = cf + NP * 6;
   for (int k = tid; k < NP; k += NT) {
     const int kk = min(k, nm - 1);
     const double* c = st.coef + rmode * 3 * nmx;
-    rc[k * 6 + 0] = c[kk];
-    rc[k * 6 + 1] = c[nmx + kk];
-    rc[k * 6 + 2] = c[2 * nmx + kk];
+    double rs[3];
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
       const bool on = mu < st.ndim && ((st.scale_mask >> (3 * mu + rslot)) & 1);
-      rc[k * 6 + 3 + mu] = on ? st.scale[mu * 3 * nmx + rslot * nmx + kk] : 1.0;
+      rs[mu] = on ? st.scale[mu * 3 * nmx + rslot * nmx + kk] : 1.0;
     }
+    const double rr = three ? rs[2] : rs[1];
+    rc[k * 5 + 0] = rs[0];
+    rc[k * 5 + 1] = three ? rs[1] : 0.0;
+    rc[k * 5 + 2] = rr * c[kk];
+    rc[k * 5 + 3] = rr * c[nmx + kk];
+    rc[k * 5 + 4] = rr * c[2 * nmx + kk];
   }
   for (int c = tid; c < TN; c += NT) {
     const int aa = min(a0 + c, na - 1);
     int i = aa, j = 0;
     if (three) j = dn1.quot(aa, i);
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const bool col_mode = m == 0 || three;
-      const int x = m == 0 ? i : j;
-      const double* q = st.coef + m * 3 * nmx;
-      cc[c * 9 + 3 * m + 0] = col_mode ? q[x] : 0.0;
-      cc[c * 9 + 3 * m + 1] = col_mode ? q[nmx + x] : 0.0;
-      cc[c * 9 + 3 * m + 2] = col_mode ? q[2 * nmx + x] : 0.0;
-    }
+    double cs[3];
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
       double f = 1.0;
@@ -529,60 +561,61 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, in
         if (sm & 1) f *= sc[i];
         if (three && (sm & 2)) f *= sc[nmx + j];
       }
-      cc[c * 9 + 6 + mu] = f;
+      cs[mu] = f;
     }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const bool col_mode = m == 0 || three;
+      const int x = m == 0 ? i : j;
+      const double* q = st.coef + m * 3 * nmx;
+      cc[c * 7 + 3 * m + 0] = col_mode ? cs[m] * q[x] : 0.0;
+      cc[c * 7 + 3 * m + 1] = col_mode ? cs[m] * q[nmx + x] : 0.0;
+      cc[c * 7 + 3 * m + 2] = col_mode ? cs[m] * q[2 * nmx + x] : 0.0;
+    }
+    cc[c * 7 + 6] = three ? cs[2] : cs[1];
   }
   load_tile_kmajor<T, NT>(Ws, na, nm, a0, NP, TN, stage, ld, tid);
   __syncthreads();  // staged centres and coefficients
-  const double d = st.diff[inst * ns + sp];
-  // a thread keeps one column when NT is a multiple of TN: its column
-  // coefficients then live in registers
-  const bool colfix = NT % TN == 0;
-  double cr[9];
+  double cr[7];
   if (colfix) {
-    int cfix;
-    (void)dtn.quot(tid, cfix);
 #pragma unroll
-    for (int x = 0; x < 9; ++x) cr[x] = cc[cfix * 9 + x];
+    for (int x = 0; x < 7; ++x) cr[x] = cc[c_fix * 7 + x];
   }
-  for (int e0 = 0; e0 < total; e0 += NT * kStencilBatch) {
+  for (int e0 = 0; e0 < total; e0 += NT * kB) {
     if (e0 > 0) request(e0);
 #pragma unroll
-    for (int q = 0; q < kStencilBatch; ++q) {
+    for (int q = 0; q < kB; ++q) {
       const int e = e0 + tid + NT * q;
       if (e >= total) break;
-      int c;
-      const int k = dtn.quot(e, c);
-      const int aa = a0 + c;
+      int k, c;
+      elem(e, k, c);
       double v = 0.0;
-      if (k < nm && aa < na) {
+      if (k < nm && a0 + c < na) {
         const double w0 = static_cast<double>(stage[k * ld + c]);
-        const double* r6 = rc + k * 6;
-        double c9[9];
-#pragma unroll
-        for (int x = 0; x < 9; ++x) c9[x] = colfix ? cr[x] : cc[c * 9 + x];
         double f = 0.0;
-        if (st.what != 2) {
+        if (diffuse) {
+          double c7[7];
+#pragma unroll
+          for (int x = 0; x < 7; ++x) c7[x] = colfix ? cr[x] : cc[c * 7 + x];
+          const double* r5 = rc + k * 5;
           const int km = k > 0 ? k - 1 : (perr ? nm - 1 : k);
           const int kp = k + 1 < nm ? k + 1 : (perr ? 0 : k);
           const double wkm = static_cast<double>(stage[km * ld + c]);
           const double wkp = static_cast<double>(stage[kp * ld + c]);
-          // row mode
-          f += r6[3 + rmode] * c9[6 + rmode] * (r6[0] * wkm + r6[1] * w0 + r6[2] * wkp);
-          // column modes
-          f += r6[3] * c9[6] * (c9[0] * static_cast<double>(c0m[q]) + c9[1] * w0 + c9[2] * static_cast<double>(c0p[q]));
+          f = c7[6] * (r5[2] * wkm + r5[3] * w0 + r5[4] * wkp);
+          f += r5[0] * (c7[0] * static_cast<double>(c0m[q]) + c7[1] * w0 + c7[2] * static_cast<double>(c0p[q]));
           if (three)
-            f += r6[4] * c9[7] *
-                 (c9[3] * static_cast<double>(c1m[q]) + c9[4] * w0 + c9[5] * static_cast<double>(c1p[q]));
+            f += r5[1] * (c7[3] * static_cast<double>(c1m[q]) + c7[4] * w0 + c7[5] * static_cast<double>(c1p[q]));
           f *= d;
         }
-        if (st.what != 1 && st.reaction != 0) {
+        if (react) {
+          const double dw0 = w0;
           const double o0 = static_cast<double>(oth[q][0]), o1 = static_cast<double>(oth[q][1]);
-          const double u = sp == 0 ? w0 : o0;
-          const double vv = sp == 1 ? w0 : (sp == 0 ? o0 : o1);
-          const double w = sp == 2 ? w0 : o1;
+          const double u = sp == 0 ? dw0 : o0;
+          const double vv = sp == 1 ? dw0 : (sp == 0 ? o0 : o1);
+          const double w = sp == 2 ? dw0 : o1;
           double G0, G1, G2;
-          reaction3(st, inst, u, vv, w, G0, G1, G2);
+          reaction3c(rcst, u, vv, w, G0, G1, G2);
           f += sp == 0 ? G0 : (sp == 1 ? G1 : G2);
         }
         v = f;
@@ -609,7 +642,7 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
   constexpr int KR = KCH > 0 ? KCH : 1;  // register prefetch extent
   // cross-product prefetch only where two factor register sets fit
   // (FP64 with 128-long contractions keeps one set, loaded per product)
-  constexpr bool kPre = KCH > 0 && NW == 4 && sizeof(T) * FM * KCH * 4 <= 256;
+  constexpr bool kPre = KCH > 0 && (NW == 4 || FM > 1) && sizeof(T) * FM * KCH * 4 <= 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int nm = a.nm, na = a.na, TN = a.tn;
@@ -777,13 +810,14 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
   }
 }
 
-// 8-wave FP32 workgroups are held to 128 VGPRs (4 waves per SIMD), so two
-// of them share a CU.
-template <typename T, int NW>
-constexpr int waves_per_eu() { return (NW == 8 && sizeof(T) == 4) ? 4 : 1; }
+// 8-wave FP32 workgroups with one-row sub-tiles (many workgroups) are held
+// to 128 VGPRs (4 waves per SIMD) so that two share a CU; the others may
+// use up to 256.
+template <typename T, int FM, int NW>
+constexpr int waves_per_eu() { return (NW == 8 && sizeof(T) == 4 && FM == 1) ? 4 : (NW == 8 ? 2 : 1); }
 
 template <typename T, int FM, int FN, int KCH, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, NW>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW>())))
 void strided_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
   // 1D grid of 8 * per_xcd workgroups, dispatched round-robin over the 8
@@ -933,7 +967,7 @@ __device__ __forceinline__ int group_member(const GroupMap& m, int L, int& local
 }
 
 template <typename T, int FM, int FN, int KCH, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, NW>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW>())))
 void strided_group_kernel(const StridedGroup* __restrict__ grp) {
   extern __shared__ __align__(256) unsigned char smem[];
   const GroupMap& m = grp->map;

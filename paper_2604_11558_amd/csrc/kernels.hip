@@ -233,11 +233,12 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   const int j = q - k * n2;
   const T* Wi = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * NS * npts;
   T* F = static_cast<T*>(a.F) + static_cast<int64_t>(inst) * NS * npts;
+  const ReactConst rc = react_const(a, inst);  // uniform constants, requested first
   double w[3] = {0, 0, 0};
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
   double G[3] = {0, 0, 0};
-  if (a.what != 1 && a.reaction != 0) reaction_dev(a, inst, w, G);
+  if (a.what != 1 && a.reaction != 0) reaction3c(rc, w[0], w[1], w[2], G[0], G[1], G[2]);
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
     double f = a.what != 2 ? diffusion_fast<T, NDIM>(a, Wi + sp * npts, w[sp], sp, inst, p, i, j, k) : 0.0;

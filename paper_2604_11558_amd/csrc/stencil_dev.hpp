@@ -32,6 +32,47 @@ __device__ __forceinline__ void reaction3(const StencilArgs& a, int inst, double
   }
 }
 
+// The reaction constants of one instance, read once (uniform values) so that
+// their loads are issued together at the start of a kernel.
+struct ReactConst {
+  int reaction;
+  double ur, vr, wr, g0, g1, g2, kap, mu;
+};
+
+__device__ __forceinline__ ReactConst react_const(const StencilArgs& a, int inst) {
+  ReactConst c;
+  c.reaction = a.reaction;
+  const int ns = a.nspecies;
+  const double* rp = a.rparams + inst * 4;
+  const double* wr = a.wref + inst * ns;
+  const double* g0 = a.g0 + inst * ns;
+  c.ur = wr[0];
+  c.vr = ns > 1 ? wr[1] : 0.0;
+  c.wr = ns > 2 ? wr[2] : 0.0;
+  c.g0 = g0[0];
+  c.g1 = ns > 1 ? g0[1] : 0.0;
+  c.g2 = ns > 2 ? g0[2] : 0.0;
+  c.kap = rp[2];
+  c.mu = rp[3];
+  return c;
+}
+
+// reaction3 with the constants already loaded
+__device__ __forceinline__ void reaction3c(const ReactConst& c, double dp, double dq, double dr, double& G0,
+                                           double& G1, double& G2) {
+  const double ur = c.ur, vr = c.vr;
+  const double N = ur * ur * dq + 2.0 * ur * vr * dp + 2.0 * ur * dp * dq + vr * dp * dp + dp * dp * dq;
+  if (c.reaction == 1) {
+    G0 = c.g0 - dp + N;
+    G1 = c.g1 - N;
+    G2 = 0.0;
+  } else {
+    G0 = c.g0 - dp + N - c.kap * (ur * dr + c.wr * dp + dp * dr);
+    G1 = c.g1 - N;
+    G2 = c.g2 + c.mu * (dp - dr);
+  }
+}
+
 __device__ __forceinline__ void reaction_dev(const StencilArgs& a, int inst, const double* w, double* G) {
   reaction3(a, inst, w[0], w[1], w[2], G[0], G[1], G[2]);
 }
