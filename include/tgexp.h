@@ -216,14 +216,25 @@ int tg_group_run(const tg_plan* plans, int32_t n_plans, void* const* states, int
 int tg_group_info(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t* grouped,
                   int32_t* launches_per_step);
 
+/* Route for a grouped run: times `iters` grouped steps (after 2 warm-up
+ * steps) with every plan on route 0 and then on route 2, on private copies
+ * of the states (not modified), and sets the faster route (by at least 2%)
+ * on all plans, so that they stay groupable.  Plans whose fused route does
+ * not fit are left as they are (*best_us = 0).  Allocates one copy of each
+ * state for the duration of the call; synchronous. */
+int tg_group_autotune(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t iters, void* stream,
+                      double* best_us);
+
 /* ---- autotuning ----------------------------------------------------------
  * Times `iters` steps (after 2 warm-up steps) of each candidate launch
  * configuration on a private copy of `state` (device, plan layout; not
  * modified) and keeps the fastest: the route (0, 2, and 1 except for
  * split-bf16 plans) and, per fused launch, the tile width (16 / 32 / 64
  * columns for strided launches that do not cover whole planes, 16 / 32
- * rows for first-mode launches), by coordinate descent.  Every candidate
- * computes the same step.  *best_us: time per step of the choice.
+ * rows for first-mode launches), by coordinate descent; a candidate must
+ * be at least 2% faster to replace the current choice (routes are tried
+ * in the order 0, 2, 1).  Every candidate computes the same step.
+ * *best_us: time per step of the choice.
  * Allocates one state-sized buffer for the duration of the call;
  * synchronous.  Captured graphs of the plan are dropped. */
 int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, double* best_us);

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "tg_plan_tiles": (ctypes.c_int, [_p, _pi, _pi]),
     "tg_run_timed": (ctypes.c_int, [_p, _p, _c_i64, _p, _c_int, _pi, _pd]),
     "tg_plan_set_tiles": (ctypes.c_int, [_p, _c_int, _pi]),
+    "tg_group_autotune": (ctypes.c_int, [ctypes.POINTER(_p), _c_int, ctypes.POINTER(_p), _c_int, _p, _pd]),
 }
 
 _lib = None
@@ -321,6 +322,14 @@ def group_run(plans, states, n_steps: int, stream=None):
     _check(lib().tg_group_run(hp, len(plans), hs, int(n_steps), _stream_ptr(stream)))
 
 
+def group_autotune(plans, states, iters: int = 10, stream=None) -> float:
+    """Pick the route (0 or 2) of a grouped run on copies of the states; microseconds per step."""
+    hp, hs = _group_args(plans, states)
+    best = ctypes.c_double()
+    _check(lib().tg_group_autotune(hp, len(plans), hs, int(iters), _stream_ptr(stream), ctypes.byref(best)))
+    return best.value
+
+
 def group_info(plans, states) -> dict:
     hp, hs = _group_args(plans, states)
     g, n = ctypes.c_int32(), ctypes.c_int32()
@@ -328,5 +337,5 @@ def group_info(plans, states) -> dict:
     return {"grouped": bool(g.value), "launches_per_step": n.value}
 
 
-__all__ = ["Grid", "Plan", "TGError", "lib", "group_run", "group_info", "GEOMETRY", "PRECISION",
+__all__ = ["Grid", "Plan", "TGError", "lib", "group_run", "group_info", "group_autotune", "GEOMETRY", "PRECISION",
            "REACTION"]

@@ -255,6 +255,10 @@ std::vector<double> reaction_at(int reaction, int ns, const double* rp, const do
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// an autotuning candidate replaces the current choice only when it is at
+// least 2% faster, so that timing noise does not flip between near-equal ones
+constexpr double kTuneGain = 0.98;
+
 // Launch-timing hook (tg_run_timed): when set, an event is recorded on the
 // launch stream before every kernel launch of a step.
 struct LaunchEvents {
@@ -1503,6 +1507,83 @@ int tg_group_run(const tg_plan* plans, int32_t n_plans, void* const* states, int
   });
 }
 
+int tg_group_autotune(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t iters, void* stream,
+                      double* best_us) {
+  std::vector<void*> tmp;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  tg_plan_s* P0 = (plans && n_plans >= 1) ? plans[0] : nullptr;
+  int rc = guarded([&] {
+    TG_REQUIRE(plans && states && n_plans >= 1 && n_plans <= tg::kMaxGroup && iters >= 1 && iters <= 10000,
+               TG_EINVAL, "tg_group_autotune: bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<tg_plan_s*> ps(plans, plans + n_plans);
+    bool fused_all = true;
+    for (int q = 0; q < n_plans; ++q) {
+      TG_REQUIRE(ps[q] && states[q] && aligned(ps[q], states[q]), TG_EINVAL, "tg_group_autotune: bad plan or state");
+      fused_all = fused_all && ps[q]->fused_ok;
+      void* t = nullptr;
+      const size_t bytes = static_cast<size_t>(ps[q]->state_elems) * ps[q]->esize;
+      hip_check(hipMalloc(&t, bytes), "hipMalloc(group autotune state)");
+      tmp.push_back(t);
+      hip_check(hipMemcpyAsync(t, states[q], bytes, hipMemcpyDeviceToDevice, st), "group autotune copy");
+    }
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    std::vector<int> routes = fused_all ? std::vector<int>{0, 2} : std::vector<int>{};
+    if (routes.empty()) {
+      if (best_us) *best_us = 0.0;
+      return TG_OK;  // nothing to choose: the plans run their own routes
+    }
+    auto set_route = [&](int r) {
+      for (auto* P : ps)
+        if (P->route != r) {
+          drop_graphs(P);
+          P->route = r;
+        }
+    };
+    double best = std::numeric_limits<double>::infinity();
+    int best_route = routes[0];
+    for (int r : routes) {
+      set_route(r);
+      tg_group_s* G = find_group(plans, n_plans, tmp.data());
+      for (int w = 0; w < 2; ++w) group_step_any(G, st);
+      hip_check(hipEventRecord(e0, st), "event record");
+      for (int it = 0; it < iters; ++it) group_step_any(G, st);
+      hip_check(hipEventRecord(e1, st), "event record");
+      hip_check(hipEventSynchronize(e1), "event sync");
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+      const double us = 1e3 * static_cast<double>(ms) / iters;
+      if (us < (std::isfinite(best) ? kTuneGain * best : best)) {
+        best = us;
+        best_route = r;
+      }
+    }
+    set_route(best_route);
+    if (best_us) *best_us = best;
+    return TG_OK;
+  });
+  // drop the groups built on the private copies, then the copies
+  if (P0 && !tmp.empty()) {
+    (void)hipDeviceSynchronize();
+    for (auto it = P0->groups.begin(); it != P0->groups.end();) {
+      bool uses_tmp = false;
+      for (size_t k = 2; k < it->first.size(); k += 3)
+        for (void* t : tmp) uses_tmp = uses_tmp || it->first[k] == reinterpret_cast<uintptr_t>(t);
+      if (uses_tmp) {
+        delete it->second;
+        it = P0->groups.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (void* t : tmp) (void)hipFree(t);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return rc;
+}
+
 int tg_group_info(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t* grouped,
                   int32_t* launches_per_step) {
   return guarded([&] {
@@ -1557,10 +1638,6 @@ int tg_plan_set_tiles(tg_plan p, int32_t n_ops, const int32_t* tiles) {
     return TG_OK;
   });
 }
-
-// a candidate replaces the current choice only when it is at least 2%
-// faster, so that timing noise does not flip between near-equal ones
-constexpr double kTuneGain = 0.98;
 
 int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, double* best_us) {
   void* tmp = nullptr;

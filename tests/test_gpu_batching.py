@@ -168,3 +168,20 @@ def test_set_tiles_checks_and_keeps_results():
     x = case.device_state()
     case.plan.run(x, 6)
     assert rel_err(case.full_from_device(x), case.oracle_run(6)) < 1e-12
+
+
+def test_group_autotune_keeps_plans_groupable():
+    cases = [Case("sphere", (70, 45), "fp32", tau=1e-2, seed=23, batch=2),
+             Case("sphere", (24, 20), "fp32", tau=1e-2, seed=24)]
+    plans = [c.plan for c in cases]
+    states = [c.device_state() for c in cases]
+    before = [s.clone() for s in states]
+    us = tg.group_autotune(plans, states, iters=3)
+    assert us > 0
+    for a, b in zip(states, before):
+        assert torch.equal(a, b)  # the states are not touched
+    assert plans[0].route == plans[1].route
+    assert tg.group_info(plans, states)["grouped"]
+    tg.group_run(plans, states, 5)
+    for c, x in zip(cases, states):
+        assert rel_err(c.full_from_device(x), c.oracle_run(5)) < TOL["fp32"]
