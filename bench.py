@@ -36,8 +36,8 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = None
-TRAFFIC_DIGEST = None
+TRAFFIC = {"fused:0:16,64": 11004473, "fused:1:16,64": 13292695}
+TRAFFIC_DIGEST = "5e7a8fffacafe4904e49d6315c07765ba2122b2cc5ecc8b99fd4ae60efe201e6"
 
 
 def cpu_model() -> str:
@@ -322,6 +322,10 @@ def main():
         raise RuntimeError("a product launch without flops")
     key = f"{r['route']}:{dom}:{','.join(map(str, r['tiles']))}"
     roof["traffic"] = (TRAFFIC or {}).get(key) if TRAFFIC_DIGEST == kernel_sources_digest() else None
+    roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    # one read of the launch's input and one write of its output (the
+    # plane-tail launch also reads the state it updates)
+    roof["algorithmic_bytes_per_launch"] = dof * 4 * (3 if dom == len(r["flops"]) - 1 and dom > 0 else 2)
     roof["avg_launch_us"] = r["op_times"][dom] * 1e6
     roof["launch_key"] = key
     out = {
