@@ -48,9 +48,9 @@ def chain(se: SplitEE, s: int):
     """
     g, A, tau, d = se.geometry, se.A, se.tau, se.diff[s]
     ops = []
-    if g == "disk":
+    if g in ("disk", "disk_lambda"):
         lam_t, Q, _ = eig_tridiag(A[1])
-        c = tau * np.outer(se.grid[0] ** -2.0, lam_t)
+        c = tau * np.outer(se.grid[0] ** (-2.0 - (se.extent[1] if g == "disk_lambda" else 0.0)), lam_t)
         P, dP = _dense_pair(A[0], tau * d)
         ops = [("mode", Q.T, None, 2), ("had", phi1_scalar(d * c), _dphi1(c, d * c)),
                ("mode", Q, None, 2), ("mode", P, tau * dP, 1)]
@@ -117,7 +117,8 @@ def param_derivative(kind, U, params):
     """dG_r/dp_q pointwise, list over r of list over q.
 
     Schnakenberg p = (a, b); AIS3 p = (a, b, kappa, mu) with
-    G = (a - u + u^2 v - kappa u w, b - u^2 v, mu (u - w)).
+    G = (a - u + u^2 v - kappa u w, b - u^2 v, mu (u - w)); scaled
+    Schnakenberg p = (a, b, gamma) with G = gamma (a - u + u^2 v, b - u^2 v).
     """
     one = np.ones_like(U[0])
     zero = np.zeros_like(U[0])
@@ -126,6 +127,10 @@ def param_derivative(kind, U, params):
     if kind == "ais3":
         u, _, w = U
         return [[one, zero, -u * w, zero], [zero, one, zero, zero], [zero, zero, zero, u - w]]
+    if kind == "schnakenberg_scaled":
+        u, v = U
+        a, b, gam = params
+        return [[gam * one, zero, a - u + u * u * v], [zero, gam * one, b - u * u * v]]
     raise NotImplementedError(kind)
 
 

@@ -28,11 +28,18 @@ def terms(geometry: str, n, extent=(1.0, 1.0)):
                   + A_phi(x)I(x)D_rho                                  eq. (ball)
     cylinder: M = I(x)I(x)A_{rho,2} + I(x)A_theta(x)D_rho + A_z(x)I(x)I  eq. (cylinder)
 
-    D_rho = diag(rho_i^-2), D_phi = diag(sin^-2 phi_k).  A sphere of radius
-    rho_* carries the factor rho_*^-2 on both terms.
+    disk_lambda: M = I (x) A_lambda + A_theta (x) D_rho^lambda     Section 5.3
+
+    D_rho = diag(rho_i^-2), D_phi = diag(sin^-2 phi_k), D_rho^lambda =
+    diag(rho_i^(-2-lambda)) (lambda = extent[1]).  A sphere of radius rho_*
+    carries the factor rho_*^-2 on both terms.
     """
     ops = op.operators_1d(geometry, n, extent)
     A, g = ops["A"], ops["grid"]
+    if geometry == "disk_lambda":
+        Ar, At = A
+        Dr = np.diag(g[0] ** (-2.0 - extent[1]))
+        return [_kron(np.eye(n[1]), Ar), _kron(At, Dr)]
     if geometry == "disk":
         Ar, At = A
         Dr = np.diag(g[0] ** -2.0)
@@ -69,8 +76,14 @@ def laplacian(geometry: str, n, extent=(1.0, 1.0)):
 def dirichlet_lift(geometry: str, n, extent=(1.0, 1.0)) -> np.ndarray:
     """Vector r with M w + r * w_D the discrete Laplacian when w = w_D at z_*.
 
-    Only the cylinder has a Dirichlet end (Table 1); elsewhere r = 0.
+    The cylinder has a Dirichlet end at z_* (Table 1) and the anomalous disk
+    one at rho_* (Section 5.3); elsewhere r = 0.
     """
+    if geometry == "disk_lambda":
+        nr, nt = n
+        er = np.zeros(nr)
+        er[-1] = op.rho_lambda_boundary(nr, extent[1], extent[0])
+        return np.kron(np.ones(nt), er)
     if geometry != "cylinder":
         return np.zeros(int(np.prod(n)))
     nr, nt, nz = n

@@ -70,6 +70,39 @@ def A_rho(n: int, d: int, rho_star: float = 1.0) -> np.ndarray:
     return tridiag(a, b, c)
 
 
+# --- rho of the anomalous operator Delta_lambda, eq. (A_lambda), Section 5.3 --
+# Delta_lambda = (1 - lambda) rho^-(1+lambda) d/drho + rho^-lambda d^2/drho^2
+# (+ rho^-(2+lambda) d^2/dtheta^2), homogeneous Dirichlet data at rho_* after
+# lifting.  lambda = 0 is the polar Laplacian on the Dirichlet grid.
+
+def rho_lambda_grid(n: int, lam: float, rho_star: float = 1.0) -> np.ndarray:
+    """rho_i = (1 - lambda) h / 2 + (i - 1) h, h = rho_* / (n + (1 - lambda) / 2)."""
+    s = 0.5 * (1.0 - lam)
+    h = rho_star / (n + s)
+    return s * h + h * np.arange(n)
+
+
+def A_rho_lambda(n: int, lam: float, rho_star: float = 1.0) -> np.ndarray:
+    """Tridiagonal A_lambda of eq. (A_lambda) in the layout of eq. (tridiag)
+    (a diagonal, b super-, c sub-diagonal)."""
+    s = 0.5 * (1.0 - lam)
+    h = rho_star / (n + s)
+    hp = h ** (2.0 + lam)
+    ell = np.arange(1, n + 1, dtype=float)
+    a = -2.0 / ((s + ell - 1.0) ** lam * hp)
+    l = np.arange(1, n, dtype=float)
+    b = (1.0 - lam + l - 1.0) / ((s + l - 1.0) ** (1.0 + lam) * hp)
+    c = l / ((s + l) ** (1.0 + lam) * hp)
+    return tridiag(a, b, c)
+
+
+def rho_lambda_boundary(n: int, lam: float, rho_star: float = 1.0) -> float:
+    """b_n: the coefficient of the Dirichlet value at rho_* in the last row."""
+    s = 0.5 * (1.0 - lam)
+    h = rho_star / (n + s)
+    return (1.0 - lam + n - 1.0) / ((s + n - 1.0) ** (1.0 + lam) * h ** (2.0 + lam))
+
+
 # --- phi: polar angle on (0, pi), eqs. (syscn), (A_phi), Appendix A ---------
 
 def sigma_phi(n: int) -> float:
@@ -138,8 +171,16 @@ def symmetriser(A: np.ndarray) -> np.ndarray:
 
 
 def operators_1d(geometry: str, n, extent=(1.0, 1.0)):
-    """Per-mode dense 1D operators and grids for a geometry (paper order)."""
+    """Per-mode dense 1D operators and grids for a geometry (paper order).
+
+    ``extent`` = (rho_*, z_*); for "disk_lambda" (the anomalous operator of
+    Section 5.3) the second entry is lambda.
+    """
     rho_star, z_star = extent
+    if geometry == "disk_lambda":
+        nr, nt = n
+        return {"A": [A_rho_lambda(nr, z_star, rho_star), A_theta(nt)],
+                "grid": [rho_lambda_grid(nr, z_star, rho_star), theta_grid(nt)]}
     if geometry == "disk":
         nr, nt = n
         return {"A": [A_rho(nr, 2, rho_star), A_theta(nt)],

@@ -29,6 +29,21 @@ def schnakenberg_jacobian(U, a, b):
     return [[-1.0 + 2.0 * u * v, u * u], [-2.0 * u * v, -u * u]]
 
 
+# --- Schnakenberg kinetics with the factor alpha_1, eqs. (schnaksys), (schnaknl)
+# (Section 5.3): g = alpha_1 (b(u, v), c(u, v)); p = (alpha_2, beta_1, alpha_1).
+
+def schnakenberg_scaled(U, a, b, gamma):
+    return [gamma * g for g in schnakenberg(U, a, b)]
+
+
+def schnakenberg_scaled_equilibrium(a, b, gamma):
+    return schnakenberg_equilibrium(a, b)
+
+
+def schnakenberg_scaled_jacobian(U, a, b, gamma):
+    return [[gamma * x for x in row] for row in schnakenberg_jacobian(U, a, b)]
+
+
 # --- BVAM kinetics, eq. (BVAMnl) ---------------------------------------------
 
 BVAM_FIG1 = dict(gamma=3.87e-3, delta=7.5e-3, alpha1=8.99e-1, alpha2=2e-1,
@@ -99,6 +114,7 @@ def ais3_jacobian(U, a, b, kappa, mu):
 MODELS = {
     "schnakenberg": (schnakenberg, schnakenberg_equilibrium, schnakenberg_jacobian),
     "ais3": (ais3, ais3_equilibrium, ais3_jacobian),
+    "schnakenberg_scaled": (schnakenberg_scaled, schnakenberg_scaled_equilibrium, schnakenberg_scaled_jacobian),
 }
 
 

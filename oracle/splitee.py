@@ -38,7 +38,8 @@ class SplitEE:
     """Split exponential Euler for one geometry, grid and set of species.
 
     ``diff`` holds d_s per species.  ``extent`` = (rho_*, z_*); for the
-    sphere rho_* is its radius (operator scaled by rho_*^-2).
+    sphere rho_* is its radius (operator scaled by rho_*^-2); for
+    "disk_lambda" the second entry is lambda (Section 5.3).
     """
 
     def __init__(self, geometry, n, diff, tau, extent=(1.0, 1.0)):
@@ -58,9 +59,10 @@ class SplitEE:
     def _build_factors(self):
         g, A, tau = self.geometry, self.A, self.tau
         self.f = []  # per species dict of factors
-        if g == "disk":
+        if g in ("disk", "disk_lambda"):
             lam_t, Q, _ = eig_tridiag(A[1])
-            rinv2 = self.grid[0] ** -2.0
+            # D_rho: rho^-2, or rho^(-2-lambda) for the anomalous operator
+            rinv2 = self.grid[0] ** (-2.0 - (self.extent[1] if g == "disk_lambda" else 0.0))
             for d in self.diff:
                 self.f.append({
                     "P_rho": phi1_matrix(A[0], tau * d),
@@ -115,7 +117,7 @@ class SplitEE:
     def split_phi1(self, F: np.ndarray, s: int = 0) -> np.ndarray:
         """phi_1(tau d_s M_1) ... phi_1(tau d_s M_d) F in the paper's tensor form."""
         g, f = self.geometry, self.f[s]
-        if g == "disk":  # eq. (ee_disk): phi1(tau A_rho) (Phi o (F Q)) Q^T
+        if g in ("disk", "disk_lambda"):  # eq. (ee_disk): phi1(tau A_rho) (Phi o (F Q)) Q^T
             Y = f["Phi_rt"] * (F @ self.Q)
             return f["P_rho"] @ (Y @ self.Q.T)
         if g == "sphere":  # eq. (ee_sphere): Q (Phi o (Q^T F phi1(tau A_phi)^T))
@@ -182,7 +184,7 @@ def run(workload, perturbation: np.ndarray, steps: int, n=None, callback=None):
     se = make(workload, n)
     eq = reactions.equilibrium(workload.reaction, workload.params)
     Ws = initial_state(workload, perturbation)
-    wd = eq if workload.geometry == "cylinder" else None
+    wd = eq if workload.geometry in ("cylinder", "disk_lambda") else None
     react = lambda U: reactions.reaction(workload.reaction, U, workload.params)  # noqa: E731
     for it in range(steps):
         Ws = se.step(Ws, react, w_dirichlet=wd)

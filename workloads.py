@@ -21,7 +21,7 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-GEOMETRIES = ("disk", "sphere", "ball", "cylinder")
+GEOMETRIES = ("disk", "sphere", "ball", "cylinder", "disk_lambda")
 
 
 @dataclasses.dataclass(frozen=True)
@@ -29,7 +29,7 @@ class Workload:
     """One synthetic problem instance family.
 
     ``n`` is the grid in the paper's coordinate order:
-      disk (n_rho, n_theta); sphere (n_theta, n_phi);
+      disk and disk_lambda (n_rho, n_theta); sphere (n_theta, n_phi);
       ball (n_rho, n_theta, n_phi); cylinder (n_rho, n_theta, n_z).
     ``reaction`` names the kinetics ("schnakenberg" or "ais3": a 3-species
     activator-inhibitor-substrate system); ``params`` are its constants,
@@ -46,7 +46,7 @@ class Workload:
     steps: int
     seed: int
     amplitude: float = 1e-3
-    extent: Tuple[float, float] = (1.0, 1.0)  # (rho_*, z_*)
+    extent: Tuple[float, float] = (1.0, 1.0)  # (rho_*, z_*); disk_lambda: (rho_*, lambda)
     batch: int = 1
 
     @property
@@ -70,6 +70,9 @@ class Workload:
 # inhibitor workloads; the 3-species model constants are (a, b, kappa, mu).
 SCHNAK = (0.1, 0.9)
 AIS3 = (0.1, 0.9, 0.5, 1.0)
+# anomalous-diffusion disk (Section 5.3): (alpha_2, beta_1, alpha_1) and lambda
+SCHNAK_ANOMALOUS = (0.14, 1.34, 500.0)
+ANOMALOUS_LAMBDA = -1.95
 
 WORKLOADS: Dict[str, Workload] = {
     "disk_32x64": Workload("disk_32x64", "disk", (32, 64), "schnakenberg",
@@ -89,6 +92,14 @@ WORKLOADS: Dict[str, Workload] = {
     "disk_256x512": Workload("disk_256x512", "disk", (256, 512),
                              "schnakenberg", SCHNAK, (1.0, 20.0), 1e-2, 400,
                              seed=6),
+    # Section 5.3: anomalous diffusion Delta_lambda, lambda = -1.95, on the
+    # unit disk with Dirichlet data at the equilibrium; kinetics alpha_1 (b, c)
+    # with (alpha_2, beta_1, alpha_1) = (0.14, 1.34, 500), d = (1, delta = 50),
+    # t_* = 2.5 in m = 25000 steps, perturbation 1e-5 U(0, 1)
+    "disk_lambda_160x160": Workload("disk_lambda_160x160", "disk_lambda", (160, 160),
+                                    "schnakenberg_scaled", SCHNAK_ANOMALOUS, (1.0, 50.0),
+                                    1e-4, 25000, seed=8, amplitude=1e-5,
+                                    extent=(1.0, ANOMALOUS_LAMBDA)),
 }
 
 
