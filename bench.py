@@ -153,6 +153,19 @@ def other_workloads(tg, torch, steps):
         out[f"cylinder_100x100x100_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s",
                                                "ms_per_step": sec * 1e3, "dof": wl.dof}
         del plan, x
+    # 160 x 160 anomalous-diffusion disk (lambda = -1.95), FP64 and FP32
+    wl = workloads.WORKLOADS["disk_lambda_160x160"]
+    grid = tg.Grid(wl.geometry, wl.n, wl.extent)
+    for prec in ("fp64", "fp32"):
+        plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, prec)
+        x = plan.state_from_deviation(workloads.perturbation(wl)[None])
+        plan.autotune(x, iters=10)
+        plan.run(x, 16)
+        sec = time_gpu_run(plan, x, steps, 0, torch)
+        out[f"disk_lambda_160x160_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s",
+                                              "ms_per_step": sec * 1e3, "dof": wl.dof,
+                                              "route": plan.route}
+        del plan, x
     # 256 x 512 disk: FP32 forward + checkpointed reverse sweep, 400 steps
     from paper_2604_11558_amd.autograd import integrate
     wl = workloads.WORKLOADS["disk_256x512"]

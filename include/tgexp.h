@@ -57,7 +57,11 @@ enum {
   TG_ENONFINITE = -5  /* a non-finite value was produced by the update */
 };
 
-enum { TG_DISK = 0, TG_SPHERE = 1, TG_BALL = 2, TG_CYLINDER = 3 };
+/* Geometries (Section 2, eqs. (disk)-(cylinder)); TG_DISK_LAMBDA is the
+ * unit-radius-scaled disk with the anomalous operator Delta_lambda of
+ * Section 5.3 (eqs. (anomalous), (A_lambda)): radial operator A_lambda with
+ * Dirichlet data at rho_*, D_rho = rho^(-2-lambda), periodic theta. */
+enum { TG_DISK = 0, TG_SPHERE = 1, TG_BALL = 2, TG_CYLINDER = 3, TG_DISK_LAMBDA = 4 };
 
 /* Arithmetic of the mu-mode products.  Factors are always computed in
  * FP64 on the host and rounded to the storage type.
@@ -77,8 +81,11 @@ enum { TG_FP64 = 0, TG_FP32 = 1, TG_BF16X2 = 2, TG_BF16X3 = 3 };
  *       (a + b, b / (a + b)^2).
  *   TG_REACT_AIS3: (a, b, kappa, mu), three species (u, v, w):
  *       g_u = a - u + u^2 v - kappa u w, g_v = b - u^2 v, g_w = mu (u - w).
+ *   TG_REACT_SCHNAKENBERG_SCALED: (a, b, gamma): gamma times the
+ *       Schnakenberg terms (eqs. (schnaksys), (schnaknl): a = alpha_2,
+ *       b = beta_1, gamma = alpha_1); same equilibrium.
  *   TG_REACT_NONE: g = 0 (pure diffusion). */
-enum { TG_REACT_NONE = 0, TG_REACT_SCHNAKENBERG = 1, TG_REACT_AIS3 = 2 };
+enum { TG_REACT_NONE = 0, TG_REACT_SCHNAKENBERG = 1, TG_REACT_AIS3 = 2, TG_REACT_SCHNAKENBERG_SCALED = 3 };
 
 /* tg_apply_operator selectors */
 enum { TG_APPLY_F = 0, TG_APPLY_DIFFUSION = 1, TG_APPLY_REACTION = 2 };
@@ -94,7 +101,9 @@ int tg_version(void);
 /* ---- grid and operator set-up (host, FP64) ------------------------------
  * extent = {rho_*, z_*}: radius of disk / ball / cylinder, or of the sphere
  * (its operator is scaled by rho_*^-2), and the cylinder height (ignored
- * elsewhere).  NULL means {1, 1}.  Section 3, Table 1. */
+ * elsewhere).  NULL means {1, 1}.  Section 3, Table 1.  For TG_DISK_LAMBDA
+ * extent = {rho_*, lambda} is required, with lambda < 1 (the first grid
+ * point (1 - lambda) h / 2 must be positive). */
 int tg_grid_create(int32_t geometry, const int32_t* n, const double* extent, tg_grid* out);
 int tg_grid_destroy(tg_grid g);
 /* ndim (2 or 3) and the n[] of the grid (n must hold 3 ints). */
@@ -144,7 +153,8 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
  *   grad[s]         += tau <lambda_s, (dS_s/dd_s) F_s> + <mu_s, M W_n,s>
  *   grad[nslab + s] += sum over points of mu_s (the derivative with respect
  *                      to a constant source in species s' reaction: the
- *                      Schnakenberg and 3-species constants a and b)
+ *                      Schnakenberg and 3-species constants a and b; for
+ *                      TG_REACT_SCHNAKENBERG_SCALED, dL/da = gamma times it)
  * where nslab = batch * n_species, F_s = d_s M W_n,s + g_s(W_n) and the
  * old lambda_s is used on the right.  state_n: the state at step n (input,
  * device, plan layout); lambda: dL/dW_{n+1} in, dL/dW_n out (device, same

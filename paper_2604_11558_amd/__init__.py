@@ -16,11 +16,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtgexp.so")
 
-GEOMETRY = {"disk": 0, "sphere": 1, "ball": 2, "cylinder": 3}
+GEOMETRY = {"disk": 0, "sphere": 1, "ball": 2, "cylinder": 3, "disk_lambda": 4}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
-REACTION = {"none": 0, "schnakenberg": 1, "ais3": 2}
+REACTION = {"none": 0, "schnakenberg": 1, "ais3": 2, "schnakenberg_scaled": 3}
 APPLY = {"F": 0, "diffusion": 1, "reaction": 2}
-NDIM = {"disk": 2, "sphere": 2, "ball": 3, "cylinder": 3}
+NDIM = {"disk": 2, "sphere": 2, "ball": 3, "cylinder": 3, "disk_lambda": 2}
 ROUTES = {"fused": 0, "generic": 1, "fused_stencil_apart": 2}
 
 _c_int = ctypes.c_int32

@@ -102,14 +102,15 @@ std::vector<double> transpose(const std::vector<double>& A, int n) {
 double tg_grid_s::extent_of(int mode) const {
   switch (coord[mode]) {
     case tg::RHO2:
-    case tg::RHO3: return extent[0];
+    case tg::RHO3:
+    case tg::RHO_LAMBDA: return extent[0];
     case tg::ZED: return extent[1];
     default: return 1.0;
   }
 }
-tg::Tridiag tg_grid_s::op(int mode) const { return tg::coord_operator(coord[mode], n[mode], extent_of(mode)); }
+tg::Tridiag tg_grid_s::op(int mode) const { return tg::coord_operator(coord[mode], n[mode], extent_of(mode), lam); }
 std::vector<double> tg_grid_s::coords(int mode) const {
-  return tg::coord_grid(coord[mode], n[mode], extent_of(mode));
+  return tg::coord_grid(coord[mode], n[mode], extent_of(mode), lam);
 }
 tg::Eig tg_grid_s::eig(int mode) const {
   if (coord[mode] == tg::THETA) return tg::eig_theta(n[mode]);
@@ -124,6 +125,8 @@ int tg_version(void) { return 1; }
 int tg_grid_create(int32_t geometry, const int32_t* n, const double* extent, tg_grid* out) {
   return guarded([&] {
     TG_REQUIRE(n && out, TG_EINVAL, "tg_grid_create: null pointer");
+    TG_REQUIRE(geometry != TG_DISK_LAMBDA || extent, TG_EINVAL,
+               "tg_grid_create: the anomalous disk needs extent = (rho_*, lambda)");
     auto g = new tg_grid_s();
     g->geometry = geometry;
     switch (geometry) {
@@ -131,6 +134,7 @@ int tg_grid_create(int32_t geometry, const int32_t* n, const double* extent, tg_
       case TG_SPHERE: g->ndim = 2; g->coord[0] = tg::THETA; g->coord[1] = tg::PHI; break;
       case TG_BALL: g->ndim = 3; g->coord[0] = tg::RHO3; g->coord[1] = tg::THETA; g->coord[2] = tg::PHI; break;
       case TG_CYLINDER: g->ndim = 3; g->coord[0] = tg::RHO2; g->coord[1] = tg::THETA; g->coord[2] = tg::ZED; break;
+      case TG_DISK_LAMBDA: g->ndim = 2; g->coord[0] = tg::RHO_LAMBDA; g->coord[1] = tg::THETA; break;
       default: delete g; throw Fail(TG_EINVAL, "tg_grid_create: unknown geometry");
     }
     for (int m = 0; m < g->ndim; ++m) {
@@ -140,7 +144,15 @@ int tg_grid_create(int32_t geometry, const int32_t* n, const double* extent, tg_
       }
       g->n[m] = n[m];
     }
-    if (extent) {
+    if (geometry == TG_DISK_LAMBDA) {
+      // extent = (rho_*, lambda); the grid needs (1 - lambda) / 2 > 0
+      if (!(extent[0] > 0.0) || !(extent[1] < 1.0) || !std::isfinite(extent[1])) {
+        delete g;
+        throw Fail(TG_EINVAL, "tg_grid_create: anomalous disk needs rho_* > 0 and lambda < 1");
+      }
+      g->extent[0] = extent[0];
+      g->lam = extent[1];
+    } else if (extent) {
       if (!(extent[0] > 0.0) || !(extent[1] > 0.0)) {
         delete g;
         throw Fail(TG_EINVAL, "tg_grid_create: extents must be positive");
@@ -224,7 +236,7 @@ namespace {
 
 std::vector<double> default_reference(int reaction, int ns, const double* rp) {
   std::vector<double> w(ns, 0.0);
-  if (reaction == TG_REACT_SCHNAKENBERG) {
+  if (reaction == TG_REACT_SCHNAKENBERG || reaction == TG_REACT_SCHNAKENBERG_SCALED) {
     const double a = rp[0], b = rp[1];
     w[0] = a + b;
     w[1] = b / ((a + b) * (a + b));
@@ -244,6 +256,10 @@ std::vector<double> reaction_at(int reaction, int ns, const double* rp, const do
     const double u2v = w[0] * w[0] * w[1];
     g[0] = rp[0] - w[0] + u2v;
     g[1] = rp[1] - u2v;
+  } else if (reaction == TG_REACT_SCHNAKENBERG_SCALED) {
+    const double u2v = w[0] * w[0] * w[1];
+    g[0] = rp[2] * (rp[0] - w[0] + u2v);
+    g[1] = rp[2] * (rp[1] - u2v);
   } else if (reaction == TG_REACT_AIS3) {
     const double u2v = w[0] * w[0] * w[1];
     g[0] = rp[0] - w[0] + u2v - rp[2] * w[0] * w[2];
@@ -413,8 +429,13 @@ void build_plan(tg_plan_s* P) {
   };
   std::vector<FSpec> fspecs;
 
-  if (G.geometry == TG_DISK) {  // eq. (ee_disk)
+  if (G.geometry == TG_DISK || G.geometry == TG_DISK_LAMBDA) {  // eq. (ee_disk)
+    // D_rho: rho^-2, or rho^(-2-lambda) for the anomalous operator (Section 5.3)
     auto rinv2 = inv2(G.coords(0));
+    if (G.geometry == TG_DISK_LAMBDA) {
+      const auto r = G.coords(0);
+      for (size_t i = 0; i < rinv2.size(); ++i) rinv2[i] = std::pow(r[i], -2.0 - G.lam);
+    }
     set_scale(1, 0, rinv2);
     auto et = G.eig(1);
     auto er = G.eig(0);
@@ -1275,6 +1296,7 @@ int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* di
       case TG_REACT_NONE: need_ns = -1; need_np = 0; break;
       case TG_REACT_SCHNAKENBERG: need_ns = 2; need_np = 2; break;
       case TG_REACT_AIS3: need_ns = 3; need_np = 4; break;
+      case TG_REACT_SCHNAKENBERG_SCALED: need_ns = 2; need_np = 3; break;
       default: throw Fail(TG_EINVAL, "tg_plan_create: unknown reaction");
     }
     TG_REQUIRE(n_species >= 1 && n_species <= 3, TG_EINVAL, "tg_plan_create: 1 to 3 species");

@@ -41,7 +41,7 @@ double sigma_phi(int n) {
   return std::fabs(f(a)) < std::fabs(f(b)) ? a : b;
 }
 
-std::vector<double> coord_grid(Coord c, int n, double extent) {
+std::vector<double> coord_grid(Coord c, int n, double extent, double lam) {
   std::vector<double> g(n);
   switch (c) {
     case RHO2: {  // half-point grid, h = rho_* / (n - 1/2)
@@ -52,6 +52,12 @@ std::vector<double> coord_grid(Coord c, int n, double extent) {
     case RHO3: {  // rho_i = i h, h = rho_* / n
       const double h = extent / n;
       for (int i = 0; i < n; ++i) g[i] = (i + 1) * h;
+      break;
+    }
+    case RHO_LAMBDA: {  // rho_i = (1 - lambda) h / 2 + (i - 1) h, h = rho_* / (n + (1 - lambda) / 2)
+      const double s = 0.5 * (1.0 - lam);
+      const double h = extent / (n + s);
+      for (int i = 0; i < n; ++i) g[i] = (s + i) * h;
       break;
     }
     case THETA: {  // theta_j = j h, h = 2 pi / n
@@ -74,7 +80,7 @@ std::vector<double> coord_grid(Coord c, int n, double extent) {
   return g;
 }
 
-Tridiag coord_operator(Coord c, int n, double extent) {
+Tridiag coord_operator(Coord c, int n, double extent, double lam) {
   if (n < 3) throw std::invalid_argument("grid needs at least 3 points per coordinate");
   Tridiag T;
   T.n = n;
@@ -96,6 +102,18 @@ Tridiag coord_operator(Coord c, int n, double extent) {
       set_bc([&](int l) { return 2.0 * l / ((2.0 * l - 1.0) * h2); },
              [&](int l) { return l == n - 1 ? 2.0 / h2 : 2.0 * l / ((2.0 * l + 1.0) * h2); },
              -2.0 / h2);
+      break;
+    }
+    case RHO_LAMBDA: {
+      // eq. (A_lambda), 1-based l: a_l = -2 / ((s+l-1)^lam h^(2+lam)),
+      // b_l = (1-lam+l-1) / ((s+l-1)^(1+lam) h^(2+lam)), c_l = l / ((s+l)^(1+lam) h^(2+lam))
+      const double s = 0.5 * (1.0 - lam);
+      const double h = extent / (n + s), hp = std::pow(h, 2.0 + lam);
+      for (int r = 0; r < n; ++r) T.dg[r] = -2.0 / (std::pow(s + r, lam) * hp);
+      for (int l = 1; l <= n - 1; ++l) {
+        T.up[l - 1] = (1.0 - lam + l - 1.0) / (std::pow(s + l - 1.0, 1.0 + lam) * hp);
+        T.lo[l] = l / (std::pow(s + l, 1.0 + lam) * hp);
+      }
       break;
     }
     case RHO3: {

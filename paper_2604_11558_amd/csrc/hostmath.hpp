@@ -26,13 +26,16 @@ struct Eig {
   std::vector<double> lam, V, Vinv;
 };
 
-enum Coord { RHO2 = 0, RHO3 = 1, THETA = 2, PHI = 3, ZED = 4 };
+// RHO_LAMBDA: the radial part of the anomalous operator Delta_lambda with
+// Dirichlet data at rho_* (Section 5.3, eq. (A_lambda)); its lambda is the
+// extra argument below.
+enum Coord { RHO2 = 0, RHO3 = 1, THETA = 2, PHI = 3, ZED = 4, RHO_LAMBDA = 5 };
 
 // Grid points of one coordinate (paper eqs. (A_theta), (disk_discr),
-// (ball_discr), (A_phi), (A_z)).
-std::vector<double> coord_grid(Coord c, int n, double extent);
+// (ball_discr), (A_phi), (A_z), (A_lambda)).
+std::vector<double> coord_grid(Coord c, int n, double extent, double lam = 0.0);
 // The matching tridiagonal operator.
-Tridiag coord_operator(Coord c, int n, double extent);
+Tridiag coord_operator(Coord c, int n, double extent, double lam = 0.0);
 // sigma of system (syscn): root in (0, 1/2) (Appendix A).
 double sigma_phi(int n);
 

@@ -319,11 +319,12 @@ __global__ __launch_bounds__(256) void adjoint_combine_kernel(AdjointArgs a) {
   const double* wr = a.wref + inst * ns;
   double m[3] = {0, 0, 0}, jt[3] = {0, 0, 0};
   for (int q = 0; q < ns && q < 3; ++q) m[q] = static_cast<double>(mu[q * a.npts]);
-  if (a.reaction == 1) {  // g_u = a - u + u^2 v,  g_v = b - u^2 v
+  if (a.reaction == 1 || a.reaction == 3) {  // (gamma times) g_u = a - u + u^2 v,  g_v = b - u^2 v
+    const double gam = a.reaction == 3 ? a.rparams[inst * 4 + 2] : 1.0;
     const double u = wr[0] + static_cast<double>(st[0]);
     const double v = wr[1] + static_cast<double>(st[a.npts]);
-    jt[0] = (-1.0 + 2.0 * u * v) * m[0] - 2.0 * u * v * m[1];
-    jt[1] = u * u * m[0] - u * u * m[1];
+    jt[0] = gam * ((-1.0 + 2.0 * u * v) * m[0] - 2.0 * u * v * m[1]);
+    jt[1] = gam * (u * u * m[0] - u * u * m[1]);
   } else if (a.reaction == 2) {  // + kappa u w and mu (u - w) terms
     const double* rp = a.rparams + inst * 4;
     const double kap = rp[2], mup = rp[3];

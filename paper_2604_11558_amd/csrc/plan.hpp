@@ -17,6 +17,7 @@ struct tg_grid_s {
   int ndim = 0;
   int n[3] = {1, 1, 1};
   double extent[2] = {1.0, 1.0};
+  double lam = 0.0;  // lambda of the anomalous disk (TG_DISK_LAMBDA)
   tg::Coord coord[3] = {tg::RHO2, tg::THETA, tg::PHI};
   double extent_of(int mode) const;          // 0-based mode
   tg::Tridiag op(int mode) const;            // 0-based mode, unscaled

@@ -19,9 +19,10 @@ __device__ __forceinline__ void reaction3(const StencilArgs& a, int inst, double
   const double* g0 = a.g0 + inst * ns;
   const double ur = wr[0], vr = wr[1];
   const double N = ur * ur * dq + 2.0 * ur * vr * dp + 2.0 * ur * dp * dq + vr * dp * dp + dp * dp * dq;
-  if (a.reaction == 1) {  // Schnakenberg: a - u + u^2 v,  b - u^2 v
-    G0 = g0[0] - dp + N;
-    G1 = g0[1] - N;
+  if (a.reaction == 1 || a.reaction == 3) {  // (gamma times) Schnakenberg: a - u + u^2 v,  b - u^2 v
+    const double gam = a.reaction == 3 ? rp[2] : 1.0;
+    G0 = g0[0] + gam * (N - dp);
+    G1 = g0[1] - gam * N;
     G2 = 0.0;
   } else {  // a - u + u^2 v - kappa u w,  b - u^2 v,  mu (u - w)
     const double kap = rp[2], mu = rp[3];
@@ -36,7 +37,7 @@ __device__ __forceinline__ void reaction3(const StencilArgs& a, int inst, double
 // their loads are issued together at the start of a kernel.
 struct ReactConst {
   int reaction;
-  double ur, vr, wr, g0, g1, g2, kap, mu;
+  double ur, vr, wr, g0, g1, g2, kap, mu, gam;
 };
 
 __device__ __forceinline__ ReactConst react_const(const StencilArgs& a, int inst) {
@@ -54,6 +55,7 @@ __device__ __forceinline__ ReactConst react_const(const StencilArgs& a, int inst
   c.g2 = ns > 2 ? g0[2] : 0.0;
   c.kap = rp[2];
   c.mu = rp[3];
+  c.gam = c.reaction == 3 ? rp[2] : 1.0;
   return c;
 }
 
@@ -62,9 +64,9 @@ __device__ __forceinline__ void reaction3c(const ReactConst& c, double dp, doubl
                                            double& G1, double& G2) {
   const double ur = c.ur, vr = c.vr;
   const double N = ur * ur * dq + 2.0 * ur * vr * dp + 2.0 * ur * dp * dq + vr * dp * dp + dp * dp * dq;
-  if (c.reaction == 1) {
-    G0 = c.g0 - dp + N;
-    G1 = c.g1 - N;
+  if (c.reaction == 1 || c.reaction == 3) {
+    G0 = c.g0 + c.gam * (N - dp);
+    G1 = c.g1 - c.gam * N;
     G2 = 0.0;
   } else {
     G0 = c.g0 - dp + N - c.kap * (ur * dr + c.wr * dp + dp * dr);

@@ -5,7 +5,7 @@ from types import SimpleNamespace
 import numpy as np
 import pytest
 
-from gpu_helpers import Case, adjoint_tol
+from gpu_helpers import DIRICHLET, Case, adjoint_tol
 from oracle import adjoint, assemble
 
 torch = pytest.importorskip("torch")
@@ -33,7 +33,7 @@ def _grads(case, steps, segment, target_layout, adjoint_precision="fp64"):
 def _oracle(case, steps, target):
     wl = SimpleNamespace(geometry=case.geometry, reaction=case.kind, tau=case.tau, extent=case.extent,
                          diff=tuple(case.diff[0]), params=tuple(case.params[0]), n=case.n)
-    wd = case.eq[0] if case.geometry == "cylinder" else None
+    wd = case.eq[0] if case.geometry in DIRICHLET else None
     L0, lam0, gd, gp = adjoint.loss_and_grad(wl, case.oracle_full(0), target, steps, w_dirichlet=wd)
     return L0, np.stack([assemble.to_layout(x) for x in lam0]), gd, gp[:2]
 

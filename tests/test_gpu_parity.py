@@ -17,6 +17,7 @@ GRIDS = [
     ("sphere", (70, 45)), ("sphere", (3, 4)),
     ("ball", (20, 24, 37)), ("ball", (3, 3, 3)),
     ("cylinder", (27, 30, 19)), ("cylinder", (3, 4, 3)),
+    ("disk_lambda", (37, 70)), ("disk_lambda", (3, 3)),
 ]
 TOL = {"fp64": 1e-12, "fp32": 2e-6}
 
@@ -42,7 +43,7 @@ def test_diffusion_operator(geometry, n, precision):
         assert err < (1e-13 if precision == "fp64" else 1e-6), err
 
 
-@pytest.mark.parametrize("geometry,n", GRIDS[:3] + [("cylinder", (27, 30, 19))])
+@pytest.mark.parametrize("geometry,n", GRIDS[:3] + [("cylinder", (27, 30, 19)), ("disk_lambda", (37, 70))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_reaction(geometry, n, precision):
     ns = 3 if geometry == "cylinder" else 2
@@ -134,7 +135,7 @@ def test_equilibrium_is_stationary():
 # over the measured errors.
 BF16_TOL = {"bf16x2": {"split": 6e-5, "steps": 1.5e-6}, "bf16x3": {"split": 3.5e-6, "steps": 3e-8}}
 BF16_GRIDS = [("disk", (37, 70)), ("sphere", (70, 45)), ("ball", (20, 24, 37)),
-              ("cylinder", (27, 30, 19)), ("ball", (64, 64, 128))]
+              ("cylinder", (27, 30, 19)), ("ball", (64, 64, 128)), ("disk_lambda", (37, 70))]
 
 
 @pytest.mark.parametrize("geometry,n", BF16_GRIDS)

@@ -1,7 +1,8 @@
 """The benchmark-sized workloads against the FP64 oracle, at their full grid
 sizes: the 32 x 64 disk (all 100 steps), the 64 x 64 x 128 ball in
-lockstep with the oracle (error after every step), the 100^3 cylinder with
-three species in split-bf16, and the gradient of the 256 x 512 disk."""
+lockstep with the oracle (error after every step), the 160 x 160
+anomalous-diffusion disk, the 100^3 cylinder with three species in
+split-bf16, and the gradient of the 256 x 512 disk."""
 from types import SimpleNamespace
 
 import numpy as np
@@ -28,7 +29,7 @@ def _setup(w, precision, n_steps_note=""):
 def _oracle_stepper(w, eq):
     se = splitee.make(w)
     react = lambda U: reactions.reaction(w.reaction, U, w.params)  # noqa: E731
-    wd = eq if w.geometry == "cylinder" else None
+    wd = eq if w.geometry in ("cylinder", "disk_lambda") else None
     return lambda W: se.step(W, react, w_dirichlet=wd)
 
 
@@ -67,6 +68,28 @@ def test_ball_64x64x128_lockstep_errors():
         worst["fp64"] = max(worst["fp64"], e64)
         worst["fp32"] = max(worst["fp32"], e32)
     assert worst["fp64"] < 1e-12 and worst["fp32"] < 2e-7, worst
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-7)])
+def test_disk_lambda_160x160(precision, tol):
+    """The anomalous-diffusion disk (lambda = -1.95, alpha_1 = 500 kinetics)
+    at full size, 200 steps; errors also relative to the deviation from the
+    lifted equilibrium, which is what the steps change."""
+    w = workloads.WORKLOADS["disk_lambda_160x160"]
+    plan, x, W, eq = _setup(w, precision)
+    steps = 200
+    plan.run(x, steps)
+    step = _oracle_stepper(w, eq)
+    for _ in range(steps):
+        W = step(W)
+    ref = np.stack([assemble.to_layout(u) for u in W])
+    got = _full(plan, x)
+    err = rel_err(got, ref)
+    dev = ref - np.asarray(eq).reshape(-1, 1, 1)
+    dev_err = float(np.abs(got - ref).max() / np.abs(dev).max())
+    print("disk_lambda 160x160 %s, %d steps: %.2e (deviation-relative %.2e)" % (precision, steps, err, dev_err))
+    assert err < tol
+    assert dev_err < (1e-8 if precision == "fp64" else 1e-3)
 
 
 # split-bf16 on the cylinder (100 points per mode, d_w = 40): operand

@@ -31,7 +31,9 @@ def _oracle_ops(geometry, n, extent):
 
 CASES = [("disk", (7, 12), (1.3, 1.0)), ("sphere", (10, 9), (1.0, 1.0)),
          ("ball", (8, 6, 11), (0.8, 1.0)), ("cylinder", (9, 10, 7), (1.2, 2.5)),
-         ("ball", (64, 64, 128), (1.0, 1.0))]
+         ("ball", (64, 64, 128), (1.0, 1.0)),
+         ("disk_lambda", (9, 12), (1.0, -1.95)), ("disk_lambda", (11, 8), (1.3, 0.5)),
+         ("disk_lambda", (160, 160), (1.0, -1.95))]
 
 
 @pytest.mark.parametrize("geometry,n,extent", CASES)
@@ -57,7 +59,7 @@ def test_eigendecomposition(geometry, n, extent):
                                    atol=1e-11 * scale)
 
 
-@pytest.mark.parametrize("geometry,n,extent", CASES[:4])
+@pytest.mark.parametrize("geometry,n,extent", CASES[:4] + CASES[5:7])
 @pytest.mark.parametrize("c", [1e-5, 3e-3, 0.2])
 def test_phi1_factor_matches_oracle(geometry, n, extent, c):
     g = tg.Grid(geometry, n, extent)
@@ -84,3 +86,7 @@ def test_invalid_grid(geometry, n):
 def test_invalid_extent():
     with pytest.raises(tg.TGError):
         tg.Grid("disk", (4, 4), (0.0, 1.0))
+    # the anomalous disk: extent = (rho_*, lambda) with lambda < 1
+    for ext in ((1.0, 1.0), (1.0, 2.0), (0.0, -1.0), (1.0, float("nan"))):
+        with pytest.raises(tg.TGError):
+            tg.Grid("disk_lambda", (4, 4), ext)
