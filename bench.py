@@ -153,6 +153,25 @@ def other_workloads(tg, torch, steps):
         out[f"cylinder_100x100x100_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s",
                                                "ms_per_step": sec * 1e3, "dof": wl.dof}
         del plan, x
+    # steady-state indicators on the 64 x 64 x 128 ball, FP32 (fused into the
+    # update launch plus one small summing launch per recorded step)
+    wl = workloads.WORKLOADS["ball_64x64x128"]
+    grid = tg.Grid(wl.geometry, wl.n, wl.extent)
+    plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, "fp32")
+    x = plan.state_from_deviation(workloads.perturbation(wl)[None])
+    plan.autotune(x, iters=10)
+    plain = time_gpu_run(plan, x, steps, 16, torch)
+    res = {"plain_ms_per_step": plain * 1e3}
+    for every in (1, 10):
+        plan.run_diag(x, 2 * every, every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = plan.run_diag(x, steps, every)
+        torch.cuda.synchronize()
+        res[f"every_{every}_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / steps
+        res[f"every_{every}_last_record"] = rec[-1, 0].cpu().numpy().tolist()
+    out["ball_64x64x128_fp32_indicators"] = res
+    del plan, x
     # 160 x 160 anomalous-diffusion disk (lambda = -1.95), FP64 and FP32
     wl = workloads.WORKLOADS["disk_lambda_160x160"]
     grid = tg.Grid(wl.geometry, wl.n, wl.extent)

@@ -146,6 +146,32 @@ int tg_step(tg_plan p, void* state, void* stream);
  * update produced a non-finite value. */
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
 
+/* Steady-state indicators (Section 5.2, the text after the disk experiment:
+ * the integral mean of the solution and the L2 norm of one step's
+ * increment), gathered in the step's last launch where the old and new
+ * values meet, plus one small launch that adds up per-tile partial sums in
+ * a fixed order (the results are reproducible run to run).
+ *
+ * Quadrature: each point owns the cell between the midpoints to its
+ * neighbours along every coordinate (the end cells closed at 0 and rho_*,
+ * 0 and pi, 0 and z_*; theta cells 2 pi / n wide), weighted by that cell's
+ * measure in the volume element (rho, rho_*^2 sin(phi), rho^2 sin(phi),
+ * rho), so the weights sum to |Omega|.
+ *
+ * tg_step_diag: one step as tg_step; diag is a device pointer to
+ * [batch][n_species][2] doubles, written on `stream`:
+ *   diag[.][.][0] = sum(w (w_ref + W_{n+1})) / sum(w)    (integral mean)
+ *   diag[.][.][1] = sqrt(sum(w (W_{n+1} - W_n)^2))        (increment)
+ * The first call allocates a partial-sum buffer of (npts / 8 + 64) * 2
+ * doubles per slab, kept by the plan; calls on one plan from different
+ * streams must not overlap.  TG_ENOTSUP for a grouped run (not offered). */
+int tg_step_diag(tg_plan p, void* state, double* diag, void* stream);
+/* n_steps steps; after steps every, 2 every, ... records the indicators of
+ * that step into diag[r][batch][n_species][2] (device memory for
+ * n_steps / every records).  The steps between records replay captured
+ * graphs.  Synchronises and checks for non-finite values like tg_run. */
+int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* diag, void* stream);
+
 /* Reverse step of the discrete adjoint of tg_step (not in the paper; the
  * exact derivative of the discrete map).  With mu_s = tau S_s^T lambda_s,
  * S_s = phi_1(tau d_s M_1) ... phi_1(tau d_s M_d):

@@ -47,6 +47,8 @@ _SIGNATURES = {
     "tg_plan_reference": (ctypes.c_int, [_p, _pd]),
     "tg_step": (ctypes.c_int, [_p, _p, _p]),
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
+    "tg_step_diag": (ctypes.c_int, [_p, _p, _p, _p]),
+    "tg_run_diag": (ctypes.c_int, [_p, _p, _c_i64, _c_int, _p, _p]),
     "tg_apply_operator": (ctypes.c_int, [_p, _p, _p, _c_int, _p]),
     "tg_apply_split_phi1": (ctypes.c_int, [_p, _p, _p, _p]),
     "tg_plan_chain": (ctypes.c_int, [_p, _pi, _pi, _pd]),
@@ -228,6 +230,26 @@ class Plan:
     def run(self, state, n_steps: int, stream=None):
         self._check_tensor(state)
         _check(lib().tg_run(self._h, state.data_ptr(), int(n_steps), _stream_ptr(stream)))
+
+    def step_diag(self, state, stream=None):
+        """One step; returns a [batch, n_species, 2] float64 device tensor of
+        (integral mean, L2 norm of the increment)."""
+        self._check_tensor(state)
+        import torch
+        out = torch.empty((self.batch, self.n_species, 2), dtype=torch.float64, device=state.device)
+        _check(lib().tg_step_diag(self._h, state.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def run_diag(self, state, n_steps: int, every: int = 1, stream=None):
+        """``n_steps`` steps; the indicators of steps every, 2 every, ... as a
+        [n_steps // every, batch, n_species, 2] float64 device tensor."""
+        self._check_tensor(state)
+        import torch
+        out = torch.empty((int(n_steps) // int(every), self.batch, self.n_species, 2), dtype=torch.float64,
+                          device=state.device)
+        _check(lib().tg_run_diag(self._h, state.data_ptr(), int(n_steps), int(every), out.data_ptr(),
+                                 _stream_ptr(stream)))
+        return out
 
     def run_timed(self, state, n_steps: int, stream=None):
         """``n_steps`` direct-launch steps; average microseconds of each launch of a step."""

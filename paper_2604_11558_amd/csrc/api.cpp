@@ -577,6 +577,20 @@ void build_plan(tg_plan_s* P) {
   const size_t o_coef = ar.add_d(coef), o_scale = ar.add_d(scale);
   const size_t o_diff = ar.add_d(P->diff), o_rp = ar.add_d(P->rparams);
   const size_t o_wref = ar.add_d(P->wref), o_g0 = ar.add_d(P->g0), o_cs = ar.add_d(cs);
+  // quadrature weights of the steady-state indicators (Section 5.2)
+  std::vector<double> w1 = tg::coord_weights(G.coord[0], n1, G.extent_of(0), G.lam);
+  if (G.geometry == TG_SPHERE)
+    for (auto& v : w1) v *= G.extent[0] * G.extent[0];
+  const auto w2 = tg::coord_weights(G.coord[1], n2, G.extent_of(1), G.lam);
+  const auto w3 = nd == 3 ? tg::coord_weights(G.coord[2], n3, G.extent_of(2), G.lam) : std::vector<double>(1, 1.0);
+  std::vector<double> w23(static_cast<size_t>(n2) * n3);
+  for (int k = 0; k < n3; ++k)
+    for (int j = 0; j < n2; ++j) w23[static_cast<size_t>(k) * n2 + j] = w2[j] * w3[k];
+  double s1 = 0.0, s23 = 0.0;
+  for (double v : w1) s1 += v;
+  for (double v : w23) s23 += v;
+  P->wsum_inv = 1.0 / (s1 * s23);
+  const size_t o_w1 = ar.add_d(w1), o_w23 = ar.add_d(w23);
 
   hip_check(hipMalloc(reinterpret_cast<void**>(&P->dmem), ar.bytes.size()), "hipMalloc(plan)");
   hip_check(hipMemcpy(P->dmem, ar.bytes.data(), ar.bytes.size(), hipMemcpyHostToDevice), "hipMemcpy(plan)");
@@ -592,6 +606,8 @@ void build_plan(tg_plan_s* P) {
   P->d_rd = D(o_rd);
   P->d_tau = D(o_tv);
   P->d_taurd = D(o_trd);
+  P->d_w1 = D(o_w1);
+  P->d_w23 = D(o_w23);
   const int nn[3] = {n1, n2, n3};
   for (const auto& o : ops) {
     tg::ChainOp c;
@@ -731,7 +747,7 @@ void build_plan(tg_plan_s* P) {
 // Launch one chain op reading X and writing Y (or updating Y += tau * acc).
 template <typename T>
 void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y, int epi, hipStream_t st,
-               double alpha = -1.0) {
+               double alpha = -1.0, const tg::DiagArgs* dg = nullptr) {
   const int nd = P->grid.ndim;
   const int nn[3] = {P->grid.n[0], P->grid.n[1], nd == 3 ? P->grid.n[2] : 1};
   int64_t na = 1, nb = 1;
@@ -770,6 +786,10 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
     g.b_sstride = slab; g.b_smod = big;
     g.c_sstride = slab;
     g.b_kcontig = 0;
+  }
+  if (dg) {
+    TG_REQUIRE(c.mode == 1 && epi == tg::EPI_UPDATE, TG_ENOTSUP, "indicators need a first-mode update");
+    g.dg = *dg;
   }
   mark_launch(st);
   hip_check(tg::launch_mode_gemm<T>(g, st), "mode product launch");
@@ -859,14 +879,20 @@ tg::FirstArgs first_args_for(const tg::FusedOp& op, const void* src, void* dst, 
 
 template <typename T>
 void launch_fused(const tg_plan_s* P, const tg::FusedOp& op, const void* src, void* dst, bool update,
-                  bool from_state, hipStream_t st) {
+                  bool from_state, hipStream_t st, const tg::DiagArgs* dg = nullptr) {
   const int nt = bf16_terms(P->precision);
+  TG_REQUIRE(!dg || update, TG_ENOTSUP, "indicators need an update launch");
   if (op.kind == 0) {
-    const tg::StridedArgs a = strided_args_for(P, op, src, dst, update, from_state);
+    tg::StridedArgs a = strided_args_for(P, op, src, dst, update, from_state);
+    if (dg) {
+      TG_REQUIRE(a.plane, TG_ENOTSUP, "indicators need a plane-tail update");
+      a.dg = *dg;
+    }
     mark_launch(st);
     hip_check(nt ? tg::launch_strided_bf16(nt, a, st) : tg::launch_strided<T>(a, st), "fused strided launch");
   } else {
-    const tg::FirstArgs a = first_args_for(op, src, dst, update);
+    tg::FirstArgs a = first_args_for(op, src, dst, update);
+    if (dg) a.dg = *dg;
     mark_launch(st);
     hip_check(nt ? tg::launch_first_bf16(nt, a, st) : tg::launch_first<T>(a, st), "fused first-mode launch");
   }
@@ -890,20 +916,22 @@ FusedIO fused_io(const tg_plan_s* P, size_t i, void* state, int route) {
 // the stencil), intermediate results go to scratch, the last op updates or
 // stores `dst`.
 template <typename T>
-void run_fused(const tg_plan_s* P, const void* src, void* dst, bool update, bool from_state, hipStream_t st) {
+void run_fused(const tg_plan_s* P, const void* src, void* dst, bool update, bool from_state, hipStream_t st,
+               const tg::DiagArgs* dg = nullptr) {
   for (size_t i = 0; i < P->fused.size(); ++i) {
     const auto& op = P->fused[i];
     const void* in = op.in < 0 ? src : P->scratch[op.in];
     const bool last = i + 1 == P->fused.size();
     void* out = last ? dst : P->scratch[op.out];
-    launch_fused<T>(P, op, in, out, last ? update : false, from_state, st);
+    launch_fused<T>(P, op, in, out, last ? update : false, from_state, st, last ? dg : nullptr);
   }
 }
 
 // Apply the split chain to `in`.  final_update: last op does state += tau*acc
 // on `out`; otherwise the last op stores into `out`.
 template <typename T>
-void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update, hipStream_t st) {
+void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update, hipStream_t st,
+               const tg::DiagArgs* dg = nullptr) {
   const size_t nops = P->chain.size();
   const void* X = in;
   int buf = (in == P->scratch[0]) ? 1 : 0;
@@ -913,7 +941,7 @@ void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update,
     void* Y = last ? out : P->scratch[buf];
     int epi = c.epi;
     if (last) epi = final_update ? tg::EPI_UPDATE : tg::EPI_STORE;
-    launch_op<T>(P, c, X, Y, epi, st);
+    launch_op<T>(P, c, X, Y, epi, st, -1.0, last ? dg : nullptr);
     X = Y;
     buf ^= 1;
   }
@@ -928,20 +956,20 @@ int active_route(const tg_plan_s* P) {
 bool use_fused(const tg_plan_s* P) { return active_route(P) != 1; }
 
 template <typename T>
-void step_impl(tg_plan_s* P, void* state, hipStream_t st) {
+void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg = nullptr) {
   const int r = active_route(P);
   if (r == 0) {
     // the first fused op computes F from the state inside its tile load
-    run_fused<T>(P, state, state, true, true, st);
+    run_fused<T>(P, state, state, true, true, st, dg);
     return;
   }
   if (r == 2) {
     launch_stencil_stage<T>(P, state, P->scratch[1], TG_APPLY_F, st);
-    run_fused<T>(P, P->scratch[1], state, true, false, st);
+    run_fused<T>(P, P->scratch[1], state, true, false, st, dg);
     return;
   }
   launch_stencil_stage<T>(P, state, P->scratch[0], TG_APPLY_F, st);
-  run_chain<T>(P, P->scratch[0], state, true, st);
+  run_chain<T>(P, P->scratch[0], state, true, st, dg);
 }
 
 // One reverse step of the discrete adjoint (see tg_adjoint_step).
@@ -1045,9 +1073,32 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   hip_check(tg::launch_adjoint_combine<T>(aa, st), "adjoint combine");
 }
 
-void step_any(tg_plan_s* P, void* state, hipStream_t st) {
-  if (P->precision == TG_FP64) step_impl<double>(P, state, st);
-  else step_impl<float>(P, state, st);
+void step_any(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg = nullptr) {
+  if (P->precision == TG_FP64) step_impl<double>(P, state, st, dg);
+  else step_impl<float>(P, state, st, dg);
+}
+
+// Indicator arguments writing to out ([nslab][2] doubles); allocates the
+// partial-sum buffer on first use.  Every n >= 3 and tiles are at least 16
+// wide, so a slab has at most npts / 48 + npts / 9 + 1 tiles in any launch
+// configuration: npts / 8 + 64 slots per slab (the launchers check it).
+tg::DiagArgs diag_args(tg_plan_s* P, double* out) {
+  if (!P->diag_part) {
+    const int64_t cap = P->npts / 8 + 64;
+    TG_REQUIRE(cap < (int64_t(1) << 30), TG_EINVAL, "indicators: grid too large");
+    hip_check(hipMalloc(reinterpret_cast<void**>(&P->diag_part), sizeof(double) * 2 * cap * P->nslab),
+              "hipMalloc(indicator partials)");
+    P->diag_cap = static_cast<int>(cap);
+  }
+  tg::DiagArgs d{};
+  d.part = P->diag_part;
+  d.out = out;
+  d.w1 = P->d_w1;
+  d.w23 = P->d_w23;
+  d.wref = P->d_wref;
+  d.wsum_inv = P->wsum_inv;
+  d.cap = P->diag_cap;
+  return d;
 }
 
 constexpr int kStepsPerGraph = 8;
@@ -1351,6 +1402,7 @@ int tg_plan_destroy(tg_plan p) {
     if (s) (void)hipFree(s);
   if (p->dflag) (void)hipFree(p->dflag);
   if (p->adj_ws) (void)hipFree(p->adj_ws);
+  if (p->diag_part) (void)hipFree(p->diag_part);
   delete p;
   return TG_OK;
 }
@@ -1400,6 +1452,50 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
     if (flag) {
       hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_run: flag reset");
       throw Fail(TG_ENONFINITE, "tg_run: non-finite value in the state");
+    }
+    return TG_OK;
+  });
+}
+
+int tg_step_diag(tg_plan p, void* state, double* diag, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state && diag, TG_EINVAL, "tg_step_diag: null pointer");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_step_diag: state must be aligned to 4 elements");
+    const tg::DiagArgs d = diag_args(p, diag);
+    step_any(p, state, static_cast<hipStream_t>(stream), &d);
+    return TG_OK;
+  });
+}
+
+int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* diag, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state && diag && n_steps >= 0 && every >= 1, TG_EINVAL, "tg_run_diag: bad argument");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_diag: state must be aligned to 4 elements");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    tg::DiagArgs d = diag_args(p, diag);
+    const int64_t records = n_steps / every;
+    int64_t done = 0;
+    for (int64_t r = 0; r < records; ++r) {
+      // every - 1 plain steps (graph replays of kStepsPerGraph, then single
+      // launches), then the recorded step
+      const int64_t plain = every - 1;
+      const int64_t full = plain / kStepsPerGraph;
+      if (full > 0) {
+        hipGraphExec_t ex = step_graph(p, state, kStepsPerGraph);
+        for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(ex, st), "tg_run_diag: graph launch");
+      }
+      for (int64_t it = full * kStepsPerGraph; it < plain; ++it) step_any(p, state, st);
+      d.out = diag + 2 * static_cast<int64_t>(p->nslab) * r;
+      step_any(p, state, st, &d);
+      done += every;
+    }
+    for (; done < n_steps; ++done) step_any(p, state, st);
+    int flag = 0;
+    hip_check(hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "tg_run_diag: flag copy");
+    hip_check(hipStreamSynchronize(st), "tg_run_diag: synchronize");
+    if (flag) {
+      hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_run_diag: flag reset");
+      throw Fail(TG_ENONFINITE, "tg_run_diag: non-finite value in the state");
     }
     return TG_OK;
   });

@@ -11,6 +11,7 @@
 #include <cstdio>
 
 #include "fused.hpp"
+#include "diag_dev.hpp"
 #include "stencil_dev.hpp"
 
 namespace tg {
@@ -634,7 +635,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, in
 // right after the MFMAs of the current one, so each product finds its
 // operands in registers after the barrier.  Waves with more than one
 // sub-tile load the later ones in place.
-template <typename T, int FM, int FN, int KCH, int NW>
+template <typename T, int FM, int FN, int KCH, int NW, bool DG = true>
 __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int by, int bz, unsigned char* smem) {
   constexpr int NT = 64 * NW;
   using acc_t = typename M16<T>::acc;
@@ -779,6 +780,8 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
   // 4. plane tail: Z[row][i'] = sum_i T[row][i] P[i'][i];  W += alpha Z
   const T* Tin = a.sandwich ? sX : sT;
   const T alpha = static_cast<T>(a.alpha);
+  const bool diag = DG && a.dg.part != nullptr;  // grouped launches carry none
+  double ds0 = 0.0, ds1 = 0.0;
   for (int sub = wave; sub < nsub; sub += NW) {
     const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
     if (sub != wave || !kPre) plane_requests(r0, c0);
@@ -804,9 +807,17 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
           if (row < nm && col < na) {
             W[static_cast<int64_t>(row) * na + col] = nv;
             bad |= !isfinite(nv);
+            if (diag)
+              diag_point(a.dg, b * nm + row, col, static_cast<double>(nv),
+                         a.update ? static_cast<double>(wv[f][j][r]) : 0.0, ds0, ds1);
           }
         }
     if (bad && a.flag) atomicOr(a.flag, 1);
+  }
+  if (diag) {
+    const int nbx = (na + TN - 1) / TN;
+    diag_flush<NW>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + static_cast<int64_t>(b) * nbx + bx,
+                   reinterpret_cast<double*>(smem));
   }
 }
 
@@ -843,7 +854,7 @@ void strided_kernel(StridedArgs a) {
 
 // ---------------------------------------------------------------------------
 // One tile of a first-mode launch: rows bx * tm .., slab by.
-template <typename T, int FM, int FN, int KCH>
+template <typename T, int FM, int FN, int KCH, bool DG = true>
 __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, unsigned char* smem) {
   using acc_t = typename M16<T>::acc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -863,6 +874,8 @@ __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, u
   const int nsub = nrt * nct;
   T* Y = static_cast<T*>(a.Y) + base;
   const T alpha = static_cast<T>(a.alpha);
+  const bool diag = DG && a.dg.part != nullptr;  // grouped launches carry none
+  double ds0 = 0.0, ds1 = 0.0;
   // final epilogue of a sub-tile: store, or add alpha * result to the target
   auto finish = [&](int r0, int c0, const acc_t (&acc)[FM][FN], const T (&yv)[FM][FN][4]) {
     bool bad = false;
@@ -877,9 +890,16 @@ __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, u
           if (rg < a.rows && col < nm) {
             Y[static_cast<int64_t>(rg) * nm + col] = nv;
             bad |= !isfinite(nv);
+            if (diag)
+              diag_point(a.dg, rg, col, static_cast<double>(nv), a.update ? static_cast<double>(yv[f][j][r]) : 0.0,
+                         ds0, ds1);
           }
         }
     if (bad && a.update && a.flag) atomicOr(a.flag, 1);
+  };
+  auto flush = [&]() {
+    if (diag)
+      diag_flush<4>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + bx, reinterpret_cast<double*>(smem));
   };
   auto prefetch = [&](int r0, int c0, T (&yv)[FM][FN][4]) {
     if (!a.update) return;
@@ -932,7 +952,10 @@ __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, u
           sT[row * ld + col] = in ? v : T(0);
         }
   }
-  if (!a.sandwich) return;
+  if (!a.sandwich) {
+    flush();
+    return;
+  }
   __syncthreads();
   const T* L2 = factor_of<T>(a.L2, s);
   for (int sub = wave; sub < nsub; sub += 4) {
@@ -944,6 +967,7 @@ __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, u
     mm_sA_gB<T, FM, FN, KCH>(acc, sT, ld, r0, L2, a.L2.ld, c0, NP, lane);
     finish(r0, c0, acc, yv);
   }
+  flush();
 }
 
 template <typename T, int FM, int FN, int KCH>
@@ -977,7 +1001,8 @@ void strided_group_kernel(const StridedGroup* __restrict__ grp) {
     int local;
     const int q = group_member(m, L, local);
     const int nbx = m.nbx[q], nby = m.nby[q];
-    strided_tile<T, FM, FN, KCH, NW>(grp->a[q], local % nbx, (local / nbx) % nby, local / (nbx * nby), smem);
+    strided_tile<T, FM, FN, KCH, NW, false>(grp->a[q], local % nbx, (local / nbx) % nby, local / (nbx * nby),
+                                            smem);
     __syncthreads();  // the next tile reuses the LDS
   }
 }
@@ -992,7 +1017,7 @@ __global__ __launch_bounds__(256) void first_group_kernel(const FirstGroup* __re
     int local;
     const int q = group_member(m, L, local);
     const int nbx = m.nbx[q];
-    first_tile<T, FM, FN, KCH>(grp->a[q], local % nbx, local / nbx, smem);
+    first_tile<T, FM, FN, KCH, false>(grp->a[q], local % nbx, local / nbx, smem);
     __syncthreads();
   }
 }
@@ -1097,16 +1122,23 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t s) {
   if (lds > kMaxLds) return hipErrorInvalidValue;
   // 8-wave workgroups for FP32 only (measured: FP64 is faster with 4)
   const int v = strided_variant(pick_kch(a.nm), NP, a.tn, sizeof(T) == 4);
-  return with_svar(v, [&]<int FM, int FN, int KCH, int NW>() -> hipError_t {
+  StridedArgs b = a;
+  if (b.dg.part) {  // indicators: plane-tail updates, one partial pair per tile
+    b.dg.tiles = (a.na + a.tn - 1) / a.tn * a.nb;
+    if (!a.plane || !a.update || b.dg.tiles > b.dg.cap) return hipErrorInvalidValue;
+  }
+  hipError_t e = with_svar(v, [&]<int FM, int FN, int KCH, int NW>() -> hipError_t {
     auto k = strided_kernel<T, FM, FN, KCH, NW>;
     hipError_t e = allow_lds(k, lds);
     if (e != hipSuccess) return e;
     const int64_t total = static_cast<int64_t>((a.na + a.tn - 1) / a.tn) * a.nb * a.nslab;
     if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
     const int per_xcd = static_cast<int>((total + 7) / 8);
-    hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * NW), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * NW), lds, s, b);
     return hipGetLastError();
   });
+  if (e != hipSuccess || !b.dg.part) return e;
+  return launch_diag_finish(b.dg, b.nslab, s);
 }
 
 template <typename T, int FM, int FN, int KCH>
@@ -1127,15 +1159,24 @@ hipError_t launch_first(const FirstArgs& a, hipStream_t s) {
   if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP)) return hipErrorInvalidValue;
   const size_t lds = first_lds_bytes<T>(a.nm, a.tm, a.sandwich);
   if (lds > kMaxLds) return hipErrorInvalidValue;
-  const int kch = pick_kch(a.nm);
-  if (a.tm == 16) {
-    if (kch == 4) return go_first<T, 1, 2, 4>(a, lds, s);
-    if (kch == 8) return go_first<T, 1, 2, 8>(a, lds, s);
-    return go_first<T, 1, 2, 0>(a, lds, s);
+  FirstArgs b = a;
+  if (b.dg.part) {  // indicators: one partial pair per row block
+    b.dg.tiles = (a.rows + a.tm - 1) / a.tm;
+    if (!a.update || b.dg.tiles > b.dg.cap) return hipErrorInvalidValue;
   }
-  if (kch == 4) return go_first<T, 2, 2, 4>(a, lds, s);
-  if (kch == 8) return go_first<T, 2, 2, 8>(a, lds, s);
-  return go_first<T, 2, 2, 0>(a, lds, s);
+  const int kch = pick_kch(a.nm);
+  hipError_t e;
+  if (a.tm == 16) {
+    if (kch == 4) e = go_first<T, 1, 2, 4>(b, lds, s);
+    else if (kch == 8) e = go_first<T, 1, 2, 8>(b, lds, s);
+    else e = go_first<T, 1, 2, 0>(b, lds, s);
+  } else {
+    if (kch == 4) e = go_first<T, 2, 2, 4>(b, lds, s);
+    else if (kch == 8) e = go_first<T, 2, 2, 8>(b, lds, s);
+    else e = go_first<T, 2, 2, 0>(b, lds, s);
+  }
+  if (e != hipSuccess || !b.dg.part) return e;
+  return launch_diag_finish(b.dg, b.nslab, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -53,6 +53,7 @@ struct StridedArgs {
   int update;      // plane tail: 1 = W += alpha * Z, 0 = W = Z
   double alpha;
   int* flag;
+  DiagArgs dg;     // plane-tail updates only (row j + n2 k, column i)
 };
 
 // First mode product over rows r (all slower points) of every slab:
@@ -69,6 +70,7 @@ struct FirstArgs {
   int update;
   double alpha;
   int* flag;
+  DiagArgs dg;     // updates only (row = slower points j + n2 k, column i)
 };
 
 // Grouped persistent launch of up to kMaxGroup launches of one kind (the

@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "fused.hpp"
+#include "diag_dev.hpp"
 #include "stencil_dev.hpp"
 
 namespace tg {
@@ -280,6 +281,8 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
   float* W = static_cast<float*>(a.W) + base;
   const int kbt = (na + 31) / 32;
   const float alpha = static_cast<float>(a.alpha);
+  const bool diag = a.dg.part != nullptr;
+  double ds0 = 0.0, ds1 = 0.0;
   for (int sub = wave; sub < nsub; sub += 4) {
     const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
     float wv[FM][FN][4];
@@ -307,9 +310,15 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
           if (row < nm && col < na) {
             W[static_cast<int64_t>(row) * na + col] = nv;
             bad |= !isfinite(nv);
+            if (diag) diag_point(a.dg, b * nm + row, col, nv, wv[f][j][r], ds0, ds1);
           }
         }
     if (bad && a.flag) atomicOr(a.flag, 1);
+  }
+  if (diag) {
+    const int nbx = (na + TN - 1) / TN;
+    diag_flush<4>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + static_cast<int64_t>(b) * nbx + blockIdx.x,
+                  reinterpret_cast<double*>(smem));
   }
 }
 
@@ -341,6 +350,8 @@ __global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
   float* Y = static_cast<float*>(a.Y) + base;
   const float alpha = static_cast<float>(a.alpha);
   const int kblocks = NP / 32;
+  const bool diag = a.dg.part != nullptr;
+  double ds0 = 0.0, ds1 = 0.0;
   auto finish = [&](int r0, int c0, const fx4 (&acc)[FM][FN]) {
     bool bad = false;
 #pragma unroll
@@ -352,12 +363,19 @@ __global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
           const int rg = rt0 + r0 + 16 * f + 4 * g + r, col = c0 + 16 * j + li;
           if (rg < a.rows && col < nm) {
             float* dst = Y + static_cast<int64_t>(rg) * nm + col;
-            const float nv = a.update ? *dst + alpha * acc[f][j][r] : acc[f][j][r];
+            const float ov = a.update ? *dst : 0.0f;
+            const float nv = a.update ? ov + alpha * acc[f][j][r] : acc[f][j][r];
             *dst = nv;
             bad |= !isfinite(nv);
+            if (diag) diag_point(a.dg, rg, col, nv, ov, ds0, ds1);
           }
         }
     if (bad && a.update && a.flag) atomicOr(a.flag, 1);
+  };
+  auto flush = [&]() {
+    if (diag)
+      diag_flush<4>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + blockIdx.x,
+                    reinterpret_cast<double*>(smem));
   };
   const __bf16* L1 = bf_factor(a.L1, s);
   const int64_t t1 = static_cast<int64_t>(a.L1.ld) * a.L1.ld;
@@ -397,7 +415,10 @@ __global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
           put1<NT>(sT, tstr, row * ldk + col, in ? acc[f][j][r] * ph[f][j][r] : 0.0f);
         }
   }
-  if (!a.sandwich) return;
+  if (!a.sandwich) {
+    flush();
+    return;
+  }
   __syncthreads();
   const __bf16* L2 = bf_factor(a.L2, s);
   const int64_t t2 = static_cast<int64_t>(a.L2.ld) * a.L2.ld;
@@ -408,6 +429,7 @@ __global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
     gemm_lds_fac<NT, FM, FN, KB>(acc, sT, tstr, ldk, r0, L2, t2, a.L2.ld, c0, kblocks, lane);
     finish(r0, c0, acc);
   }
+  flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -464,9 +486,15 @@ hipError_t launch_strided_bf16(int nterms, const StridedArgs& a, hipStream_t s) 
     return hipErrorInvalidValue;
   const size_t lds = strided_bf16_lds_bytes(nterms, a.nm, a.na, a.tn, a.sandwich, a.plane);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (nterms == 2) return sbf_dispatch<2>(a, lds, s);
-  if (nterms == 3) return sbf_dispatch<3>(a, lds, s);
-  return hipErrorInvalidValue;
+  if (nterms != 2 && nterms != 3) return hipErrorInvalidValue;
+  StridedArgs b = a;
+  if (b.dg.part) {  // indicators: plane-tail updates, one partial pair per tile
+    b.dg.tiles = (a.na + a.tn - 1) / a.tn * a.nb;
+    if (!a.plane || !a.update || b.dg.tiles > b.dg.cap) return hipErrorInvalidValue;
+  }
+  const hipError_t e = nterms == 2 ? sbf_dispatch<2>(b, lds, s) : sbf_dispatch<3>(b, lds, s);
+  if (e != hipSuccess || !b.dg.part) return e;
+  return launch_diag_finish(b.dg, b.nslab, s);
 }
 
 template <int NT, int FM, int FN, int KB>
@@ -499,9 +527,15 @@ hipError_t launch_first_bf16(int nterms, const FirstArgs& a, hipStream_t s) {
   if (a.L1.ld < NP || (a.sandwich && a.L2.ld < NP)) return hipErrorInvalidValue;
   const size_t lds = first_bf16_lds_bytes(nterms, a.nm, a.tm, a.sandwich);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (nterms == 2) return fbf_dispatch<2>(a, lds, s);
-  if (nterms == 3) return fbf_dispatch<3>(a, lds, s);
-  return hipErrorInvalidValue;
+  if (nterms != 2 && nterms != 3) return hipErrorInvalidValue;
+  FirstArgs b = a;
+  if (b.dg.part) {  // indicators: one partial pair per row block
+    b.dg.tiles = (a.rows + a.tm - 1) / a.tm;
+    if (!a.update || b.dg.tiles > b.dg.cap) return hipErrorInvalidValue;
+  }
+  const hipError_t e = nterms == 2 ? fbf_dispatch<2>(b, lds, s) : fbf_dispatch<3>(b, lds, s);
+  if (e != hipSuccess || !b.dg.part) return e;
+  return launch_diag_finish(b.dg, b.nslab, s);
 }
 
 }  // namespace tg

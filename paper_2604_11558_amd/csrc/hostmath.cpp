@@ -80,6 +80,33 @@ std::vector<double> coord_grid(Coord c, int n, double extent, double lam) {
   return g;
 }
 
+std::vector<double> coord_weights(Coord c, int n, double extent, double lam) {
+  std::vector<double> w(n);
+  if (c == THETA) {
+    for (int i = 0; i < n; ++i) w[i] = 2.0 * kPi / n;
+    return w;
+  }
+  const auto g = coord_grid(c, n, extent, lam);
+  const double hi = c == PHI ? kPi : extent;  // every other range starts at 0
+  // integral of the volume-element factor from 0 to x
+  auto prim = [c](double x) {
+    switch (c) {
+      case RHO2:
+      case RHO_LAMBDA: return 0.5 * x * x;
+      case RHO3: return x * x * x / 3.0;
+      case PHI: return 1.0 - std::cos(x);
+      default: return x;
+    }
+  };
+  double left = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double right = i + 1 < n ? 0.5 * (g[i] + g[i + 1]) : hi;
+    w[i] = prim(right) - prim(left);
+    left = right;
+  }
+  return w;
+}
+
 Tridiag coord_operator(Coord c, int n, double extent, double lam) {
   if (n < 3) throw std::invalid_argument("grid needs at least 3 points per coordinate");
   Tridiag T;

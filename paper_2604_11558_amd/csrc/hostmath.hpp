@@ -36,6 +36,13 @@ enum Coord { RHO2 = 0, RHO3 = 1, THETA = 2, PHI = 3, ZED = 4, RHO_LAMBDA = 5 };
 std::vector<double> coord_grid(Coord c, int n, double extent, double lam = 0.0);
 // The matching tridiagonal operator.
 Tridiag coord_operator(Coord c, int n, double extent, double lam = 0.0);
+// Quadrature weight of each grid point along one coordinate: the measure,
+// in that coordinate's factor of the volume element (rho for RHO2 and
+// RHO_LAMBDA, rho^2 for RHO3, sin(phi) for PHI, 1 for THETA and ZED), of the
+// cell between the midpoints to its neighbours, the end cells closed by the
+// ends of the coordinate's range.  The weights sum to the coordinate's
+// factor of the domain measure.
+std::vector<double> coord_weights(Coord c, int n, double extent, double lam = 0.0);
 // sigma of system (syscn): root in (0, 1/2) (Appendix A).
 double sigma_phi(int n);
 

@@ -1,6 +1,7 @@
 // Device kernels: MFMA mu-mode products with fused epilogues, and the
 // stencil + reaction stage of the split exponential Euler step.
 #include "kernels.hpp"
+#include "diag_dev.hpp"
 #include "stencil_dev.hpp"
 
 #include <algorithm>
@@ -131,6 +132,8 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
   const bool phi_epi = g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC;
   const double cs = phi_epi ? g.cs[s] : 0.0;
   const double pbv = (phi_epi && g.pb) ? g.pb[b] : 1.0;
+  const bool diag = g.dg.part != nullptr;  // EPI_UPDATE of a first-mode product
+  double ds0 = 0.0, ds1 = 0.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -155,23 +158,35 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
               *dst = v * static_cast<T>(x * g.rd[s]) * (phi1_t(xt) - phi2_t(xt));
             }
           } else if (g.epi == EPI_UPDATE) {
-            const T nv = *dst + static_cast<T>(g.alpha) * v;
+            const T ov = *dst;
+            const T nv = ov + static_cast<T>(g.alpha) * v;
             *dst = nv;
             if (!isfinite(nv) && g.flag) atomicOr(g.flag, 1);
+            if (diag) diag_point(g.dg, row, col, static_cast<double>(nv), static_cast<double>(ov), ds0, ds1);
           } else {
             *dst = v;
           }
         }
       }
+  if (diag)
+    diag_flush<4>(g.dg, ds0, ds1, static_cast<int64_t>(s) * g.dg.tiles + blockIdx.x,
+                  reinterpret_cast<double*>(&sA[0][0]));
 }
 
 template <typename T, int TM, int TN>
 static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
   constexpr int KC = 16;
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
+  GemmArgs h = g;
+  if (h.dg.part) {  // indicators: first-mode updates, one partial pair per tile
+    h.dg.tiles = tiles;
+    if (g.epi != EPI_UPDATE || !g.b_kcontig || g.nbatch != 1 || tiles > h.dg.cap) return hipErrorInvalidValue;
+  }
   dim3 grid(tiles, g.nbatch, g.nslab);
-  hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC>), grid, dim3(256), 0, s, g);
-  return hipGetLastError();
+  hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC>), grid, dim3(256), 0, s, h);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !h.dg.part) return e;
+  return launch_diag_finish(h.dg, g.nslab, s);
 }
 
 template <typename T>
@@ -268,6 +283,40 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
 
 template hipError_t launch_stencil<double>(const StencilArgs&, hipStream_t);
 template hipError_t launch_stencil<float>(const StencilArgs&, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Steady-state indicators: each slab's partial pairs summed in a fixed order.
+__global__ __launch_bounds__(256) void diag_finish_kernel(DiagArgs d) {
+  __shared__ double r0[256], r1[256];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const double* part = d.part + 2 * static_cast<int64_t>(s) * d.tiles;
+  double a = 0.0, b = 0.0;
+  for (int i = t; i < d.tiles; i += 256) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  r0[t] = a;
+  r1[t] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      r0[t] += r0[t + w];
+      r1[t] += r1[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    d.out[2 * s] = d.wref[s] + d.wsum_inv * r0[0];
+    d.out[2 * s + 1] = sqrt(r1[0]);
+  }
+}
+
+hipError_t launch_diag_finish(const DiagArgs& d, int nslab, hipStream_t s) {
+  if (!d.part || !d.out || nslab <= 0 || nslab > 65535 || d.tiles <= 0 || d.tiles > d.cap)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(diag_finish_kernel, dim3(nslab), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Per-slab dot products (double accumulation, block reduction in LDS).

@@ -11,6 +11,28 @@ namespace tg {
 // EPI_PHI_ACC: C += acc * phi_1(x).
 enum Epilogue : int { EPI_STORE = 0, EPI_PHI = 1, EPI_UPDATE = 2, EPI_DPHI = 3, EPI_PHI_ACC = 4 };
 
+// Steady-state indicators gathered in the update epilogue of a step's last
+// launch.  Each workgroup sums, over the points it updates, w * W_new and
+// w * (W_new - W_old)^2 with w = w1[i] * w23[j + n2 k] the quadrature weight
+// of point (i, j, k), and stores the two sums in part[2 * (slab * tiles +
+// tile) + {0, 1}] (no atomics: the sums are reproducible).  A finishing
+// launch adds up each slab's partial sums in a fixed order and writes
+// out[2 * slab] = wref[slab] + wsum_inv * sum(w W_new) (the integral mean of
+// the full value) and out[2 * slab + 1] = sqrt(sum(w dW^2)).
+struct DiagArgs {
+  double* part;         // null: no indicators
+  double* out;
+  const double* w1;     // [n1]
+  const double* w23;    // [n2 * n3]
+  const double* wref;   // [nslab]
+  double wsum_inv;
+  int tiles;            // partial slots per slab (set by the launcher)
+  int cap;              // slots per slab available in part
+};
+
+// Sum each slab's `tiles` partial pairs and write the indicators.
+hipError_t launch_diag_finish(const DiagArgs& d, int nslab, hipStream_t s);
+
 // One mu-mode product over a batch of "slabs" (species x instances), as a
 // GEMM C = A * B per (slab, batch b):
 //   strided mode (mu >= 2):  A = factor L (M x K, row-major), B = X_b (K x N,
@@ -40,6 +62,7 @@ struct GemmArgs {
   int tile;                        // 0: 64x64, 1: 32x64, 2: 64x32, 3: 32x32
   int* flag;                       // EPI_UPDATE: set to 1 if a non-finite value is written
   const double* rd;                // per slab 1 / d_s (EPI_DPHI)
+  DiagArgs dg;                     // EPI_UPDATE of a first-mode product only
 };
 
 template <typename T>

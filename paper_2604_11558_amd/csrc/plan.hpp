@@ -83,6 +83,14 @@ struct tg_plan_s {
   const double* d_tau = nullptr;     // tau per slab
   const double* d_taurd = nullptr;   // tau / d per slab
   void* adj_ws = nullptr;            // adjoint workspace: 8 state-sized buffers
+  // steady-state indicators: quadrature weights w1 [n1], w23 [n2 n3] (the
+  // sphere's rho_*^2 folded into w1), 1 / sum of all weights, and the
+  // per-tile partial sums (allocated on first use, diag_cap slots per slab)
+  const double* d_w1 = nullptr;
+  const double* d_w23 = nullptr;
+  double wsum_inv = 0.0;
+  double* diag_part = nullptr;
+  int diag_cap = 0;
   int nmax = 0;
   int periodic_mask = 0;
   int scale_mask = 0;
