@@ -103,6 +103,21 @@ WORKLOADS: Dict[str, Workload] = {
 }
 
 
+# Section 5.5: bulk-surface Schnakenberg, ball (u, v) + its surface (r, s).
+# Grid (n_rho, n_theta, n_phi) = (30, 50, 30), t_* = 15 in m = 150000 steps,
+# perturbations 1e-3 N(0, 1) per point and species (the paper's draw).
+BULK_SURFACE = dict(name="ball_sphere_30x50x30", n=(30, 50, 30), tau=1e-4, steps=150000, seed=9,
+                    amplitude=1e-3)
+
+
+def bulk_surface_perturbations(n: Tuple[int, int, int], seed: int, amplitude: float = 1e-3):
+    """(bulk [2][n3][n2][n1], surface [2][n3][n2]) deviations, amplitude * N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    bulk = amplitude * rng.standard_normal((2, n[2], n[1], n[0]))
+    surf = amplitude * rng.standard_normal((2, n[2], n[1]))
+    return bulk, surf
+
+
 def scaled(w: Workload, n: Tuple[int, ...], steps: Optional[int] = None,
            name: Optional[str] = None) -> Workload:
     """Same physics on a different grid (used for small parity cases)."""
