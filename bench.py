@@ -172,6 +172,29 @@ def other_workloads(tg, torch, steps):
         res[f"every_{every}_last_record"] = rec[-1, 0].cpu().numpy().tolist()
     out["ball_64x64x128_fp32_indicators"] = res
     del plan, x
+    # bulk-surface ball (30 x 50 x 30) + sphere (50 x 30), Section 5.5's grid
+    bs = workloads.BULK_SURFACE
+    nb = bs["n"]
+    cpl = (55.0, 5.0 / 12.0, 5.0 / 12.0, 5.0, 5.0)  # zeta1, zeta2, zeta3, eta1, eta2
+    db, dsf = workloads.bulk_surface_perturbations(nb, bs["seed"], bs["amplitude"])
+    for prec in ("fp64", "fp32"):
+        bulk = tg.Plan(tg.Grid("ball", nb), [(1.0, 10.0)], "schnakenberg_scaled", (0.1, 0.9, 55.0),
+                       bs["tau"], prec)
+        surf = tg.Plan(tg.Grid("sphere", nb[1:]), [(1.0, 10.0)], "schnakenberg_scaled", (0.1, 0.9, 55.0),
+                       bs["tau"], prec)
+        xb = bulk.state_from_deviation(db[None])
+        xs = surf.state_from_deviation(dsf[None])
+        tg.coupled_run(bulk, surf, xb, xs, cpl, 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tg.coupled_run(bulk, surf, xb, xs, cpl, steps)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        dof = 2 * int(np.prod(nb)) + 2 * nb[1] * nb[2]
+        out[f"ball_sphere_30x50x30_coupled_{prec}"] = {
+            "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
+            "paper_run_seconds_at_this_rate": bs["steps"] * sec}
+        del bulk, surf, xb, xs
     # 160 x 160 anomalous-diffusion disk (lambda = -1.95), FP64 and FP32
     wl = workloads.WORKLOADS["disk_lambda_160x160"]
     grid = tg.Grid(wl.geometry, wl.n, wl.extent)

@@ -172,6 +172,32 @@ int tg_step_diag(tg_plan p, void* state, double* diag, void* stream);
  * graphs.  Synchronises and checks for non-finite values like tg_run. */
 int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* diag, void* stream);
 
+/* Bulk-surface Schnakenberg system (Section 5.5, eqs. (bulkballsys),
+ * (bulkballnl)): u, v in a ball (plan `bulk`: TG_BALL, two species,
+ * d = (1, delta), kinetics TG_REACT_SCHNAKENBERG_SCALED with gamma =
+ * alpha_1) and r, s on its surface (plan `surface`: TG_SPHERE of the same
+ * radius on the ball's (theta, phi) grid, two species, d = (1, epsilon),
+ * TG_REACT_SCHNAKENBERG_SCALED with gamma = zeta_1), same batch and
+ * precision.  coupling = {zeta1, zeta2, zeta3, eta1, eta2} (host).
+ *
+ * The Robin conditions du/dn = zeta1 (zeta2 r - zeta3 u) and
+ * delta dv/dn = zeta1 (eta1 s - eta2 v) enter the ball's boundary row
+ * through its ghost point: F_u += kappa zeta1 (zeta2 r - zeta3 u) and
+ * F_v += kappa zeta1 (eta1 s - eta2 v) on the layer rho = rho_*, with
+ * kappa = (2 / h)(1 + h / rho_*), h = rho_* / n_rho; the surface gets
+ * F_r -= zeta1 (zeta2 r - zeta3 u), F_s -= zeta1 (eta1 s - eta2 v).  The
+ * exchange is evaluated at t_n with the kinetics; then each side takes its
+ * own split step (route 0 plans run route 2 here: the exchange is added by
+ * a separate stencil launch).  States: each plan's layout, in place.
+ * TG_EINVAL when the plans do not match as described. */
+int tg_coupled_step(tg_plan bulk, tg_plan surface, void* bulk_state, void* surface_state, const double* coupling,
+                    void* stream);
+/* n_steps coupled steps, replayed from a captured graph of 8 steps (kept by
+ * the bulk plan per pair of states and coupling constants); synchronises and
+ * returns TG_ENONFINITE if either state received a non-finite value. */
+int tg_coupled_run(tg_plan bulk, tg_plan surface, void* bulk_state, void* surface_state, const double* coupling,
+                   int64_t n_steps, void* stream);
+
 /* Reverse step of the discrete adjoint of tg_step (not in the paper; the
  * exact derivative of the discrete map).  With mu_s = tau S_s^T lambda_s,
  * S_s = phi_1(tau d_s M_1) ... phi_1(tau d_s M_d):

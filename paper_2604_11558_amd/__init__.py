@@ -48,6 +48,8 @@ _SIGNATURES = {
     "tg_step": (ctypes.c_int, [_p, _p, _p]),
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
     "tg_step_diag": (ctypes.c_int, [_p, _p, _p, _p]),
+    "tg_coupled_step": (ctypes.c_int, [_p, _p, _p, _p, _pd, _p]),
+    "tg_coupled_run": (ctypes.c_int, [_p, _p, _p, _p, _pd, _c_i64, _p]),
     "tg_run_diag": (ctypes.c_int, [_p, _p, _c_i64, _c_int, _p, _p]),
     "tg_apply_operator": (ctypes.c_int, [_p, _p, _p, _c_int, _p]),
     "tg_apply_split_phi1": (ctypes.c_int, [_p, _p, _p, _p]),
@@ -336,6 +338,30 @@ def _group_args(plans, states):
     hp = (_p * len(plans))(*[p._h.value if isinstance(p._h, _p) else p._h for p in plans])
     hs = (_p * len(states))(*[s.data_ptr() for s in states])
     return hp, hs
+
+
+def _coupling(coupling):
+    c = np.ascontiguousarray(np.asarray(coupling, dtype=np.float64).reshape(5))
+    return c, _dptr(c)
+
+
+def coupled_step(bulk, surface, bulk_state, surface_state, coupling, stream=None):
+    """One bulk-surface step (ball plan + sphere plan); coupling =
+    (zeta1, zeta2, zeta3, eta1, eta2)."""
+    bulk._check_tensor(bulk_state)
+    surface._check_tensor(surface_state)
+    c, cp = _coupling(coupling)
+    _check(lib().tg_coupled_step(bulk._h, surface._h, bulk_state.data_ptr(), surface_state.data_ptr(), cp,
+                                 _stream_ptr(stream)))
+
+
+def coupled_run(bulk, surface, bulk_state, surface_state, coupling, n_steps: int, stream=None):
+    """``n_steps`` bulk-surface steps (graph replays)."""
+    bulk._check_tensor(bulk_state)
+    surface._check_tensor(surface_state)
+    c, cp = _coupling(coupling)
+    _check(lib().tg_coupled_run(bulk._h, surface._h, bulk_state.data_ptr(), surface_state.data_ptr(), cp,
+                                int(n_steps), _stream_ptr(stream)))
 
 
 def group_run(plans, states, n_steps: int, stream=None):

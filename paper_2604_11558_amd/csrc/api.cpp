@@ -1128,6 +1128,50 @@ hipGraphExec_t step_graph(tg_plan_s* P, void* state, int steps) {
   return ex;
 }
 
+// ---------------------------------------------------------------------------
+// Bulk-surface step (Section 5.5): both stencil launches read the states at
+// t_n (each with the other's values at the interface), then each side runs
+// its own split products from its F.  Route 0 computes F inside the first
+// product's tile, which knows no partner, so its plans take route 2 here.
+struct Coupled {
+  tg_plan_s* bulk;
+  tg_plan_s* surf;
+  double c[5];  // zeta1, zeta2, zeta3, eta1, eta2
+};
+
+template <typename T>
+void coupled_impl(const Coupled& C, void* ub, void* us, hipStream_t st) {
+  tg_plan_s* B = C.bulk;
+  tg_plan_s* S = C.surf;
+  const int rb = active_route(B), rs = active_route(S);
+  void* fb = rb == 1 ? B->scratch[0] : B->scratch[1];
+  void* fs = rs == 1 ? S->scratch[0] : S->scratch[1];
+  const double h = B->grid.extent[0] / B->grid.n[0];
+  tg::StencilArgs ab = stencil_args(B, ub, fb, TG_APPLY_F);
+  tg::StencilArgs as = stencil_args(S, us, fs, TG_APPLY_F);
+  tg::CoupleArgs cb{1, us, S->d_wref, B->grid.n[0], (2.0 / h) * (1.0 + h / B->grid.extent[0]),
+                    C.c[0], C.c[1], C.c[2], C.c[3], C.c[4]};
+  tg::CoupleArgs cs = cb;
+  cs.kind = 2;
+  cs.other = ub;
+  cs.oref = B->d_wref;
+  ab.cp = cb;
+  as.cp = cs;
+  mark_launch(st);
+  hip_check(tg::launch_stencil<T>(ab, st), "bulk stencil launch");
+  mark_launch(st);
+  hip_check(tg::launch_stencil<T>(as, st), "surface stencil launch");
+  if (rb == 1) run_chain<T>(B, fb, ub, true, st);
+  else run_fused<T>(B, fb, ub, true, false, st);
+  if (rs == 1) run_chain<T>(S, fs, us, true, st);
+  else run_fused<T>(S, fs, us, true, false, st);
+}
+
+void coupled_any(const Coupled& C, void* ub, void* us, hipStream_t st) {
+  if (C.bulk->precision == TG_FP64) coupled_impl<double>(C, ub, us, st);
+  else coupled_impl<float>(C, ub, us, st);
+}
+
 // Device buffers are read and written as 4-element vectors.
 bool aligned(const tg_plan_s* p, const void* ptr) {
   return reinterpret_cast<uintptr_t>(ptr) % (4u * static_cast<unsigned>(p->esize)) == 0;
@@ -1403,6 +1447,7 @@ int tg_plan_destroy(tg_plan p) {
   if (p->dflag) (void)hipFree(p->dflag);
   if (p->adj_ws) (void)hipFree(p->adj_ws);
   if (p->diag_part) (void)hipFree(p->diag_part);
+  for (auto& kv : p->coupled_graphs) (void)hipGraphExecDestroy(kv.second);
   delete p;
   return TG_OK;
 }
@@ -1496,6 +1541,88 @@ int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* 
     if (flag) {
       hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_run_diag: flag reset");
       throw Fail(TG_ENONFINITE, "tg_run_diag: non-finite value in the state");
+    }
+    return TG_OK;
+  });
+}
+
+static Coupled check_coupled(tg_plan bulk, tg_plan surface, void* ub, void* us, const double* coupling) {
+  TG_REQUIRE(bulk && surface && ub && us && coupling, TG_EINVAL, "bulk-surface step: null pointer");
+  TG_REQUIRE(bulk->grid.geometry == TG_BALL && surface->grid.geometry == TG_SPHERE, TG_EINVAL,
+             "bulk-surface step: needs a ball plan and a sphere plan");
+  TG_REQUIRE(bulk->ns == 2 && surface->ns == 2, TG_EINVAL, "bulk-surface step: two species on each side");
+  TG_REQUIRE(bulk->batch == surface->batch, TG_EINVAL, "bulk-surface step: batch sizes differ");
+  TG_REQUIRE(bulk->precision == surface->precision, TG_EINVAL, "bulk-surface step: precisions differ");
+  TG_REQUIRE(bulk->grid.n[1] == surface->grid.n[0] && bulk->grid.n[2] == surface->grid.n[1], TG_EINVAL,
+             "bulk-surface step: the sphere grid must be the ball's (theta, phi) grid");
+  TG_REQUIRE(bulk->grid.extent[0] == surface->grid.extent[0], TG_EINVAL,
+             "bulk-surface step: the sphere's radius must be the ball's");
+  TG_REQUIRE(bulk != surface && ub != us, TG_EINVAL, "bulk-surface step: distinct plans and states");
+  TG_REQUIRE(aligned(bulk, ub) && aligned(surface, us), TG_EINVAL,
+             "bulk-surface step: states must be aligned to 4 elements");
+  for (int q = 0; q < 5; ++q)
+    TG_REQUIRE(std::isfinite(coupling[q]), TG_EINVAL, "bulk-surface step: non-finite coupling constant");
+  Coupled C{bulk, surface, {coupling[0], coupling[1], coupling[2], coupling[3], coupling[4]}};
+  return C;
+}
+
+int tg_coupled_step(tg_plan bulk, tg_plan surface, void* bulk_state, void* surface_state, const double* coupling,
+                    void* stream) {
+  return guarded([&] {
+    const Coupled C = check_coupled(bulk, surface, bulk_state, surface_state, coupling);
+    coupled_any(C, bulk_state, surface_state, static_cast<hipStream_t>(stream));
+    return TG_OK;
+  });
+}
+
+int tg_coupled_run(tg_plan bulk, tg_plan surface, void* bulk_state, void* surface_state, const double* coupling,
+                   int64_t n_steps, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(n_steps >= 0, TG_EINVAL, "tg_coupled_run: negative step count");
+    const Coupled C = check_coupled(bulk, surface, bulk_state, surface_state, coupling);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t full = n_steps / kStepsPerGraph;
+    if (full > 0) {
+      std::vector<uint64_t> key = {surface->serial, surface->version, bulk->version,
+                                   reinterpret_cast<uint64_t>(bulk_state), reinterpret_cast<uint64_t>(surface_state)};
+      for (double v : C.c) {
+        uint64_t b;
+        std::memcpy(&b, &v, sizeof(b));
+        key.push_back(b);
+      }
+      hipGraphExec_t ex = nullptr;
+      auto it = bulk->coupled_graphs.find(key);
+      if (it != bulk->coupled_graphs.end()) {
+        ex = it->second;
+      } else {
+        if (!bulk->capture_stream)
+          hip_check(hipStreamCreateWithFlags(&bulk->capture_stream, hipStreamNonBlocking), "capture stream");
+        hipGraph_t graph = nullptr;
+        hip_check(hipStreamBeginCapture(bulk->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        try {
+          for (int i = 0; i < kStepsPerGraph; ++i) coupled_any(C, bulk_state, surface_state, bulk->capture_stream);
+        } catch (...) {
+          (void)hipStreamEndCapture(bulk->capture_stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        hip_check(hipStreamEndCapture(bulk->capture_stream, &graph), "end capture");
+        hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "graph instantiate");
+        bulk->coupled_graphs[key] = ex;
+      }
+      for (int64_t i = 0; i < full; ++i) hip_check(hipGraphLaunch(ex, st), "tg_coupled_run: graph launch");
+    }
+    for (int64_t i = full * kStepsPerGraph; i < n_steps; ++i) coupled_any(C, bulk_state, surface_state, st);
+    int flag[2] = {0, 0};
+    hip_check(hipMemcpyAsync(&flag[0], bulk->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+    hip_check(hipMemcpyAsync(&flag[1], surface->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+    hip_check(hipStreamSynchronize(st), "tg_coupled_run: synchronize");
+    if (flag[0] || flag[1]) {
+      hip_check(hipMemset(bulk->dflag, 0, sizeof(int)), "flag reset");
+      hip_check(hipMemset(surface->dflag, 0, sizeof(int)), "flag reset");
+      throw Fail(TG_ENONFINITE, "tg_coupled_run: non-finite value in a state");
     }
     return TG_OK;
   });

@@ -233,6 +233,37 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   }
 }
 
+// Bulk-surface exchange terms (see CoupleArgs) at point p = i + n1 q of this
+// side; du, dv are this side's deviations there.
+template <typename T>
+__device__ __forceinline__ void exchange(const StencilArgs& a, int inst, int p, int i, int npts, double du,
+                                         double dv, double& G0, double& G1) {
+  const CoupleArgs& c = a.cp;
+  const T* other = static_cast<const T*>(c.other);
+  const double* wr = a.wref + inst * 2;
+  const double* orf = c.oref + inst * 2;
+  if (c.kind == 1) {  // bulk: only the boundary layer exchanges
+    const int n1 = a.n[0];
+    if (i != n1 - 1) return;
+    const int64_t m = npts / n1, q = p / n1;
+    const double dr = static_cast<double>(other[(inst * 2) * m + q]);
+    const double ds = static_cast<double>(other[(inst * 2 + 1) * m + q]);
+    const double fu = (c.z2 * orf[0] - c.z3 * wr[0]) + (c.z2 * dr - c.z3 * du);
+    const double fv = (c.e1 * orf[1] - c.e2 * wr[1]) + (c.e1 * ds - c.e2 * dv);
+    G0 += c.kappa * c.z1 * fu;
+    G1 += c.kappa * c.z1 * fv;
+  } else {  // surface point p sits above the bulk point (on1 - 1, p)
+    const int64_t nb = static_cast<int64_t>(c.on1) * npts;
+    const int64_t b = static_cast<int64_t>(c.on1) * p + (c.on1 - 1);
+    const double dub = static_cast<double>(other[(inst * 2) * nb + b]);
+    const double dvb = static_cast<double>(other[(inst * 2 + 1) * nb + b]);
+    const double fu = (c.z2 * wr[0] - c.z3 * orf[0]) + (c.z2 * du - c.z3 * dub);
+    const double fv = (c.e1 * wr[1] - c.e2 * orf[1]) + (c.e1 * dv - c.e2 * dvb);
+    G0 -= c.z1 * fu;
+    G1 -= c.z1 * fv;
+  }
+}
+
 // Same computation with the mode count and species count fixed at compile
 // time: every neighbour load of every species is issued before use.
 template <typename T, int NDIM, int NS>
@@ -254,6 +285,9 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   for (int sp = 0; sp < NS; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
   double G[3] = {0, 0, 0};
   if (a.what != 1 && a.reaction != 0) reaction3c(rc, w[0], w[1], w[2], G[0], G[1], G[2]);
+  if constexpr (NS == 2) {
+    if (a.cp.kind != 0 && a.what != 1) exchange<T>(a, inst, p, i, npts, w[0], w[1], G[0], G[1]);
+  }
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
     double f = a.what != 2 ? diffusion_fast<T, NDIM>(a, Wi + sp * npts, w[sp], sp, inst, p, i, j, k) : 0.0;

@@ -68,6 +68,20 @@ struct GemmArgs {
 template <typename T>
 hipError_t launch_mode_gemm(const GemmArgs& g, hipStream_t s);
 
+// Bulk-surface exchange added to F by the stencil launch (two species on
+// each side; both states in deviation form around their references):
+//   bulk (ball) boundary layer i = n1 - 1, above surface point q = j + n2 k:
+//     F_u += kappa z1 (z2 r - z3 u),   F_v += kappa z1 (e1 s - e2 v)
+//   surface point q:   F_r -= z1 (z2 r - z3 u_b),   F_s -= z1 (e1 s - e2 v_b)
+// with u_b, v_b the bulk values at (n_rho - 1, q).
+struct CoupleArgs {
+  int kind;               // 0 none, 1 bulk side, 2 surface side
+  const void* other;      // partner state (same element type) [batch][2][...]
+  const double* oref;     // partner reference [batch][2]
+  int on1;                // n_rho of the bulk (surface side)
+  double kappa, z1, z2, z3, e1, e2;
+};
+
 // F = d_s * M W (+ G(W)) pointwise stencil over all modes, deviation form.
 struct StencilArgs {
   const void* W;
@@ -87,6 +101,7 @@ struct StencilArgs {
   const double* rparams;    // [batch][4]
   const double* wref;       // [batch][nspecies] reference state (deviation origin)
   const double* g0;         // [batch][nspecies] reaction at the reference state
+  CoupleArgs cp;            // bulk-surface exchange (separate stencil launch only)
 };
 
 template <typename T>

@@ -107,4 +107,7 @@ struct tg_plan_s {
   uint64_t version = 0;
   // grouped runs led by this plan, keyed by (serial, version, state) of members
   std::map<std::vector<uint64_t>, tg_group_s*> groups;
+  // captured bulk-surface steps led by this (bulk) plan, keyed by the
+  // partner's (serial, version), both states and the coupling constants
+  std::map<std::vector<uint64_t>, hipGraphExec_t> coupled_graphs;
 };
