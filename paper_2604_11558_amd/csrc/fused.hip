@@ -446,11 +446,14 @@ constexpr int stencil_batch() { return NT >= 512 ? 4 : 8; }
 
 __host__ __device__ inline int stencil_coef_doubles(int NP, int TN) { return NP * 5 + TN * 7; }
 
-template <typename T, int NT>
+// DIM (2 or 3) and NSP (species) fix the grid's mode and species counts at
+// compile time; 0 reads them from the arguments.
+template <typename T, int NT, int DIM = 0, int NSP = 0>
 __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, int sp, int a0, int NP, int TN, int nm,
                                              int na, T* sX, T* stage, int ld, double* cfd, int tid) {
-  const int ns = st.nspecies;
-  const bool three = st.ndim == 3;
+  const int ns = NSP ? NSP : st.nspecies;
+  const int ndim = DIM ? DIM : st.ndim;
+  const bool three = ndim == 3;
   const int n1 = st.n[0], n2 = st.n[1];
   const int nmx = st.nmax;
   const int64_t plane = static_cast<int64_t>(nm) * na;
@@ -505,6 +508,12 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, in
       k = dtn.quot(e, c);
     }
   };
+  // species read by the reaction besides sp (index clamped for fewer species)
+  const int o0s = ns > 1 ? (sp == 0 ? 1 : 0) : 0;
+  const int o1s = ns > 2 ? (sp == 2 ? 1 : 2) : 0;
+  // Every address below is clamped into the slab (row min(k, nm - 1), the
+  // column's clamped neighbours), so the loads carry no conditions and the
+  // compiler issues them back to back.
   auto request = [&](int e0) {
 #pragma unroll
     for (int q = 0; q < kB; ++q) {
@@ -512,68 +521,106 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, in
       int k, c;
       elem(e, k, c);
       const Col g = colfix ? cf0 : col_of(c);
-      oth[q][0] = oth[q][1] = c0m[q] = c0p[q] = c1m[q] = c1p[q] = T(0);
-      if (e < total && k < nm && g.aa < na) {
-        const int64_t p = static_cast<int64_t>(k) * na;
-        if (diffuse) {
-          c0m[q] = Ws[p + g.im];
-          c0p[q] = Ws[p + g.ip];
-          if (three) {
-            c1m[q] = Ws[p + g.jm];
-            c1p[q] = Ws[p + g.jp];
-          }
-        }
-        if (react) {
-          // the other species, by value (no dynamically indexed arrays)
-          if (ns > 1) oth[q][0] = Wi[(sp == 0 ? 1 : 0) * plane + p + g.aa];
-          if (ns > 2) oth[q][1] = Wi[(sp == 2 ? 1 : 2) * plane + p + g.aa];
-        }
-      }
+      const int64_t p = static_cast<int64_t>(min(k, nm - 1)) * na;
+      const int ac = min(g.aa, na - 1);
+      // (the compute phase reads these only for elements inside the tile,
+      // and each only where its term exists)
+      c0m[q] = Ws[p + g.im];
+      c0p[q] = Ws[p + g.ip];
+      c1m[q] = Ws[p + g.jm];
+      c1p[q] = Ws[p + g.jp];
+      oth[q][0] = Wi[o0s * plane + p + ac];
+      oth[q][1] = Wi[o1s * plane + p + ac];
     }
   };
+  // Operator coefficients: the row (k = tid) and column (c = tid) entries
+  // are requested first, unconditionally (every index is below nmax and
+  // the tables hold 3 x 3 x nmax entries), so one round trip serves all.
+  const double* rcoef = st.coef + rmode * 3 * nmx;
+  const int kr = min(tid, NP - 1), kkr = min(kr, nm - 1);
+  double rsv[3], rcv[3];
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) rsv[mu] = st.scale[mu * 3 * nmx + rslot * nmx + kkr];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) rcv[x] = rcoef[x * nmx + kkr];
+  const int cq = min(tid, TN - 1), acq = min(a0 + cq, na - 1);
+  int ci = acq, cj = 0;
+  if (three) cj = dn1.quot(acq, ci);
+  double csv[3][2], ccv[2][3];
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) {
+    csv[mu][0] = st.scale[mu * 3 * nmx + ci];
+    csv[mu][1] = st.scale[mu * 3 * nmx + nmx + cj];
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int x = 0; x < 3; ++x) ccv[m][x] = st.coef[m * 3 * nmx + x * nmx + (m == 0 ? ci : cj)];
   request(0);
-  for (int k = tid; k < NP; k += NT) {
-    const int kk = min(k, nm - 1);
-    const double* c = st.coef + rmode * 3 * nmx;
+  // row table: rs_0, rs_1, L, D, U = rs_r * (lo, dg, up) of the row mode
+  auto put_row = [&](int k, const double (&rs_)[3], const double (&c_)[3]) {
     double rs[3];
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
-      const bool on = mu < st.ndim && ((st.scale_mask >> (3 * mu + rslot)) & 1);
-      rs[mu] = on ? st.scale[mu * 3 * nmx + rslot * nmx + kk] : 1.0;
+      const bool on = mu < ndim && ((st.scale_mask >> (3 * mu + rslot)) & 1);
+      rs[mu] = on ? rs_[mu] : 1.0;
     }
     const double rr = three ? rs[2] : rs[1];
     rc[k * 5 + 0] = rs[0];
     rc[k * 5 + 1] = three ? rs[1] : 0.0;
-    rc[k * 5 + 2] = rr * c[kk];
-    rc[k * 5 + 3] = rr * c[nmx + kk];
-    rc[k * 5 + 4] = rr * c[2 * nmx + kk];
+    rc[k * 5 + 2] = rr * c_[0];
+    rc[k * 5 + 3] = rr * c_[1];
+    rc[k * 5 + 4] = rr * c_[2];
+  };
+  if (tid < NP) put_row(tid, rsv, rcv);
+  for (int k = tid + NT; k < NP; k += NT) {  // only when NP > NT
+    const int kk = min(k, nm - 1);
+    double a_[3], b_[3];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) a_[mu] = st.scale[mu * 3 * nmx + rslot * nmx + kk];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) b_[x] = rcoef[x * nmx + kk];
+    put_row(k, a_, b_);
   }
-  for (int c = tid; c < TN; c += NT) {
-    const int aa = min(a0 + c, na - 1);
-    int i = aa, j = 0;
-    if (three) j = dn1.quot(aa, i);
+  // column table: A_m, B_m, C_m = cs_m * (lo, dg, up) of column mode m, and
+  // cs_r (the row mode's column scale)
+  auto put_col = [&](int c, const double (&cs_)[3][2], const double (&q_)[2][3]) {
     double cs[3];
 #pragma unroll
     for (int mu = 0; mu < 3; ++mu) {
       double f = 1.0;
-      if (mu < st.ndim) {
+      if (mu < ndim) {
         const int sm = st.scale_mask >> (3 * mu);
-        const double* sc = st.scale + mu * 3 * nmx;
-        if (sm & 1) f *= sc[i];
-        if (three && (sm & 2)) f *= sc[nmx + j];
+        if (sm & 1) f *= cs_[mu][0];
+        if (three && (sm & 2)) f *= cs_[mu][1];
       }
       cs[mu] = f;
     }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const bool col_mode = m == 0 || three;
-      const int x = m == 0 ? i : j;
-      const double* q = st.coef + m * 3 * nmx;
-      cc[c * 7 + 3 * m + 0] = col_mode ? cs[m] * q[x] : 0.0;
-      cc[c * 7 + 3 * m + 1] = col_mode ? cs[m] * q[nmx + x] : 0.0;
-      cc[c * 7 + 3 * m + 2] = col_mode ? cs[m] * q[2 * nmx + x] : 0.0;
+      cc[c * 7 + 3 * m + 0] = col_mode ? cs[m] * q_[m][0] : 0.0;
+      cc[c * 7 + 3 * m + 1] = col_mode ? cs[m] * q_[m][1] : 0.0;
+      cc[c * 7 + 3 * m + 2] = col_mode ? cs[m] * q_[m][2] : 0.0;
     }
     cc[c * 7 + 6] = three ? cs[2] : cs[1];
+  };
+  if (tid < TN) put_col(tid, csv, ccv);
+  for (int c = tid + NT; c < TN; c += NT) {  // only when TN > NT
+    const int aa = min(a0 + c, na - 1);
+    int i = aa, j = 0;
+    if (three) j = dn1.quot(aa, i);
+    double a_[3][2], b_[2][3];
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      a_[mu][0] = st.scale[mu * 3 * nmx + i];
+      a_[mu][1] = st.scale[mu * 3 * nmx + nmx + j];
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int x = 0; x < 3; ++x) b_[m][x] = st.coef[m * 3 * nmx + x * nmx + (m == 0 ? i : j)];
+    put_col(c, a_, b_);
   }
   load_tile_kmajor<T, NT>(Ws, na, nm, a0, NP, TN, stage, ld, tid);
   __syncthreads();  // staged centres and coefficients
@@ -683,7 +730,15 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
     // The stencil launch is always the last mode (nb == 1): the column a
     // holds the faster coordinates, the row k the slowest one.
     double* cfs = reinterpret_cast<double*>(sT + NP * ld);
-    stencil_tile<T, NT>(a.st, s / a.st.nspecies, s % a.st.nspecies, a0, NP, TN, nm, na, sX, sT, ld, cfs, tid);
+    const int sns = a.st.nspecies, inst = s / sns, sp = s % sns;
+    // the common shapes with their mode and species counts fixed (fewer
+    // branches and live scalars in the staging and arithmetic)
+    if (a.st.ndim == 3 && sns == 2)
+      stencil_tile<T, NT, 3, 2>(a.st, inst, sp, a0, NP, TN, nm, na, sX, sT, ld, cfs, tid);
+    else if (a.st.ndim == 2 && sns == 2)
+      stencil_tile<T, NT, 2, 2>(a.st, inst, sp, a0, NP, TN, nm, na, sX, sT, ld, cfs, tid);
+    else
+      stencil_tile<T, NT>(a.st, inst, sp, a0, NP, TN, nm, na, sX, sT, ld, cfs, tid);
   } else {
     load_tile_kmajor<T, NT>(static_cast<const T*>(a.X) + base, na, nm, a0, NP, TN, sX, ld, tid);
   }
