@@ -36,8 +36,9 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11004473, "fused:1:16,64": 13292695}
-TRAFFIC_DIGEST = "5e7a8fffacafe4904e49d6315c07765ba2122b2cc5ecc8b99fd4ae60efe201e6"
+TRAFFIC = {"fused:0:16,64": 11019983, "fused:1:16,64": 13298844,
+           "fused_stencil_apart:0:32,64": 9819774, "fused_stencil_apart:1:32,64": 13298849}
+TRAFFIC_DIGEST = "caf7f5f4e84c7a83a620cdd065e629e7b983a203582d4d6ab50fd970938880bd"
 
 
 def cpu_model() -> str:
@@ -273,6 +274,9 @@ def main():
                     help="only launch --steps FP32 steps and a calibration copy (for rocprofv3)")
     ap.add_argument("--route", default="", help="--profile: launch route (default: the plan's)")
     ap.add_argument("--tiles", default="", help="--profile: comma-separated tile widths")
+    ap.add_argument("--fp32-config", default="",
+                    help="route:tiles for the FP32 headline instead of the autotuner's choice "
+                         "(e.g. fused:16,64; used to profile a fixed configuration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -299,7 +303,14 @@ def main():
         setup = time.perf_counter() - t0
         x = plan.state_from_deviation(pert)
         # launch configuration: route and tile widths chosen by the autotuner
-        tune = plan.autotune(x, iters=20)
+        # (or given for FP32)
+        if prec == "fp32" and args.fp32_config:
+            rname, tl = args.fp32_config.split(":")
+            plan.set_route(rname)
+            plan.set_tiles([int(t) for t in tl.split(",")])
+            tune = {"tiles": plan.tiles(), "us_per_step": None}
+        else:
+            tune = plan.autotune(x, iters=20)
         route = plan.route
         # timed region: W warm-up steps, then K steps replayed from the
         # captured graph (tg_run), synchronised on both sides
