@@ -168,7 +168,7 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
 int tg_step_diag(tg_plan p, void* state, double* diag, void* stream);
 /* n_steps steps; after steps every, 2 every, ... records the indicators of
  * that step into diag[r][batch][n_species][2] (device memory for
- * n_steps / every records).  The steps between records replay captured
+ * n_steps / every records; may be NULL when that is 0).  The steps between records replay captured
  * graphs.  Synchronises and checks for non-finite values like tg_run. */
 int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* diag, void* stream);
 

@@ -1514,11 +1514,12 @@ int tg_step_diag(tg_plan p, void* state, double* diag, void* stream) {
 
 int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* diag, void* stream) {
   return guarded([&] {
-    TG_REQUIRE(p && state && diag && n_steps >= 0 && every >= 1, TG_EINVAL, "tg_run_diag: bad argument");
+    TG_REQUIRE(p && state && n_steps >= 0 && every >= 1, TG_EINVAL, "tg_run_diag: bad argument");
+    TG_REQUIRE(diag || n_steps / every == 0, TG_EINVAL, "tg_run_diag: null record buffer");
     TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_diag: state must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    tg::DiagArgs d = diag_args(p, diag);
     const int64_t records = n_steps / every;
+    tg::DiagArgs d = records > 0 ? diag_args(p, diag) : tg::DiagArgs{};
     int64_t done = 0;
     for (int64_t r = 0; r < records; ++r) {
       // every - 1 plain steps (graph replays of kStepsPerGraph, then single

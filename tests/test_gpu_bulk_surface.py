@@ -134,6 +134,32 @@ def test_exchange_conserves_mass(precision, tol):
     assert moved > 1e-3 and np.isfinite(s1).all() and np.abs(s1).max() < 10.0
 
 
+def test_batch_of_two_instances():
+    """Two instances per plan (different initial data): instance b of the
+    ball exchanges with instance b of the sphere only."""
+    n = (8, 10, 9)
+    pb = (P["alpha2"], P["beta1"], P["alpha1"])
+    ps = (P["alpha2"], P["beta1"], P["zeta1"])
+    bulk = tg.Plan(tg.Grid("ball", n), [(1.0, P["delta"])], "schnakenberg_scaled", pb, 1e-4, "fp64", batch=2)
+    surf = tg.Plan(tg.Grid("sphere", n[1:]), [(1.0, P["epsilon"])], "schnakenberg_scaled", ps, 1e-4, "fp64",
+                   batch=2)
+    draws = [workloads.bulk_surface_perturbations(n, 20 + b) for b in range(2)]
+    xb = bulk.state_from_deviation(np.stack([d[0] for d in draws]))
+    xs = surf.state_from_deviation(np.stack([d[1] for d in draws]))
+    tg.coupled_run(bulk, surf, xb, xs, COUPLING, 6)
+    oracle = BS.BulkSurface(n, 1e-4)
+    fb = xb.double().cpu().numpy() + bulk.reference[:, :, None, None, None]
+    fs = xs.double().cpu().numpy() + surf.reference[:, :, None, None]
+    for b in range(2):
+        U = [bulk.reference[b, q] + assemble.from_layout(draws[b][0][q]) for q in range(2)]
+        S = [surf.reference[b, q] + assemble.from_layout(draws[b][1][q]) for q in range(2)]
+        for _ in range(6):
+            U, S = oracle.step(U, S)
+        rb = np.stack([assemble.to_layout(u) for u in U])
+        rs = np.stack([assemble.to_layout(v) for v in S])
+        assert rel_err(fb[b], rb) < 1e-12 and rel_err(fs[b], rs) < 1e-12, b
+
+
 def test_mismatched_plans_are_rejected():
     pair = Pair((6, 8, 7), "fp64")
     xb, xs = pair.states()

@@ -124,6 +124,11 @@ def test_run_diag_records_and_state(precision):
     case.plan.run(y, 21)
     assert rec.shape == (5, 1, 2, 2)
     assert torch.equal(x, y)
+    # fewer steps than one record: plain steps, an empty record buffer
+    x2, y2 = x.clone(), x.clone()
+    assert case.plan.run_diag(x2, 3, every=4).shape[0] == 0
+    case.plan.run(y2, 3)
+    assert torch.equal(x2, y2)
     for r in range(5):
         case.plan.run(z, 3)
         old = _dev(case, z)
