@@ -524,38 +524,49 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs& st, int inst, in
       const int64_t p = static_cast<int64_t>(min(k, nm - 1)) * na;
       const int ac = min(g.aa, na - 1);
       // (the compute phase reads these only for elements inside the tile,
-      // and each only where its term exists)
+      // and each only where its term exists; with the mode and species
+      // counts fixed, the loads of absent terms are left out)
       c0m[q] = Ws[p + g.im];
       c0p[q] = Ws[p + g.ip];
-      c1m[q] = Ws[p + g.jm];
-      c1p[q] = Ws[p + g.jp];
+      if (DIM == 0 || DIM == 3) {
+        c1m[q] = Ws[p + g.jm];
+        c1p[q] = Ws[p + g.jp];
+      } else {
+        c1m[q] = c1p[q] = T(0);
+      }
       oth[q][0] = Wi[o0s * plane + p + ac];
-      oth[q][1] = Wi[o1s * plane + p + ac];
+      oth[q][1] = NSP == 0 || NSP > 2 ? Wi[o1s * plane + p + ac] : T(0);
     }
   };
   // Operator coefficients: the row (k = tid) and column (c = tid) entries
-  // are requested first, unconditionally (every index is below nmax and
-  // the tables hold 3 x 3 x nmax entries), so one round trip serves all.
+  // are requested first (every index is below nmax and the tables hold
+  // 3 x 3 x nmax entries), so one round trip serves all.
+  // (only the threads that own a row or a column load; whole waves past
+  // them skip the loads)
   const double* rcoef = st.coef + rmode * 3 * nmx;
-  const int kr = min(tid, NP - 1), kkr = min(kr, nm - 1);
-  double rsv[3], rcv[3];
+  double rsv[3] = {1.0, 1.0, 1.0}, rcv[3] = {0.0, 0.0, 0.0};
+  if (tid < NP) {
+    const int kkr = min(tid, nm - 1);
 #pragma unroll
-  for (int mu = 0; mu < 3; ++mu) rsv[mu] = st.scale[mu * 3 * nmx + rslot * nmx + kkr];
+    for (int mu = 0; mu < 3; ++mu) rsv[mu] = st.scale[mu * 3 * nmx + rslot * nmx + kkr];
 #pragma unroll
-  for (int x = 0; x < 3; ++x) rcv[x] = rcoef[x * nmx + kkr];
-  const int cq = min(tid, TN - 1), acq = min(a0 + cq, na - 1);
-  int ci = acq, cj = 0;
-  if (three) cj = dn1.quot(acq, ci);
-  double csv[3][2], ccv[2][3];
-#pragma unroll
-  for (int mu = 0; mu < 3; ++mu) {
-    csv[mu][0] = st.scale[mu * 3 * nmx + ci];
-    csv[mu][1] = st.scale[mu * 3 * nmx + nmx + cj];
+    for (int x = 0; x < 3; ++x) rcv[x] = rcoef[x * nmx + kkr];
   }
+  double csv[3][2] = {{1.0, 1.0}, {1.0, 1.0}, {1.0, 1.0}}, ccv[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  if (tid < TN) {
+    const int acq = min(a0 + tid, na - 1);
+    int ci = acq, cj = 0;
+    if (three) cj = dn1.quot(acq, ci);
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+    for (int mu = 0; mu < 3; ++mu) {
+      csv[mu][0] = st.scale[mu * 3 * nmx + ci];
+      csv[mu][1] = st.scale[mu * 3 * nmx + nmx + cj];
+    }
 #pragma unroll
-    for (int x = 0; x < 3; ++x) ccv[m][x] = st.coef[m * 3 * nmx + x * nmx + (m == 0 ? ci : cj)];
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int x = 0; x < 3; ++x) ccv[m][x] = st.coef[m * 3 * nmx + x * nmx + (m == 0 ? ci : cj)];
+  }
   request(0);
   // row table: rs_0, rs_1, L, D, U = rs_r * (lo, dg, up) of the row mode
   auto put_row = [&](int k, const double (&rs_)[3], const double (&c_)[3]) {
