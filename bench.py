@@ -36,9 +36,9 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11019983, "fused:1:16,64": 13298844,
-           "fused_stencil_apart:0:32,64": 9819774, "fused_stencil_apart:1:32,64": 13298849}
-TRAFFIC_DIGEST = "caf7f5f4e84c7a83a620cdd065e629e7b983a203582d4d6ab50fd970938880bd"
+TRAFFIC = {"fused:0:16,64": 11011748, "fused:1:16,64": 13311141,
+           "fused_stencil_apart:0:32,64": 9792135, "fused_stencil_apart:1:32,64": 13311137}
+TRAFFIC_DIGEST = "bd91bdb1ae12efcc1406b229e0c4c9b48137bfab5597b633a2bcf76a204c5f36"
 
 
 def cpu_model() -> str:
