@@ -34,7 +34,7 @@ from .splitee import SplitEE
 
 # Section 5.5: alpha_1 = zeta_1 = 55, alpha_2 = 0.1, beta_1 = 0.9,
 # zeta_2 = zeta_3 = 5/12, eta_1 = eta_2 = 5, delta = epsilon = 10
-PAPER = dict(alpha1=55.0, alpha2=0.1, beta1=0.9, zeta1=55.0, zeta2=5.0 / 12.0, zeta3=5.0 / 12.0,
+PARAMS = dict(alpha1=55.0, alpha2=0.1, beta1=0.9, zeta1=55.0, zeta2=5.0 / 12.0, zeta3=5.0 / 12.0,
              eta1=5.0, eta2=5.0, delta=10.0, epsilon=10.0)
 
 
@@ -44,7 +44,7 @@ def kappa(n_rho: int, rho_star: float = 1.0) -> float:
     return (2.0 / h) * (1.0 + h / rho_star)
 
 
-def equilibrium(p=PAPER):
+def equilibrium(p=PARAMS):
     ue, ve = R.schnakenberg_equilibrium(p["alpha2"], p["beta1"])
     return [ue, ve], [ue, ve]
 
@@ -58,7 +58,7 @@ class BulkSurface:
     pin); fields are [i, j, k] (ball) and [j, k] (surface) arrays.
     """
 
-    def __init__(self, n, tau, p=PAPER, kinetics=True):
+    def __init__(self, n, tau, p=PARAMS, kinetics=True):
         self.n, self.tau, self.p, self.kinetics = tuple(n), tau, dict(p), kinetics
         self.ball = SplitEE("ball", self.n, [1.0, p["delta"]], tau, (1.0, 1.0))
         self.surface = SplitEE("sphere", (self.n[1], self.n[2]), [1.0, p["epsilon"]], tau, (1.0, 1.0))

@@ -14,7 +14,7 @@ from oracle import assemble, bulk_surface as BS, operators as op
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-P = BS.PAPER
+P = BS.PARAMS
 COUPLING = (P["zeta1"], P["zeta2"], P["zeta3"], P["eta1"], P["eta2"])
 
 

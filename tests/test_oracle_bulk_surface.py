@@ -95,7 +95,7 @@ def test_coupling_against_assembled_operator():
     assembled as one sparse matrix: diffusion blocks plus the Robin entries
     of the boundary layer and the exchange entries of the surface."""
     n = (5, 6, 7)
-    p = BS.PAPER
+    p = BS.PARAMS
     sys = BS.BulkSurface(n, 1e-3, kinetics=False)
     Mb = assemble.laplacian("ball", n)
     Ms = assemble.laplacian("sphere", n[1:])
