@@ -35,7 +35,7 @@ from .splitee import SplitEE
 # Section 5.5: alpha_1 = zeta_1 = 55, alpha_2 = 0.1, beta_1 = 0.9,
 # zeta_2 = zeta_3 = 5/12, eta_1 = eta_2 = 5, delta = epsilon = 10
 PARAMS = dict(alpha1=55.0, alpha2=0.1, beta1=0.9, zeta1=55.0, zeta2=5.0 / 12.0, zeta3=5.0 / 12.0,
-             eta1=5.0, eta2=5.0, delta=10.0, epsilon=10.0)
+              eta1=5.0, eta2=5.0, delta=10.0, epsilon=10.0)
 
 
 def kappa(n_rho: int, rho_star: float = 1.0) -> float:
