@@ -852,6 +852,7 @@ tg::StencilArgs stencil_args(const tg_plan_s* P, const void* W, void* F, int wha
 tg::StridedArgs strided_args_for(const tg_plan_s* P, const tg::FusedOp& op, const void* src, void* dst,
                                  bool update, bool from_state) {
   tg::StridedArgs a = op.sa;
+  a.flag = P->dflag;  // allocated after the ops are built
   if (!from_state) a.stencil = 0;
   if (a.stencil) {
     a.st = stencil_args(P, src, nullptr, TG_APPLY_F);
@@ -869,8 +870,9 @@ tg::StridedArgs strided_args_for(const tg_plan_s* P, const tg::FusedOp& op, cons
   return a;
 }
 
-tg::FirstArgs first_args_for(const tg::FusedOp& op, const void* src, void* dst, bool update) {
+tg::FirstArgs first_args_for(const tg_plan_s* P, const tg::FusedOp& op, const void* src, void* dst, bool update) {
   tg::FirstArgs a = op.fa;
+  a.flag = P->dflag;  // allocated after the ops are built
   a.X = src;
   a.Y = dst;
   a.update = update ? 1 : 0;
@@ -891,7 +893,7 @@ void launch_fused(const tg_plan_s* P, const tg::FusedOp& op, const void* src, vo
     mark_launch(st);
     hip_check(nt ? tg::launch_strided_bf16(nt, a, st) : tg::launch_strided<T>(a, st), "fused strided launch");
   } else {
-    tg::FirstArgs a = first_args_for(op, src, dst, update);
+    tg::FirstArgs a = first_args_for(P, op, src, dst, update);
     if (dg) a.dg = *dg;
     mark_launch(st);
     hip_check(nt ? tg::launch_first_bf16(nt, a, st) : tg::launch_first<T>(a, st), "fused first-mode launch");
@@ -1259,7 +1261,7 @@ bool build_group_launches(tg_group_s* G) {
       int tm = 16;
       for (int q = 0; q < n; ++q) {
         const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->route);
-        g.a[q] = first_args_for(G->plans[q]->fused[k], io.in, io.out, io.update);
+        g.a[q] = first_args_for(G->plans[q], G->plans[q]->fused[k], io.in, io.out, io.update);
         tm = std::max(tm, g.a[q].tm);
       }
       for (int q = 0; q < n; ++q) g.a[q].tm = tm;

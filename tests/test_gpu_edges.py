@@ -1,0 +1,66 @@
+"""Edge cases of the device entry points: zero steps leave every state bit
+for bit unchanged, a non-finite value raised by an update is reported (and
+the flag cleared for the next run), misaligned or mismatched buffers are
+refused before any launch."""
+import numpy as np
+import pytest
+
+import paper_2604_11558_amd as tg
+from gpu_helpers import Case
+from oracle import bulk_surface as BS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("geometry,n", [("disk", (12, 16)), ("ball", (8, 10, 12))])
+def test_zero_steps_change_nothing(geometry, n):
+    case = Case(geometry, n, "fp32", seed=2)
+    x = case.device_state()
+    y = x.clone()
+    case.plan.run(x, 0)
+    assert torch.equal(x, y)
+    assert case.plan.run_diag(x, 0, every=1).shape[0] == 0
+    assert torch.equal(x, y)
+    tg.group_run([case.plan], [x], 0)
+    assert torch.equal(x, y)
+
+
+def test_zero_coupled_steps_change_nothing():
+    p = BS.PARAMS
+    n = (6, 8, 7)
+    bulk = tg.Plan(tg.Grid("ball", n), [(1.0, 10.0)], "schnakenberg_scaled", (0.1, 0.9, 55.0), 1e-4, "fp64")
+    surf = tg.Plan(tg.Grid("sphere", n[1:]), [(1.0, 10.0)], "schnakenberg_scaled", (0.1, 0.9, 55.0), 1e-4, "fp64")
+    xb = bulk.state_from_deviation(1e-3 * np.ones(bulk.state_shape))
+    xs = surf.state_from_deviation(1e-3 * np.ones(surf.state_shape))
+    yb, ys = xb.clone(), xs.clone()
+    tg.coupled_run(bulk, surf, xb, xs, (p["zeta1"], p["zeta2"], p["zeta3"], p["eta1"], p["eta2"]), 0)
+    assert torch.equal(xb, yb) and torch.equal(xs, ys)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_non_finite_state_is_reported_then_cleared(precision):
+    case = Case("disk", (12, 16), precision, seed=3)
+    x = case.device_state()
+    x.view(-1)[5] = float("nan")
+    with pytest.raises(tg.TGError) as ei:
+        case.plan.run(x, 3)
+    assert "non-finite" in str(ei.value)
+    # the flag was cleared: a clean state runs again without error
+    z = case.device_state()
+    case.plan.run(z, 3)
+    assert torch.isfinite(z).all()
+
+
+def test_misaligned_and_mismatched_buffers_are_refused():
+    case = Case("disk", (12, 16), "fp64", seed=4)
+    x = case.device_state()
+    big = torch.zeros(x.numel() + 1, dtype=x.dtype, device=x.device)
+    view = big[1:]                      # contiguous, but 8 bytes off the 32-byte vector alignment
+    assert view.is_contiguous() and view.numel() == x.numel()
+    with pytest.raises(tg.TGError):
+        case.plan.step(view)
+    with pytest.raises(ValueError):
+        case.plan.step(x.float())       # wrong element type
+    with pytest.raises(ValueError):
+        case.plan.step(x[..., :-1].contiguous())  # wrong size
