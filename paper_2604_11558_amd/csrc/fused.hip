@@ -332,6 +332,28 @@ __device__ __forceinline__ void load_tile_kmajor(const T* __restrict__ X, int na
   const Div dtn(TN);
   if (na % 4 == 0) {
     const int nvec = NP * TN / 4;
+    if (nvec <= 2 * NT) {  // the usual small tile: at most two vectors per thread
+      v4 r[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int v = tid + NT * q;
+        int c;
+        const int k = dtn.quot(4 * v, c);
+        r[q] = v4{0, 0, 0, 0};
+        if (v < nvec && k < nm && a0 + c < na)
+          r[q] = *reinterpret_cast<const v4*>(X + static_cast<int64_t>(k) * na + a0 + c);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int v = tid + NT * q;
+        if (v < nvec) {
+          int c;
+          const int k = dtn.quot(4 * v, c);
+          *reinterpret_cast<v4*>(sX + k * ld + c) = r[q];
+        }
+      }
+      return;
+    }
     for (int v0 = 0; v0 < nvec; v0 += NT * kBatch) {
       v4 r[kBatch];
 #pragma unroll
@@ -370,6 +392,28 @@ __device__ __forceinline__ void load_tile_rows(const T* __restrict__ X, int nm, 
   const Div dnp(NP);
   if (nm % 4 == 0) {
     const int nvec = TM * NP / 4;
+    if (nvec <= 2 * NT) {  // the usual small tile: at most two vectors per thread
+      v4 r[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int v = tid + NT * q;
+        int c;
+        const int rr = dnp.quot(4 * v, c);
+        r[q] = v4{0, 0, 0, 0};
+        if (v < nvec && c < nm && rt0 + rr < rows)
+          r[q] = *reinterpret_cast<const v4*>(X + static_cast<int64_t>(rt0 + rr) * nm + c);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int v = tid + NT * q;
+        if (v < nvec) {
+          int c;
+          const int rr = dnp.quot(4 * v, c);
+          *reinterpret_cast<v4*>(sX + rr * ld + c) = r[q];
+        }
+      }
+      return;
+    }
     for (int v0 = 0; v0 < nvec; v0 += NT * kBatch) {
       v4 r[kBatch];
 #pragma unroll
@@ -888,13 +932,18 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
 }
 
 // 8-wave FP32 workgroups with one-row sub-tiles (many workgroups) are held
-// to 128 VGPRs (4 waves per SIMD) so that two share a CU; the others may
-// use up to 256.
-template <typename T, int FM, int NW>
-constexpr int waves_per_eu() { return (NW == 8 && sizeof(T) == 4 && FM == 1) ? 4 : (NW == 8 ? 2 : 1); }
+// to 128 VGPRs (4 waves per SIMD) so that two share a CU, and the other
+// 8-wave ones and the FP32 runtime-K ones to 256 registers (2 waves per
+// SIMD: the runtime-K variant otherwise lands just above and runs at one);
+// the others may use more.
+template <typename T, int FM, int NW, int KCH>
+constexpr int waves_per_eu() {
+  if (NW == 8) return (sizeof(T) == 4 && FM == 1) ? 4 : 2;
+  return (sizeof(T) == 4 && KCH == 0) ? 2 : 1;
+}
 
 template <typename T, int FM, int FN, int KCH, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW, KCH>())))
 void strided_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
   // 1D grid of 8 * per_xcd workgroups, dispatched round-robin over the 8
@@ -1057,7 +1106,7 @@ __device__ __forceinline__ int group_member(const GroupMap& m, int L, int& local
 }
 
 template <typename T, int FM, int FN, int KCH, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW, KCH>())))
 void strided_group_kernel(const StridedGroup* __restrict__ grp) {
   extern __shared__ __align__(256) unsigned char smem[];
   const GroupMap& m = grp->map;
