@@ -745,7 +745,7 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
   constexpr int KR = KCH > 0 ? KCH : 1;  // register prefetch extent
   // cross-product prefetch only where two factor register sets fit
   // (FP64 with 128-long contractions keeps one set, loaded per product)
-  constexpr bool kPre = KCH > 0 && (NW == 4 || FM > 1) && sizeof(T) * FM * KCH * 4 <= 256;
+  constexpr bool kPre = KCH > 0 && (NW == 4 || FM > 1) && sizeof(T) * FM * KCH * 4 <= (sizeof(T) == 8 ? 128 : 256);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int nm = a.nm, na = a.na, TN = a.tn;
@@ -936,14 +936,20 @@ __device__ __forceinline__ void strided_tile(const StridedArgs& a, int bx, int b
 // 8-wave ones and the FP32 runtime-K ones to 256 registers (2 waves per
 // SIMD: the runtime-K variant otherwise lands just above and runs at one);
 // the others may use more.
-template <typename T, int FM, int NW, int KCH>
+template <typename T, int FM, int FN, int NW, int KCH>
 constexpr int waves_per_eu() {
   if (NW == 8) return (sizeof(T) == 4 && FM == 1) ? 4 : 2;
-  return (sizeof(T) == 4 && KCH == 0) ? 2 : 1;
+  if (sizeof(T) == 4) return KCH == 0 ? 2 : 1;
+  // FP64: the variants that fit 256 registers (spilling at most a few bytes)
+  return (FM == 2 && KCH > 0 && !(FN == 2 && KCH == 8)) ? 2 : 1;
 }
+// The persistent grouped kernels carry more live state: FP64 ones keep the
+// uncapped register budget.
+template <typename T, int FM, int FN, int NW, int KCH>
+constexpr int group_waves_per_eu() { return sizeof(T) == 8 && NW == 4 ? 1 : waves_per_eu<T, FM, FN, NW, KCH>(); }
 
 template <typename T, int FM, int FN, int KCH, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW, KCH>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, FN, NW, KCH>())))
 void strided_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
   // 1D grid of 8 * per_xcd workgroups, dispatched round-robin over the 8
@@ -1106,7 +1112,7 @@ __device__ __forceinline__ int group_member(const GroupMap& m, int L, int& local
 }
 
 template <typename T, int FM, int FN, int KCH, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(waves_per_eu<T, FM, NW, KCH>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(group_waves_per_eu<T, FM, FN, NW, KCH>())))
 void strided_group_kernel(const StridedGroup* __restrict__ grp) {
   extern __shared__ __align__(256) unsigned char smem[];
   const GroupMap& m = grp->map;
