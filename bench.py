@@ -36,9 +36,9 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11012775, "fused:1:16,64": 13298850,
-           "fused_stencil_apart:0:32,64": 9770630, "fused_stencil_apart:1:32,64": 13298854}
-TRAFFIC_DIGEST = "a20121f6d8d1bc32843903d4ef650029cbafb3d8d4ca35ffb4b1e0a566c51f42"
+TRAFFIC = {"fused:0:16,64": 11013804, "fused:1:16,64": 13312159,
+           "fused_stencil_apart:0:32,64": 9792119, "fused_stencil_apart:1:32,64": 13312165}
+TRAFFIC_DIGEST = "e9cf07af8d15c513a76eb0b0e7b5d6d52314ad8b6d1dfd2b400e4961c938ec0f"
 
 
 def cpu_model() -> str:
