@@ -30,7 +30,7 @@ import workloads  # noqa: E402
 METRIC = "dof-steps/s per GPU (FP32-MFMA vs FP64) at stated rel. error vs FP64 oracle"
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}  # dense MFMA FLOP/s, MI355X
 HBM_PEAK = 8.0e12
-KERNEL_SOURCES = ("fused.hip", "fused.hpp", "stencil_dev.hpp", "kernels.hpp")
+KERNEL_SOURCES = ("fused.hip", "fused.hpp", "stencil_dev.hpp", "kernels.hpp", "phi_dev.hpp")
 COPY_BYTES = 256 << 20
 # HBM traffic per launch (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3

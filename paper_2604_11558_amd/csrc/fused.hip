@@ -12,6 +12,7 @@
 
 #include "fused.hpp"
 #include "diag_dev.hpp"
+#include "phi_dev.hpp"
 #include "stencil_dev.hpp"
 
 namespace tg {
@@ -38,7 +39,7 @@ template <> struct M16<float> {
   }
   // accumulator element r of lane group g is row 4 g + r (FP32 layout)
   static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
-  static __device__ __forceinline__ float phi1(float x) { return x == 0.0f ? 1.0f : expm1f(x) / x; }
+  static __device__ __forceinline__ float phi1(float x) { return phi1_f32(x); }
 };
 
 static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }

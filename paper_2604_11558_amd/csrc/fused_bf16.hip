@@ -14,6 +14,7 @@
 
 #include "fused.hpp"
 #include "diag_dev.hpp"
+#include "phi_dev.hpp"
 #include "stencil_dev.hpp"
 
 namespace tg {
@@ -36,7 +37,7 @@ __device__ __forceinline__ void split_terms(float x, __bf16 (&t)[NT]) {
   }
 }
 
-__device__ __forceinline__ float phi1f(float x) { return x == 0.0f ? 1.0f : expm1f(x) / x; }
+__device__ __forceinline__ float phi1f(float x) { return phi1_f32(x); }
 
 // LDS pitch (bf16 elements) of a k-contiguous row of NP values: the byte
 // stride 2 NP + 16 puts 8 consecutive rows on distinct 16-byte bank groups.
