@@ -36,9 +36,9 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11013804, "fused:1:16,64": 13312159,
-           "fused_stencil_apart:0:32,64": 9792119, "fused_stencil_apart:1:32,64": 13312165}
-TRAFFIC_DIGEST = "e9cf07af8d15c513a76eb0b0e7b5d6d52314ad8b6d1dfd2b400e4961c938ec0f"
+TRAFFIC = {"fused:0:16,64": 10997411, "fused:1:16,64": 13327521,
+           "fused_stencil_apart:0:32,64": 9828970, "fused_stencil_apart:1:32,64": 13327519}
+TRAFFIC_DIGEST = "9f55c083ef8628e888476aa7473df5dd5b7227a9b7d7ca9d198ea3e3110c5f13"
 
 
 def cpu_model() -> str:
