@@ -139,8 +139,14 @@ int tg_plan_state_size(tg_plan p, int64_t* elems, int32_t* elem_bytes);
 /* The reference state w_ref used by the plan, [batch][n_species]. */
 int tg_plan_reference(tg_plan p, double* w_ref);
 
-/* One step of the split exponential Euler method on `state` (in place). */
+/* One step of the split exponential Euler method on `state` (in place).
+ * Asynchronous: a non-finite value it writes is reported by the next
+ * tg_run / tg_run_diag or by tg_sync_status. */
 int tg_step(tg_plan p, void* state, void* stream);
+/* Synchronise `stream` and report whether any update of this plan since the
+ * last report wrote a non-finite value (TG_ENONFINITE; the flag is then
+ * cleared).  For callers that step with tg_step / tg_step_diag. */
+int tg_sync_status(tg_plan p, void* stream);
 /* n_steps steps (in place); steps are replayed from a captured HIP graph.
  * Synchronises the stream at the end and returns TG_ENONFINITE if any
  * update produced a non-finite value. */

@@ -48,6 +48,7 @@ _SIGNATURES = {
     "tg_step": (ctypes.c_int, [_p, _p, _p]),
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
     "tg_step_diag": (ctypes.c_int, [_p, _p, _p, _p]),
+    "tg_sync_status": (ctypes.c_int, [_p, _p]),
     "tg_coupled_step": (ctypes.c_int, [_p, _p, _p, _p, _pd, _p]),
     "tg_coupled_run": (ctypes.c_int, [_p, _p, _p, _p, _pd, _c_i64, _p]),
     "tg_run_diag": (ctypes.c_int, [_p, _p, _c_i64, _c_int, _p, _p]),
@@ -232,6 +233,10 @@ class Plan:
     def run(self, state, n_steps: int, stream=None):
         self._check_tensor(state)
         _check(lib().tg_run(self._h, state.data_ptr(), int(n_steps), _stream_ptr(stream)))
+
+    def sync_status(self, stream=None):
+        """Synchronise the stream; raise TGError if a step wrote a non-finite value."""
+        _check(lib().tg_sync_status(self._h, _stream_ptr(stream)))
 
     def step_diag(self, state, stream=None):
         """One step; returns a [batch, n_species, 2] float64 device tensor of

@@ -1504,6 +1504,21 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
   });
 }
 
+int tg_sync_status(tg_plan p, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p, TG_EINVAL, "tg_sync_status: null plan");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int flag = 0;
+    hip_check(hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "tg_sync_status: flag copy");
+    hip_check(hipStreamSynchronize(st), "tg_sync_status: synchronize");
+    if (flag) {
+      hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_sync_status: flag reset");
+      throw Fail(TG_ENONFINITE, "tg_sync_status: non-finite value in the state");
+    }
+    return TG_OK;
+  });
+}
+
 int tg_step_diag(tg_plan p, void* state, double* diag, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && state && diag, TG_EINVAL, "tg_step_diag: null pointer");

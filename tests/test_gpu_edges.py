@@ -50,6 +50,13 @@ def test_non_finite_state_is_reported_then_cleared(precision):
     z = case.device_state()
     case.plan.run(z, 3)
     assert torch.isfinite(z).all()
+    # single steps report through tg_sync_status
+    y = case.device_state()
+    y.view(-1)[7] = float("inf")
+    case.plan.step(y)
+    with pytest.raises(tg.TGError):
+        case.plan.sync_status()
+    case.plan.sync_status()  # cleared
 
 
 def test_misaligned_and_mismatched_buffers_are_refused():
