@@ -339,7 +339,7 @@ def main():
         dom = int(np.argmax(op_times))
         # the other routes for comparison
         other = {}
-        for rname in ("fused", "generic", "fused_stencil_apart"):
+        for rname in ("fused", "generic", "fused_stencil_apart", "per_slice"):
             if rname == route:
                 continue
             plan.set_route(rname)

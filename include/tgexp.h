@@ -236,8 +236,13 @@ int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream);
  * sandwich, the rho product and the update in one launch per (rho, theta)
  * plane when it fits in LDS.  2: the same fused products after a separate
  * stencil + reaction launch.  1: one launch per mu-mode product plus the
- * stencil launch.  Routes 0 and 2 fall back to 1 where a shape does not
- * fit in LDS.  All routes compute the same step. */
+ * stencil launch.  3 (ball and cylinder, FP64 / FP32): as 1, but the mode
+ * whose term is scaled by rho^-2 alone (the ball's phi, the cylinder's
+ * theta) is applied by per-slice dense factors phi_1(tau d rho_i^-2 A), one
+ * per radial index i (Section 4: phi_1 of the block-diagonal term, blockwise),
+ * built on first selection; TG_ENOTSUP elsewhere.  Routes 0 and 2 fall
+ * back to 1 where a shape does not fit in LDS.  All routes compute the same
+ * step.  tg_plan_autotune also tries route 3 where it exists. */
 int tg_plan_set_route(tg_plan p, int32_t route);
 /* The route actually used by tg_step / tg_run (after fall-back). */
 int tg_plan_route(tg_plan p, int32_t* route);

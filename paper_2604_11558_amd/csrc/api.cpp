@@ -767,6 +767,23 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
   g.rd = P->d_rd;
   const int64_t slab = P->npts;
   const int big = std::numeric_limits<int>::max();
+  if (c.slice) {
+    // per slice i (grid y) and slab: C_i (nm x ncol) = P_i (nm x nm) X_i, where
+    // X_i[k][n] = X[k sk + n sn + i]
+    g.A = c.L; g.B = X; g.C = Y;
+    g.M = nm; g.N = c.ncol; g.K = nm; g.nbatch = nn[0];
+    g.lda = nm; g.ldb = c.sk; g.ldc = c.sk;
+    g.b_ncol = c.sn; g.c_ncol = c.sn;
+    g.a_bstride = static_cast<int64_t>(nm) * nm; g.b_bstride = 1; g.c_bstride = 1;
+    g.a_sstride = static_cast<int64_t>(nn[0]) * nm * nm; g.a_smod = c.fmod;
+    g.b_sstride = slab; g.b_smod = big;
+    g.c_sstride = slab;
+    g.b_kcontig = 0;
+    TG_REQUIRE(!dg, TG_ENOTSUP, "indicators need a first-mode update");
+    mark_launch(st);
+    hip_check(tg::launch_mode_gemm<T>(g, st), "per-slice product launch");
+    return;
+  }
   if (c.mode == 1) {
     // C (nb x nm) = X (nb x nm, K-contiguous) * L^T
     g.A = X; g.B = c.L; g.C = Y;
@@ -931,14 +948,86 @@ void run_fused(const tg_plan_s* P, const void* src, void* dst, bool update, bool
 
 // Apply the split chain to `in`.  final_update: last op does state += tau*acc
 // on `out`; otherwise the last op stores into `out`.
+// The per-mode chain of the active route: route 3 replaces the scaled
+// mode's eigen-basis sandwich by per-slice dense factors.
+const std::vector<tg::ChainOp>& chain_of(const tg_plan_s* P) {
+  return P->route == 3 && !P->slice_chain.empty() ? P->slice_chain : P->chain;
+}
+
+bool slice_capable(const tg_plan_s* P) {
+  return (P->grid.geometry == TG_BALL || P->grid.geometry == TG_CYLINDER) && !bf16_terms(P->precision);
+}
+
+// Per-slice factors of the scaled mode, phi_1(tau d_s rho_i^-2 A) for each
+// slab s and radial index i (the ball's phi mode, the cylinder's theta mode),
+// from the mode's eigen-decomposition; the chain of route 1 with that mode's
+// sandwich replaced by one per-slice product.
+template <typename T>
+void build_slice_chain(tg_plan_s* P) {
+  const tg_grid_s& G = P->grid;
+  const int n1 = G.n[0], n2 = G.n[1], n3 = G.n[2];
+  const bool ball = G.geometry == TG_BALL;
+  const int mode = ball ? 3 : 2;
+  const size_t first = ball ? 0 : 1;  // the sandwich pair in the route-1 chain
+  TG_REQUIRE(P->chain.size() > first + 1 && P->chain[first].mode == mode && P->chain[first + 1].mode == mode &&
+                 P->chain[first].epi == tg::EPI_PHI,
+             TG_ENOTSUP, "per-slice route: unexpected chain");
+  const int nm = G.n[mode - 1];
+  const tg::Eig e = G.eig(mode - 1);
+  const auto r = G.coords(0);
+  const int fmod = P->nslab;
+  const size_t blk = static_cast<size_t>(nm) * nm;
+  std::vector<T> host(static_cast<size_t>(fmod) * n1 * blk);
+  for (int f = 0; f < fmod; ++f)
+    for (int i = 0; i < n1; ++i) {
+      const auto Pm = tg::phi1_from_eig(e, P->tau * P->diff[f] / (r[i] * r[i]));
+      T* dst = host.data() + (static_cast<size_t>(f) * n1 + i) * blk;
+      for (size_t q = 0; q < blk; ++q) dst[q] = static_cast<T>(Pm[q]);
+    }
+  void* mem = nullptr;
+  hip_check(hipMalloc(&mem, host.size() * sizeof(T)), "hipMalloc(per-slice factors)");
+  hipError_t err = hipMemcpy(mem, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(mem);
+    hip_check(err, "hipMemcpy(per-slice factors)");
+  }
+  tg::ChainOp op = P->chain[first];
+  op.slice = 1;
+  op.L = mem;
+  op.fmod = fmod;
+  op.epi = tg::EPI_STORE;
+  op.pm = op.pn = op.pb = nullptr;
+  op.LT = op.dL = nullptr;
+  op.sk = ball ? static_cast<int64_t>(n1) * n2 : n1;
+  op.sn = ball ? n1 : static_cast<int64_t>(n1) * n2;
+  op.ncol = ball ? n2 : n3;
+  op.tile = pick_tile(nm, op.ncol, static_cast<int64_t>(n1) * P->nslab);
+  op.flops = 2.0 * nm * static_cast<double>(P->state_elems);
+  std::vector<tg::ChainOp> chain(P->chain.begin(), P->chain.begin() + first);
+  chain.push_back(op);
+  chain.insert(chain.end(), P->chain.begin() + first + 2, P->chain.end());
+  P->slice_mem = mem;
+  P->slice_chain = std::move(chain);
+}
+
+void ensure_slice_chain(tg_plan_s* P) {
+  TG_REQUIRE(slice_capable(P), TG_ENOTSUP,
+             "per-slice route: ball and cylinder plans in FP64 or FP32 only");
+  TG_REQUIRE(P->grid.n[0] <= 65535, TG_ENOTSUP, "per-slice route: too many radial slices");
+  if (!P->slice_chain.empty()) return;
+  if (P->precision == TG_FP64) build_slice_chain<double>(P);
+  else build_slice_chain<float>(P);
+}
+
 template <typename T>
 void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update, hipStream_t st,
                const tg::DiagArgs* dg = nullptr) {
-  const size_t nops = P->chain.size();
+  const auto& chain = chain_of(P);
+  const size_t nops = chain.size();
   const void* X = in;
   int buf = (in == P->scratch[0]) ? 1 : 0;
   for (size_t o = 0; o < nops; ++o) {
-    const auto& c = P->chain[o];
+    const auto& c = chain[o];
     const bool last = (o + 1 == nops);
     void* Y = last ? out : P->scratch[buf];
     int epi = c.epi;
@@ -950,12 +1039,17 @@ void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update,
 }
 
 // 0: fused with the stencil in the first tile load; 2: fused products after
-// a separate stencil launch; 1: one launch per mode product.
+// a separate stencil launch; 1: one launch per mode product; 3: as 1 with
+// per-slice dense factors for the scaled mode (ball, cylinder).
 int active_route(const tg_plan_s* P) {
   if (bf16_terms(P->precision)) return P->route == 2 ? 2 : 0;  // split-bf16 runs fused only
+  if (P->route == 3) return P->slice_chain.empty() ? 1 : 3;
   return P->fused_ok && P->route != 1 ? P->route : 1;
 }
-bool use_fused(const tg_plan_s* P) { return active_route(P) != 1; }
+bool use_fused(const tg_plan_s* P) {
+  const int r = active_route(P);
+  return r == 0 || r == 2;
+}
 
 template <typename T>
 void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg = nullptr) {
@@ -1146,8 +1240,8 @@ void coupled_impl(const Coupled& C, void* ub, void* us, hipStream_t st) {
   tg_plan_s* B = C.bulk;
   tg_plan_s* S = C.surf;
   const int rb = active_route(B), rs = active_route(S);
-  void* fb = rb == 1 ? B->scratch[0] : B->scratch[1];
-  void* fs = rs == 1 ? S->scratch[0] : S->scratch[1];
+  void* fb = !use_fused(B) ? B->scratch[0] : B->scratch[1];
+  void* fs = !use_fused(S) ? S->scratch[0] : S->scratch[1];
   const double h = B->grid.extent[0] / B->grid.n[0];
   tg::StencilArgs ab = stencil_args(B, ub, fb, TG_APPLY_F);
   tg::StencilArgs as = stencil_args(S, us, fs, TG_APPLY_F);
@@ -1163,9 +1257,9 @@ void coupled_impl(const Coupled& C, void* ub, void* us, hipStream_t st) {
   hip_check(tg::launch_stencil<T>(ab, st), "bulk stencil launch");
   mark_launch(st);
   hip_check(tg::launch_stencil<T>(as, st), "surface stencil launch");
-  if (rb == 1) run_chain<T>(B, fb, ub, true, st);
+  if (!use_fused(B)) run_chain<T>(B, fb, ub, true, st);
   else run_fused<T>(B, fb, ub, true, false, st);
-  if (rs == 1) run_chain<T>(S, fs, us, true, st);
+  if (!use_fused(S)) run_chain<T>(S, fs, us, true, st);
   else run_fused<T>(S, fs, us, true, false, st);
 }
 
@@ -1212,8 +1306,8 @@ struct tg_group_s {
   int launches_per_step() const {
     if (!grouped) {
       int n = 0;
-      for (auto* P : plans) n += active_route(P) == 1 ? static_cast<int>(P->chain.size()) + 1
-                                                       : static_cast<int>(P->fused.size()) + (active_route(P) == 2);
+      for (auto* P : plans) n += !use_fused(P) ? static_cast<int>(chain_of(P).size()) + 1
+                                               : static_cast<int>(P->fused.size()) + (active_route(P) == 2);
       return n;
     }
     return static_cast<int>(kind.size()) + (route == 2 ? static_cast<int>(plans.size()) : 0);
@@ -1449,6 +1543,7 @@ int tg_plan_destroy(tg_plan p) {
   if (p->dflag) (void)hipFree(p->dflag);
   if (p->adj_ws) (void)hipFree(p->adj_ws);
   if (p->diag_part) (void)hipFree(p->diag_part);
+  if (p->slice_mem) (void)hipFree(p->slice_mem);
   for (auto& kv : p->coupled_graphs) (void)hipGraphExecDestroy(kv.second);
   delete p;
   return TG_OK;
@@ -1658,8 +1753,9 @@ int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* st
       else launch_fused<float>(p, p->fused[op], in, out, false, from_state, st);
       return TG_OK;
     }
-    TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(p->chain.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
-    const auto& c = p->chain[op];
+    const auto& chain = chain_of(p);
+    TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(chain.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
+    const auto& c = chain[op];
     const int epi = c.epi == tg::EPI_UPDATE ? tg::EPI_STORE : c.epi;
     if (p->precision == TG_FP64) launch_op<double>(p, c, in, out, epi, st);
     else launch_op<float>(p, c, in, out, epi, st);
@@ -1669,9 +1765,10 @@ int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* st
 
 int tg_plan_set_route(tg_plan p, int32_t route) {
   return guarded([&] {
-    TG_REQUIRE(p && route >= 0 && route <= 2, TG_EINVAL, "tg_plan_set_route: bad argument");
-    TG_REQUIRE(!(route == 1 && bf16_terms(p->precision)), TG_ENOTSUP,
+    TG_REQUIRE(p && route >= 0 && route <= 3, TG_EINVAL, "tg_plan_set_route: bad argument");
+    TG_REQUIRE(!((route == 1 || route == 3) && bf16_terms(p->precision)), TG_ENOTSUP,
                "tg_plan_set_route: split-bf16 plans have no per-mode route");
+    if (route == 3) ensure_slice_chain(p);
     if (route != p->route) {
       drop_graphs(p);
       p->route = route;
@@ -1698,10 +1795,11 @@ int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops) {
         if (flops) flops[i] = p->fused[i].flops;
       }
     } else {
-      *n_ops = static_cast<int32_t>(p->chain.size());
-      for (size_t i = 0; i < p->chain.size(); ++i) {
-        if (modes) modes[i] = p->chain[i].mode;
-        if (flops) flops[i] = p->chain[i].flops;
+      const auto& chain = chain_of(p);
+      *n_ops = static_cast<int32_t>(chain.size());
+      for (size_t i = 0; i < chain.size(); ++i) {
+        if (modes) modes[i] = chain[i].mode;
+        if (flops) flops[i] = chain[i].flops;
       }
     }
     return TG_OK;
@@ -1949,6 +2047,10 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
     std::vector<int> routes;
     if (p->fused_ok) routes = {0, 2};
     if (!nt) routes.push_back(1);
+    if (slice_capable(p)) {
+      ensure_slice_chain(p);
+      routes.push_back(3);
+    }
     const int saved_route = p->route;
     double best = std::numeric_limits<double>::infinity();
     int best_route = saved_route;
@@ -1969,7 +2071,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
       p->route = r;
       set_tiles(start_tiles);
       double cur = measure();
-      if (r != 1) {
+      if (r == 0 || r == 2) {
         // coordinate descent over the fused ops' tile sizes
         for (size_t k = 0; k < p->fused.size(); ++k) {
           tg::FusedOp& op = p->fused[k];
@@ -2025,8 +2127,8 @@ int tg_run_timed(tg_plan p, void* state, int64_t n_steps, void* stream, int32_t 
                TG_EINVAL, "tg_run_timed: bad argument");
     TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_timed: state must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int L = active_route(p) == 1 ? static_cast<int>(p->chain.size()) + 1
-                                       : static_cast<int>(p->fused.size()) + (active_route(p) == 2 ? 1 : 0);
+    const int L = !use_fused(p) ? static_cast<int>(chain_of(p).size()) + 1
+                                : static_cast<int>(p->fused.size()) + (active_route(p) == 2 ? 1 : 0);
     TG_REQUIRE(L <= max_launches, TG_EINVAL, "tg_run_timed: more launches per step than max_launches");
     le.ev.resize(static_cast<size_t>(n_steps) * (L + 1), nullptr);
     for (auto& e : le.ev) hip_check(hipEventCreate(&e), "event create");

@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
   const T* B = static_cast<const T*>(g.B) + b * g.b_bstride +
                static_cast<int64_t>(s % g.b_smod) * g.b_sstride;
   T* C = static_cast<T*>(g.C) + b * g.c_bstride + static_cast<int64_t>(s) * g.c_sstride;
+  const int64_t bcol = g.b_ncol ? g.b_ncol : 1, ccol = g.c_ncol ? g.c_ncol : 1;
 
   acc_t acc[FM][FN];
 #pragma unroll
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
       } else {
         const int kk = idx / TN, nn = idx % TN;
         const int gn = n0 + nn, gk = k0 + kk;
-        rb[e] = (gn < g.N && gk < g.K) ? B[gk * g.ldb + gn] : T(0);
+        rb[e] = (gn < g.N && gk < g.K) ? B[gk * g.ldb + gn * bcol] : T(0);
       }
     }
     __syncthreads();
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
         const int col = n0 + wn * WN + j * 16 + li;
         if (row < g.M && col < g.N) {
           T v = acc[i][j][r];
-          T* dst = C + static_cast<int64_t>(row) * g.ldc + col;
+          T* dst = C + static_cast<int64_t>(row) * g.ldc + col * ccol;
           if (g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC) {
             double x = cs * pbv;
             if (g.pm) x *= g.pm[row];

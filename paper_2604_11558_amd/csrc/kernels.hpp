@@ -53,6 +53,7 @@ struct GemmArgs {
   int64_t a_sstride, b_sstride, c_sstride;  // per slab (times slab % *_smod)
   int a_smod, b_smod;                       // modulus of slab index for factors
   int b_kcontig;                            // B stored N x K (first-mode form)
+  int64_t b_ncol, c_ncol;                   // column strides of B (not k-contiguous) and C; 0 means 1
   int epi;
   double alpha;
   const double* cs;                // per slab phi_1 argument multiplier (tau d_s)

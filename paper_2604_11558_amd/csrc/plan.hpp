@@ -40,6 +40,12 @@ struct ChainOp {
   double flops = 0.0;
   const void* LT = nullptr;  // transposed factor blocks (adjoint)
   const void* dL = nullptr;  // d/dd of the factor blocks, or null if L does not depend on d
+  // per-slice product (slice != 0): one dense factor per (factor block, slice
+  // i = mode-1 index), [fmod][n1][n_mu][n_mu]; the product runs over the
+  // other columns (ncol of them, stride sn) with rows of stride sk
+  int slice = 0;
+  int64_t sk = 0, sn = 0;
+  int ncol = 0;
 };
 
 // One fused launch of the step (see fused.hpp).  in / out name the
@@ -95,6 +101,8 @@ struct tg_plan_s {
   int periodic_mask = 0;
   int scale_mask = 0;
   std::vector<tg::ChainOp> chain;   // generic route: one launch per mode product
+  std::vector<tg::ChainOp> slice_chain;  // per-slice route (ball, cylinder), built on first use
+  void* slice_mem = nullptr;             // its per-slice factors
   std::vector<tg::FusedOp> fused;   // fused route
   bool fused_ok = false;
   int route = 0;                     // 0 fused (when available), 1 generic

@@ -174,3 +174,61 @@ def test_bf16_rejects_generic_route():
     case = Case("disk", (12, 16), "bf16x3")
     with pytest.raises(tg.TGError):
         case.plan.set_route("generic")
+
+
+# per-slice route (ball phi mode, cylinder theta mode by per-radius dense factors)
+PER_SLICE_GRIDS = [("ball", (20, 24, 37)), ("ball", (3, 3, 3)), ("cylinder", (27, 30, 19)), ("cylinder", (3, 4, 3))]
+
+
+@pytest.mark.parametrize("geometry,n", PER_SLICE_GRIDS)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_per_slice_route_steps(geometry, n, precision):
+    ns = 3 if geometry == "cylinder" else 2
+    case = Case(geometry, n, precision, tau=5e-3, seed=4, n_species=ns)
+    case.plan.set_route("per_slice")
+    assert case.plan.route == "per_slice"
+    x = case.device_state()
+    case.plan.run(x, 10)
+    err = rel_err(case.full_from_device(x), case.oracle_run(10))
+    print(geometry, n, precision, "per-slice 10-step error", err)
+    assert err < (1e-12 if precision == "fp64" else 2e-7), err
+
+
+@pytest.mark.parametrize("geometry,n", PER_SLICE_GRIDS[::2])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_per_slice_split_hook(geometry, n, precision, tol):
+    ns = 3 if geometry == "cylinder" else 2
+    case = Case(geometry, n, precision, tau=0.3, seed=5, n_species=ns, amplitude=1.0)
+    case.plan.set_route("per_slice")
+    plan, x, out = _hooks(case, precision)
+    plan.split_phi1(x, out)
+    got = out.double().cpu().numpy()[0]
+    for s in range(ns):
+        F = case.to_species(case.pert[0])[s]
+        ref = assemble.to_layout(case.oracles[0].split_phi1(F, s))
+        assert rel_err(got[s], ref) < tol
+
+
+def test_per_slice_batch_with_per_instance_diffusion():
+    diff = [(1.0, 20.0), (1.0, 7.0)]
+    case = Case("ball", (12, 10, 14), "fp64", tau=1e-2, seed=6, batch=2, diff=diff)
+    case.plan.set_route("per_slice")
+    x = case.device_state()
+    case.plan.run(x, 5)
+    assert rel_err(case.full_from_device(x), case.oracle_run(5)) < 1e-12
+
+
+def test_per_slice_full_size_ball_fp32():
+    case = Case("ball", (64, 64, 128), "fp32", tau=5e-3, seed=3)
+    case.plan.set_route("per_slice")
+    x = case.device_state()
+    case.plan.run(x, 3)
+    assert rel_err(case.full_from_device(x), case.oracle_run(3)) < 2e-7
+
+
+def test_per_slice_route_is_refused_elsewhere():
+    import paper_2604_11558_amd as tg
+    for geometry, n, prec in (("disk", (8, 12), "fp64"), ("sphere", (12, 9), "fp32"), ("ball", (6, 8, 7), "bf16x3")):
+        case = Case(geometry, n, prec)
+        with pytest.raises(tg.TGError):
+            case.plan.set_route("per_slice")
