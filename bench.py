@@ -36,9 +36,9 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 10997411, "fused:1:16,64": 13327521,
-           "fused_stencil_apart:0:32,64": 9828970, "fused_stencil_apart:1:32,64": 13327519}
-TRAFFIC_DIGEST = "9f55c083ef8628e888476aa7473df5dd5b7227a9b7d7ca9d198ea3e3110c5f13"
+TRAFFIC = {"fused:0:16,64": 10997361, "fused:1:16,64": 13327453,
+           "fused_stencil_apart:0:32,64": 9828973, "fused_stencil_apart:1:32,64": 13327523}
+TRAFFIC_DIGEST = "d9dabb118e677d8a93df42ac3483c339e825a8d593b58a778eec2feb5078795a"
 
 
 def cpu_model() -> str:
@@ -377,6 +377,18 @@ def main():
     dev64 = states["fp64"]
     err_32_64_dev = float(np.abs(full32 - ref64).max() / max(np.abs(dev64).max(), 1e-300))
 
+    # time-discretisation error at tau by step doubling (first order: the
+    # difference of the tau and tau/2 runs is about half the error of the tau
+    # run), with the FP64 plan (held to the oracle at 1e-12) for speed; a
+    # reduced precision counts as equally accurate below it
+    nsteps = args.warmup + args.steps
+    plan_h = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau / 2, "fp64")
+    xh = plan_h.state_from_deviation(pert)
+    plan_h.run(xh, 2 * nsteps)
+    half = xh.double().cpu().numpy() + plan_h.reference[:, :, None, None, None]
+    del plan_h, xh
+    t_err = 2.0 * float(np.abs(ref64 - half).max() / np.abs(ref64).max())
+
     r = res["fp32"]
     dom = r["dom"]
     if r["flops"][dom] > 0:  # a product launch: MFMA-bound
@@ -419,6 +431,11 @@ def main():
                        for p in bf},
         "rel_err_fp32_vs_fp64": {"after_steps": args.warmup + args.steps, "vs_max_state": err_32_64,
                                  "vs_max_deviation": err_32_64_dev},
+        "time_discretisation_error": {"after_steps": nsteps, "vs_max_state": t_err,
+                                      "method": "2 |W_tau - W_tau/2| / |W| (step doubling, FP64)"},
+        "equal_accuracy": {"fp32": err_32_64 < t_err,
+                           **{p: float(np.abs(bf[p]["full"] - ref64).max() / np.abs(ref64).max()) < t_err
+                              for p in bf}},
         "route": res["fp32"]["route"],
         "autotuned": {p: {"route": res[p]["route"], "tiles": res[p]["tiles"]} for p in res},
         "ms_per_step_direct_launches_with_events": {p: res[p]["sec_direct"] * 1e3 for p in res},
