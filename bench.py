@@ -457,9 +457,18 @@ def main():
     if not args.no_cpu:
         v_cpu, per_step, n_cpu, ws = cpu_baseline(w, pert, args.cpu_seconds)
         out["cpu_baseline"] = {"value": v_cpu, "unit": "dof-steps/s", "cores": blas_threads(),
-                               "kind": "oracle", "host_cpu": cpu_model(),
+                               "kind": "oracle", "host_cpu": cpu_model(), "host_cpu_count": os.cpu_count(),
                                "sample": f"{n_cpu} steps of {w.name} after one warm-up step (FP64 "
                                          f"NumPy/SciPy oracle), s/step = {per_step:.3f}"}
+        # the same oracle on one BLAS thread, a short sample
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                v1, per1, n1_, _ = cpu_baseline(w, pert, min(args.cpu_seconds, 4.0))
+            out["cpu_baseline"]["one_thread"] = {"value": v1, "unit": "dof-steps/s",
+                                                 "sample": f"{n1_} steps, s/step = {per1:.3f}"}
+        except ImportError:
+            pass
         # FP32 GPU path against the oracle on the same sample
         g32 = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, "fp32")
         x = g32.state_from_deviation(pert)
