@@ -196,6 +196,20 @@ def other_workloads(tg, torch, steps):
             "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
             "paper_run_seconds_at_this_rate": bs["steps"] * sec}
         del bulk, surf, xb, xs
+    # 32 x 64 disk, 100 steps of 1e-2 (a latency-bound 4096-dof problem: one
+    # fused launch per step, graph-replayed)
+    wl = workloads.WORKLOADS["disk_32x64"]
+    grid = tg.Grid(wl.geometry, wl.n, wl.extent)
+    for prec in ("fp64", "fp32"):
+        plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, prec)
+        x = plan.state_from_deviation(workloads.perturbation(wl)[None])
+        plan.autotune(x, iters=10)
+        plan.run(x, 16)
+        sec = time_gpu_run(plan, x, max(steps, wl.steps), 0, torch)
+        out[f"disk_32x64_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3,
+                                     "steps_per_s": 1.0 / sec, "dof": wl.dof, "route": plan.route,
+                                     "launches_per_step": len(plan.chain()) + (plan.route != "fused")}
+        del plan, x
     # 160 x 160 anomalous-diffusion disk (lambda = -1.95), FP64 and FP32
     wl = workloads.WORKLOADS["disk_lambda_160x160"]
     grid = tg.Grid(wl.geometry, wl.n, wl.extent)
