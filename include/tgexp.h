@@ -234,9 +234,13 @@ int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream);
  * reaction inside the first product's tile load, each eigen-basis
  * sandwich (x V^-1, Hadamard phi_1, x V) in one launch, and the theta
  * sandwich, the rho product and the update in one launch per (rho, theta)
- * plane when it fits in LDS.  2: the same fused products after a separate
- * stencil + reaction launch.  1: one launch per mu-mode product plus the
- * stencil launch.  3 (ball and cylinder, FP64 / FP32): as 1, but the mode
+ * plane when it fits in LDS (where that single launch would both read the
+ * state for F and update it in place, as the disk's plane launch does,
+ * plans with two or more species compute F in a launch of its own first:
+ * one species' workgroup must not overwrite values another species'
+ * workgroup still reads for the reaction).  2: the same fused products
+ * after a separate stencil + reaction launch.  1: one launch per mu-mode
+ * product plus the stencil launch.  3 (ball and cylinder, FP64 / FP32): as 1, but the mode
  * whose term is scaled by rho^-2 alone (the ball's phi, the cylinder's
  * theta) is applied by per-slice dense factors phi_1(tau d rho_i^-2 A), one
  * per radial index i (Section 4: phi_1 of the block-diagonal term, blockwise),

@@ -924,11 +924,11 @@ struct FusedIO {
   bool update;
   bool from_state;
 };
-FusedIO fused_io(const tg_plan_s* P, size_t i, void* state, int route) {
+FusedIO fused_io(const tg_plan_s* P, size_t i, void* state, bool apart) {
   const auto& op = P->fused[i];
-  const void* src = route == 0 ? state : P->scratch[1];
+  const void* src = apart ? P->scratch[1] : state;
   const bool last = i + 1 == P->fused.size();
-  return FusedIO{op.in < 0 ? src : P->scratch[op.in], last ? state : P->scratch[op.out], last, route == 0};
+  return FusedIO{op.in < 0 ? src : P->scratch[op.in], last ? state : P->scratch[op.out], last, !apart};
 }
 
 // Run the fused chain: the first op reads `src` (the state when it carries
@@ -1051,15 +1051,29 @@ bool use_fused(const tg_plan_s* P) {
   return r == 0 || r == 2;
 }
 
+// Whether a fused plan computes F in a stencil launch of its own before the
+// products (route 2) instead of inside the first product's tile load
+// (route 0).  Route 0 keeps it in the tile load except where that launch
+// also updates the state in place (the disk's single plane launch) and the
+// plan has several species: there the workgroup of one species could
+// overwrite values that the workgroup of another, started later, has still
+// to read for the reaction.
+bool stencil_apart(const tg_plan_s* P) {
+  const int r = active_route(P);
+  if (r != 0) return r == 2;
+  const auto& op = P->fused.front();
+  return P->ns > 1 && op.kind == 0 && op.sa.stencil && op.sa.plane;
+}
+
 template <typename T>
 void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg = nullptr) {
   const int r = active_route(P);
-  if (r == 0) {
+  if (r == 0 && !stencil_apart(P)) {
     // the first fused op computes F from the state inside its tile load
     run_fused<T>(P, state, state, true, true, st, dg);
     return;
   }
-  if (r == 2) {
+  if (r == 0 || r == 2) {
     launch_stencil_stage<T>(P, state, P->scratch[1], TG_APPLY_F, st);
     run_fused<T>(P, P->scratch[1], state, true, false, st, dg);
     return;
@@ -1292,6 +1306,7 @@ struct tg_group_s {
   std::vector<void*> states;
   bool grouped = false;
   int route = 0;
+  bool apart = false;                     // a stencil launch per member first
   std::vector<int> kind;                  // per fused op
   std::vector<tg::GroupLaunch> launch;    // per fused op
   std::vector<size_t> offset;             // byte offset of op k's group in dev
@@ -1307,10 +1322,10 @@ struct tg_group_s {
     if (!grouped) {
       int n = 0;
       for (auto* P : plans) n += !use_fused(P) ? static_cast<int>(chain_of(P).size()) + 1
-                                               : static_cast<int>(P->fused.size()) + (active_route(P) == 2);
+                                               : static_cast<int>(P->fused.size()) + stencil_apart(P);
       return n;
     }
-    return static_cast<int>(kind.size()) + (route == 2 ? static_cast<int>(plans.size()) : 0);
+    return static_cast<int>(kind.size()) + (apart ? static_cast<int>(plans.size()) : 0);
   }
 };
 
@@ -1332,7 +1347,7 @@ bool build_group_launches(tg_group_s* G) {
       g.map.n = n;
       bool wide = false;
       for (int q = 0; q < n; ++q) {
-        const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->route);
+        const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->apart);
         g.a[q] = strided_args_for(G->plans[q], G->plans[q]->fused[k], io.in, io.out, io.update, io.from_state);
         wide |= g.a[q].tn % 32 == 0;
       }
@@ -1354,7 +1369,7 @@ bool build_group_launches(tg_group_s* G) {
       g.map.n = n;
       int tm = 16;
       for (int q = 0; q < n; ++q) {
-        const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->route);
+        const FusedIO io = fused_io(G->plans[q], k, G->states[q], G->apart);
         g.a[q] = first_args_for(G->plans[q], G->plans[q]->fused[k], io.in, io.out, io.update);
         tm = std::max(tm, g.a[q].tm);
       }
@@ -1384,6 +1399,7 @@ bool groupable(const std::vector<tg_plan_s*>& plans) {
   if (bf16_terms(P0->precision) || !use_fused(P0)) return false;
   for (const auto* P : plans) {
     if (P->precision != P0->precision || active_route(P) != active_route(P0)) return false;
+    if (stencil_apart(P) != stencil_apart(P0)) return false;
     if (P->fused.size() != P0->fused.size()) return false;
     for (size_t k = 0; k < P->fused.size(); ++k)
       if (P->fused[k].kind != P0->fused[k].kind) return false;
@@ -1397,7 +1413,7 @@ void group_step(tg_group_s* G, hipStream_t st) {
     for (size_t q = 0; q < G->plans.size(); ++q) step_any(G->plans[q], G->states[q], st);
     return;
   }
-  if (G->route == 2)
+  if (G->apart)
     for (size_t q = 0; q < G->plans.size(); ++q)
       launch_stencil_stage<T>(G->plans[q], G->states[q], G->plans[q]->scratch[1], TG_APPLY_F, st);
   for (size_t k = 0; k < G->kind.size(); ++k) {
@@ -1438,6 +1454,7 @@ tg_group_s* find_group(const tg_plan* plans, int32_t n_plans, void* const* state
     G->plans = ps;
     G->states = ss;
     G->route = active_route(P0);
+    G->apart = use_fused(P0) && stencil_apart(P0);
     if (groupable(ps)) {
       G->grouped = P0->precision == TG_FP64 ? build_group_launches<double>(G) : build_group_launches<float>(G);
       if (!G->grouped && G->dev) {
@@ -2128,7 +2145,7 @@ int tg_run_timed(tg_plan p, void* state, int64_t n_steps, void* stream, int32_t 
     TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_timed: state must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int L = !use_fused(p) ? static_cast<int>(chain_of(p).size()) + 1
-                                : static_cast<int>(p->fused.size()) + (active_route(p) == 2 ? 1 : 0);
+                                : static_cast<int>(p->fused.size()) + (stencil_apart(p) ? 1 : 0);
     TG_REQUIRE(L <= max_launches, TG_EINVAL, "tg_run_timed: more launches per step than max_launches");
     le.ev.resize(static_cast<size_t>(n_steps) * (L + 1), nullptr);
     for (auto& e : le.ev) hip_check(hipEventCreate(&e), "event create");

@@ -41,14 +41,17 @@ def test_group_of_mixed_grids_matches_oracle(precision):
         assert err < TOL[precision], (c.geometry, c.n, err)
 
 
-def test_group_of_disks_one_launch_per_step():
-    """Disks run the whole split step in one launch (theta sandwich plus the
-    rho product in the plane tail); grouped, still one launch per step."""
+def test_group_of_disks_one_product_launch_per_step():
+    """Disks run the split products in one launch (theta sandwich plus the
+    rho product and the update in the plane tail), after a stencil launch
+    per plan (the plane launch updates the states in place, which the
+    two-species reaction must not see); grouped, one product launch covers
+    both plans."""
     cases = [Case("disk", (37, 70), "fp64", tau=1e-2, seed=19, batch=2),
              Case("disk", (32, 64), "fp64", tau=1e-2, seed=20)]
     plans = [c.plan for c in cases]
     states = [c.device_state() for c in cases]
-    assert tg.group_info(plans, states) == {"grouped": True, "launches_per_step": 1}
+    assert tg.group_info(plans, states) == {"grouped": True, "launches_per_step": 1 + len(plans)}
     tg.group_run(plans, states, 8)
     for c, x in zip(cases, states):
         assert rel_err(c.full_from_device(x), c.oracle_run(8)) < 1e-12
@@ -185,3 +188,26 @@ def test_group_autotune_keeps_plans_groupable():
     tg.group_run(plans, states, 5)
     for c, x in zip(cases, states):
         assert rel_err(c.full_from_device(x), c.oracle_run(5)) < TOL["fp32"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_disk_plane_launch_with_more_workgroups_than_fit(precision):
+    """The disk's fused step runs one plane launch per (instance, species)
+    that updates the state in place, and the reaction of each species reads
+    the other species' state.  With 2048 identical instances there are more
+    workgroups than the GPU holds at once, so the two species' workgroups of
+    an instance can start far apart: F is computed by a launch of its own
+    first, every instance matches the oracle, and all are bit-identical."""
+    B = 2048
+    one = Case("disk", (32, 64), precision, tau=1e-2, seed=31, amplitude=1e-3)
+    plan = tg.Plan(one.grid, np.repeat(one.diff, B, axis=0), one.kind, np.repeat(one.params, B, axis=0),
+                   one.tau, precision, B)
+    assert plan.route == "fused"
+    x = plan.state_from_deviation(np.repeat(one.pert, B, axis=0))
+    assert len(plan.run_timed(x.clone(), 1)) == len(plan.chain()) + 1  # the stencil launch first
+    plan.run(x, 4)
+    dev = x.detach().double().cpu().numpy().reshape((B, 2, 64, 32))
+    assert np.array_equal(dev, np.repeat(dev[:1], B, axis=0))
+    ref = one.oracle_run(4)[0]
+    got = dev[0] + plan.reference[0][:, None, None]
+    assert rel_err(got, ref) < TOL[precision]
