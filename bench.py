@@ -196,20 +196,40 @@ def other_workloads(tg, torch, steps):
             "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
             "paper_run_seconds_at_this_rate": bs["steps"] * sec}
         del bulk, surf, xb, xs
-    # 32 x 64 disk, 100 steps of 1e-2 (a latency-bound 4096-dof problem: the
-    # stencil launch, then one fused launch for the products and the update,
-    # graph-replayed)
+    # 32 x 64 disk, 100 steps of 1e-2 (a latency-bound 4096-dof problem):
+    # autotuned, which picks the resident route (every step of a run in one
+    # launch, one workgroup holding the states in LDS) over the fused one
+    # (a stencil launch and a fused launch per step, graph-replayed); then
+    # the fused route for comparison, and a batch of 256 instances with
+    # their own parameters on the resident route (one workgroup each)
     wl = workloads.WORKLOADS["disk_32x64"]
     grid = tg.Grid(wl.geometry, wl.n, wl.extent)
+    nrun = max(steps, wl.steps)
     for prec in ("fp64", "fp32"):
         plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, prec)
         x = plan.state_from_deviation(workloads.perturbation(wl)[None])
-        plan.autotune(x, iters=10)
+        plan.autotune(x, iters=100)
         plan.run(x, 16)
-        sec = time_gpu_run(plan, x, max(steps, wl.steps), 0, torch)
+        sec = time_gpu_run(plan, x, nrun, 0, torch)
+        route = plan.route
+        plan.set_route("fused")
+        plan.run(x, 16)
+        sec_fused = time_gpu_run(plan, x, nrun, 0, torch)
         out[f"disk_32x64_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3,
-                                     "steps_per_s": 1.0 / sec, "dof": wl.dof, "route": plan.route,
-                                     "launches_per_step": len(plan.run_timed(x.clone(), 1))}
+                                     "steps_per_s": 1.0 / sec, "dof": wl.dof, "route": route,
+                                     "steps_timed": nrun,
+                                     "fused_route": {"ms_per_step": sec_fused * 1e3,
+                                                     "launches_per_step": len(plan.run_timed(x.clone(), 1))}}
+        del plan, x
+        B = 256
+        prm = workloads.sphere_batch_params(B)  # (a, b, d2) uniform in the sphere batch's ranges
+        plan = tg.Plan(grid, np.stack([np.ones(B), prm[:, 2]], axis=1), wl.reaction, prm[:, :2], wl.tau, prec, B)
+        x = plan.state_from_deviation(np.repeat(workloads.perturbation(wl)[None], B, axis=0))
+        plan.set_route("resident")
+        plan.run(x, 16)
+        sec = time_gpu_run(plan, x, nrun, 0, torch)
+        out[f"disk_32x64_batch256_resident_{prec}"] = {"value": B * wl.dof / sec, "unit": "dof-steps/s",
+                                                       "ms_per_step": sec * 1e3, "instances": B}
         del plan, x
     # 160 x 160 anomalous-diffusion disk (lambda = -1.95), FP64 and FP32
     wl = workloads.WORKLOADS["disk_lambda_160x160"]

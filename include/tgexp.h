@@ -244,9 +244,17 @@ int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream);
  * whose term is scaled by rho^-2 alone (the ball's phi, the cylinder's
  * theta) is applied by per-slice dense factors phi_1(tau d rho_i^-2 A), one
  * per radial index i (Section 4: phi_1 of the block-diagonal term, blockwise),
- * built on first selection; TG_ENOTSUP elsewhere.  Routes 0 and 2 fall
- * back to 1 where a shape does not fit in LDS.  All routes compute the same
- * step.  tg_plan_autotune also tries route 3 where it exists. */
+ * built on first selection; TG_ENOTSUP elsewhere.  4 (disk plans in FP64
+ * or FP32 whose step is route 0's single plane launch): resident steps --
+ * one workgroup per instance keeps the state, F and the sandwich
+ * intermediate of every species in LDS and runs many steps per launch
+ * (tg_run: up to 1024; tg_step: one), the reaction reading the other
+ * species from the same LDS; TG_ENOTSUP where the species' tiles of an
+ * instance do not fit in LDS together (160 KB) or the step has another
+ * shape.  Steps with indicators (tg_step_diag) run route 0's launches.
+ * Routes 0 and 2 fall back to 1 where a shape does not fit in LDS.  All
+ * routes compute the same step.  tg_plan_autotune also tries routes 3 and
+ * 4 where they exist. */
 int tg_plan_set_route(tg_plan p, int32_t route);
 /* The route actually used by tg_step / tg_run (after fall-back). */
 int tg_plan_route(tg_plan p, int32_t* route);
@@ -259,8 +267,8 @@ int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops);
  * split chain alone.  Route 1: out = in x_mu L (with its Hadamard phi_1
  * factor where the chain has one).  Routes 0 and 2: as in a step, `in`
  * being the previous launch's output, except for the first launch of route
- * 0, which reads the state and evaluates F = d M W + g(W) itself.  A final
- * update is replaced by a store. */
+ * 0, which reads the state and evaluates F = d M W + g(W) itself.  Route 4:
+ * route 0's single fused launch.  A final update is replaced by a store. */
 int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* stream);
 
 /* Benchmark hook: n_steps steps of tg_step (direct launches, no graph) with
@@ -306,11 +314,15 @@ int tg_group_autotune(const tg_plan* plans, int32_t n_plans, void* const* states
  * Times `iters` steps (after 2 warm-up steps) of each candidate launch
  * configuration on a private copy of `state` (device, plan layout; not
  * modified) and keeps the fastest: the route (0, 2, and 1 except for
- * split-bf16 plans) and, per fused launch, the tile width (16 / 32 / 64
- * columns for strided launches that do not cover whole planes, 16 / 32
- * rows for first-mode launches), by coordinate descent; a candidate must
- * be at least 2% faster to replace the current choice (routes are tried
- * in the order 0, 2, 1).  Every candidate computes the same step.
+ * split-bf16 plans; 3 and 4 where they exist) and, per fused launch, the
+ * tile width (16 / 32 / 64 columns for strided launches that do not cover
+ * whole planes, 16 / 32 rows for first-mode launches), by coordinate
+ * descent; a candidate must be at least 2% faster to replace the current
+ * choice (routes are tried in the order 0, 2, 1, 3, 4).  Routes 0 to 3 are
+ * timed by direct launches of single steps, route 4 by one resident launch
+ * of `iters` steps, as tg_run runs them (its single steps, tg_step, cost a
+ * launch each and more than route 0's).  Every candidate computes the same
+ * step.
  * *best_us: time per step of the choice.
  * Allocates one state-sized buffer for the duration of the call;
  * synchronous.  Captured graphs of the plan are dropped. */

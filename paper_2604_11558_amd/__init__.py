@@ -21,7 +21,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
 REACTION = {"none": 0, "schnakenberg": 1, "ais3": 2, "schnakenberg_scaled": 3}
 APPLY = {"F": 0, "diffusion": 1, "reaction": 2}
 NDIM = {"disk": 2, "sphere": 2, "ball": 3, "cylinder": 3, "disk_lambda": 2}
-ROUTES = {"fused": 0, "generic": 1, "fused_stencil_apart": 2, "per_slice": 3}
+ROUTES = {"fused": 0, "generic": 1, "fused_stencil_apart": 2, "per_slice": 3, "resident": 4}
 
 _c_int = ctypes.c_int32
 _c_i64 = ctypes.c_int64
@@ -274,8 +274,10 @@ class Plan:
                                        _stream_ptr(stream)))
 
     def set_route(self, route: str):
-        """'fused' (default), 'fused_stencil_apart', 'generic' or 'per_slice'
-        (ball and cylinder: the scaled mode by per-slice dense factors)."""
+        """'fused' (default), 'fused_stencil_apart', 'generic', 'per_slice'
+        (ball and cylinder: the scaled mode by per-slice dense factors) or
+        'resident' (disk: one workgroup per instance runs many steps with the
+        states in LDS)."""
         _check(lib().tg_plan_set_route(self._h, ROUTES[route]))
 
     @property

@@ -1041,7 +1041,22 @@ void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update,
 // 0: fused with the stencil in the first tile load; 2: fused products after
 // a separate stencil launch; 1: one launch per mode product; 3: as 1 with
 // per-slice dense factors for the scaled mode (ball, cylinder).
+// Route 4 (resident): the step is one fused strided op with the stencil, the
+// sandwich and the plane-tail update on a 2D grid (the disk), and the tiles
+// of every species of an instance fit in LDS together.
+bool resident_ok(const tg_plan_s* P) {
+  if (bf16_terms(P->precision) || !P->fused_ok || P->fused.size() != 1 || P->grid.ndim != 2) return false;
+  const tg::FusedOp& op = P->fused.front();
+  if (op.kind != 0) return false;
+  const tg::StridedArgs& a = op.sa;
+  if (!a.stencil || !a.sandwich || !a.phi || !a.plane || a.nb != 1 || P->batch > 65535) return false;
+  const size_t b = P->precision == TG_FP64 ? tg::resident_lds_bytes<double>(P->ns, a.nm, a.na)
+                                           : tg::resident_lds_bytes<float>(P->ns, a.nm, a.na);
+  return b > 0 && b <= kLdsLimit;
+}
+
 int active_route(const tg_plan_s* P) {
+  if (P->route == 4) return resident_ok(P) ? 4 : 0;
   if (bf16_terms(P->precision)) return P->route == 2 ? 2 : 0;  // split-bf16 runs fused only
   if (P->route == 3) return P->slice_chain.empty() ? 1 : 3;
   return P->fused_ok && P->route != 1 ? P->route : 1;
@@ -1065,15 +1080,48 @@ bool stencil_apart(const tg_plan_s* P) {
   return P->ns > 1 && op.kind == 0 && op.sa.stencil && op.sa.plane;
 }
 
+// Launches of one step of the active route.
+int step_launches(const tg_plan_s* P) {
+  const int r = active_route(P);
+  if (r == 4) return 1;
+  if (r == 0 || r == 2) return static_cast<int>(P->fused.size()) + (stencil_apart(P) ? 1 : 0);
+  return static_cast<int>(chain_of(P).size()) + 1;
+}
+
+// `steps` steps of a route-4 plan: resident launches of at most
+// kResidentChunk steps each.
+constexpr int64_t kResidentChunk = 1024;
+template <typename T>
+void run_resident(tg_plan_s* P, void* state, int64_t steps, hipStream_t st) {
+  tg::ResidentArgs r{};
+  r.a = strided_args_for(P, P->fused.front(), state, state, true, true);
+  r.np = tg::resident_np(r.a.nm, r.a.na);
+  r.tn = tg::resident_tn(r.a.nm, r.a.na);
+  r.ninst = P->batch;
+  for (int64_t done = 0; done < steps; done += kResidentChunk) {
+    r.steps = static_cast<int>(std::min<int64_t>(kResidentChunk, steps - done));
+    mark_launch(st);
+    hip_check(tg::launch_resident<T>(r, st), "resident launch");
+  }
+}
+void run_resident_any(tg_plan_s* P, void* state, int64_t steps, hipStream_t st) {
+  if (P->precision == TG_FP64) run_resident<double>(P, state, steps, st);
+  else run_resident<float>(P, state, steps, st);
+}
+
 template <typename T>
 void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg = nullptr) {
   const int r = active_route(P);
+  if (r == 4 && !dg) {
+    run_resident<T>(P, state, 1, st);
+    return;
+  }
   if (r == 0 && !stencil_apart(P)) {
     // the first fused op computes F from the state inside its tile load
     run_fused<T>(P, state, state, true, true, st, dg);
     return;
   }
-  if (r == 0 || r == 2) {
+  if (r == 0 || r == 2 || r == 4) {  // (route 4 with indicators: the fused launches)
     launch_stencil_stage<T>(P, state, P->scratch[1], TG_APPLY_F, st);
     run_fused<T>(P, P->scratch[1], state, true, false, st, dg);
     return;
@@ -1321,8 +1369,7 @@ struct tg_group_s {
   int launches_per_step() const {
     if (!grouped) {
       int n = 0;
-      for (auto* P : plans) n += !use_fused(P) ? static_cast<int>(chain_of(P).size()) + 1
-                                               : static_cast<int>(P->fused.size()) + stencil_apart(P);
+      for (auto* P : plans) n += step_launches(P);
       return n;
     }
     return static_cast<int>(kind.size()) + (apart ? static_cast<int>(plans.size()) : 0);
@@ -1593,18 +1640,28 @@ int tg_step(tg_plan p, void* state, void* stream) {
   });
 }
 
+// n plain steps: resident launches on route 4, else graph replays of
+// kStepsPerGraph steps and single steps for the rest.
+static void run_plain(tg_plan_s* p, void* state, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  if (active_route(p) == 4) {
+    run_resident_any(p, state, n, st);
+    return;
+  }
+  const int64_t full = n / kStepsPerGraph;
+  if (full > 0) {
+    hipGraphExec_t ex = step_graph(p, state, kStepsPerGraph);
+    for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(ex, st), "graph launch");
+  }
+  for (int64_t it = full * kStepsPerGraph; it < n; ++it) step_any(p, state, st);
+}
+
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && state && n_steps >= 0, TG_EINVAL, "tg_run: bad argument");
     TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run: state must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t chunk = kStepsPerGraph;
-    const int64_t full = n_steps / chunk;
-    if (full > 0) {
-      hipGraphExec_t ex = step_graph(p, state, static_cast<int>(chunk));
-      for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(ex, st), "tg_run: graph launch");
-    }
-    for (int64_t it = full * chunk; it < n_steps; ++it) step_any(p, state, st);
+    run_plain(p, state, n_steps, st);
     int flag = 0;
     hip_check(hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "tg_run: flag copy");
     hip_check(hipStreamSynchronize(st), "tg_run: synchronize");
@@ -1653,18 +1710,12 @@ int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* 
     for (int64_t r = 0; r < records; ++r) {
       // every - 1 plain steps (graph replays of kStepsPerGraph, then single
       // launches), then the recorded step
-      const int64_t plain = every - 1;
-      const int64_t full = plain / kStepsPerGraph;
-      if (full > 0) {
-        hipGraphExec_t ex = step_graph(p, state, kStepsPerGraph);
-        for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(ex, st), "tg_run_diag: graph launch");
-      }
-      for (int64_t it = full * kStepsPerGraph; it < plain; ++it) step_any(p, state, st);
+      run_plain(p, state, every - 1, st);
       d.out = diag + 2 * static_cast<int64_t>(p->nslab) * r;
       step_any(p, state, st, &d);
       done += every;
     }
-    for (; done < n_steps; ++done) step_any(p, state, st);
+    run_plain(p, state, n_steps - done, st);
     int flag = 0;
     hip_check(hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "tg_run_diag: flag copy");
     hip_check(hipStreamSynchronize(st), "tg_run_diag: synchronize");
@@ -1763,9 +1814,9 @@ int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* st
     TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_chain_op: bad pointers");
     TG_REQUIRE(aligned(p, in) && aligned(p, out), TG_EINVAL, "tg_apply_chain_op: buffers must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (use_fused(p)) {
+    if (use_fused(p) || active_route(p) == 4) {
       TG_REQUIRE(op >= 0 && op < static_cast<int32_t>(p->fused.size()), TG_EINVAL, "tg_apply_chain_op: op out of range");
-      const bool from_state = active_route(p) == 0;
+      const bool from_state = active_route(p) != 2;
       if (p->precision == TG_FP64) launch_fused<double>(p, p->fused[op], in, out, false, from_state, st);
       else launch_fused<float>(p, p->fused[op], in, out, false, from_state, st);
       return TG_OK;
@@ -1782,10 +1833,12 @@ int tg_apply_chain_op(tg_plan p, int32_t op, const void* in, void* out, void* st
 
 int tg_plan_set_route(tg_plan p, int32_t route) {
   return guarded([&] {
-    TG_REQUIRE(p && route >= 0 && route <= 3, TG_EINVAL, "tg_plan_set_route: bad argument");
+    TG_REQUIRE(p && route >= 0 && route <= 4, TG_EINVAL, "tg_plan_set_route: bad argument");
     TG_REQUIRE(!((route == 1 || route == 3) && bf16_terms(p->precision)), TG_ENOTSUP,
                "tg_plan_set_route: split-bf16 plans have no per-mode route");
     if (route == 3) ensure_slice_chain(p);
+    TG_REQUIRE(route != 4 || resident_ok(p), TG_ENOTSUP,
+               "tg_plan_set_route: the resident route needs a disk plan in FP64 or FP32 whose species fit in LDS");
     if (route != p->route) {
       drop_graphs(p);
       p->route = route;
@@ -1805,7 +1858,7 @@ int tg_plan_route(tg_plan p, int32_t* route) {
 int tg_plan_chain(tg_plan p, int32_t* n_ops, int32_t* modes, double* flops) {
   return guarded([&] {
     TG_REQUIRE(p && n_ops, TG_EINVAL, "tg_plan_chain: null pointer");
-    if (use_fused(p)) {
+    if (use_fused(p) || active_route(p) == 4) {
       *n_ops = static_cast<int32_t>(p->fused.size());
       for (size_t i = 0; i < p->fused.size(); ++i) {
         if (modes) modes[i] = p->fused[i].mode;
@@ -2045,12 +2098,19 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
       }
       return b > 0 && b <= kLdsLimit;
     };
-    // time `iters` steps of the current configuration (+inf if it cannot run)
+    // time `iters` steps of the current configuration (+inf if it cannot
+    // run): direct launches, or on route 4 one resident launch of `iters`
+    // steps, as tg_run takes them
     auto measure = [&]() {
       try {
-        for (int w = 0; w < 2; ++w) step_any(p, tmp, st);
+        const bool res = active_route(p) == 4;
+        if (res) run_resident_any(p, tmp, 2, st);
+        else
+          for (int w = 0; w < 2; ++w) step_any(p, tmp, st);
         hip_check(hipEventRecord(e0, st), "event record");
-        for (int it = 0; it < iters; ++it) step_any(p, tmp, st);
+        if (res) run_resident_any(p, tmp, iters, st);
+        else
+          for (int it = 0; it < iters; ++it) step_any(p, tmp, st);
         hip_check(hipEventRecord(e1, st), "event record");
         hip_check(hipEventSynchronize(e1), "event sync");
         float ms = 0.0f;
@@ -2068,6 +2128,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
       ensure_slice_chain(p);
       routes.push_back(3);
     }
+    if (resident_ok(p)) routes.push_back(4);
     const int saved_route = p->route;
     double best = std::numeric_limits<double>::infinity();
     int best_route = saved_route;
@@ -2144,8 +2205,7 @@ int tg_run_timed(tg_plan p, void* state, int64_t n_steps, void* stream, int32_t 
                TG_EINVAL, "tg_run_timed: bad argument");
     TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_timed: state must be aligned to 4 elements");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int L = !use_fused(p) ? static_cast<int>(chain_of(p).size()) + 1
-                                : static_cast<int>(p->fused.size()) + (stencil_apart(p) ? 1 : 0);
+    const int L = step_launches(p);
     TG_REQUIRE(L <= max_launches, TG_EINVAL, "tg_run_timed: more launches per step than max_launches");
     le.ev.resize(static_cast<size_t>(n_steps) * (L + 1), nullptr);
     for (auto& e : le.ev) hip_check(hipEventCreate(&e), "event create");

@@ -1438,6 +1438,285 @@ hipError_t launch_first_group(const GroupLaunch& L, const FirstGroup* dev, hipSt
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Several split steps in one launch for a plan whose step is a single fused
+// op (stencil, sandwich with its phi_1 factor, plane tail with the update:
+// the disk, eq. (ee_disk)).  One workgroup per instance keeps the state, F
+// and the sandwich intermediate of every species in LDS, so the steps cost
+// no launches and no HBM round trips, and the reaction reads the other
+// species from the same workgroup's LDS.
+//
+// LDS: sW, sF, sT = [ns][NP][ld] (row k: mode 2, the sandwich's coordinate;
+// column c: mode 1), then the operator tables rc [NP][5] (rs_0, 0, L, D, U
+// of the row mode, as in stencil_tile) and cc [TN][4] (A, B, C of the column
+// mode, cs_r) in FP64.  Padding rows and columns of sF and sT stay zero.
+//
+// KR > 0: NP = 16 KR, TN = 16 KC and NW = KR KC waves, so each wave owns one
+// 16 x 16 output position of every product for all species and keeps, for
+// all the steps, its factor rows (V^-1, V), its factor columns (P of each
+// species) and its phi_1 values in registers: a step then reads nothing
+// but LDS.  KR == 0: any padded shape, factors read from L2 per product
+// and phi_1 evaluated per step.
+template <typename T, int NW, int KR, int KC>
+__global__ __launch_bounds__(64 * NW) void resident_kernel(ResidentArgs r) {
+  // species held in registers by the register-resident form
+  constexpr int NSR = KR > 0 ? 2 : 3;
+  extern __shared__ __align__(256) unsigned char smem[];
+  constexpr int NT = 64 * NW;
+  using acc_t = typename M16<T>::acc;
+  const StridedArgs& a = r.a;
+  const StencilArgs& st = a.st;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int ns = st.nspecies, inst = blockIdx.x;
+  const int nm = a.nm, na = a.na, NP = r.np, TN = r.tn;
+  const int ld = pitch_kmajor<T>(TN), tile = NP * ld;
+  T* sW = reinterpret_cast<T*>(smem);
+  T* sF = sW + ns * tile;
+  T* sT = sF + ns * tile;
+  double* rc = reinterpret_cast<double*>(sT + ns * tile);
+  double* cc = rc + 5 * NP;
+  const int64_t plane = static_cast<int64_t>(nm) * na;
+  T* Wg = static_cast<T*>(a.W) + static_cast<int64_t>(inst) * ns * plane;
+  const Div dld(ld), dna(na);
+
+  // 1. the state of every species; padding and work tiles zeroed
+  for (int s = 0; s < ns; ++s)
+    for (int e = tid; e < tile; e += NT) {
+      int c;
+      const int k = dld.quot(e, c);
+      const bool in = k < nm && c < na;
+      sW[s * tile + e] = in ? Wg[s * plane + static_cast<int64_t>(k) * na + c] : T(0);
+      sF[s * tile + e] = T(0);
+      sT[s * tile + e] = T(0);
+    }
+  // operator tables (2D: the row mode is mode 2, the column mode mode 1)
+  const int nmx = st.nmax;
+  for (int k = tid; k < NP; k += NT) {
+    const int kk = min(k, nm - 1);
+    const double rs0 = ((st.scale_mask >> 1) & 1) ? st.scale[nmx + kk] : 1.0;
+    const double rs1 = ((st.scale_mask >> 4) & 1) ? st.scale[3 * nmx + nmx + kk] : 1.0;
+    const double* rcoef = st.coef + 3 * nmx;
+    rc[k * 5 + 0] = rs0;
+    rc[k * 5 + 1] = 0.0;
+    rc[k * 5 + 2] = rs1 * rcoef[kk];
+    rc[k * 5 + 3] = rs1 * rcoef[nmx + kk];
+    rc[k * 5 + 4] = rs1 * rcoef[2 * nmx + kk];
+  }
+  for (int c = tid; c < TN; c += NT) {
+    const int ci = min(c, na - 1);
+    const double cs0 = (st.scale_mask & 1) ? st.scale[ci] : 1.0;
+    const double cs1 = ((st.scale_mask >> 3) & 1) ? st.scale[3 * nmx + ci] : 1.0;
+    cc[c * 4 + 0] = cs0 * st.coef[ci];
+    cc[c * 4 + 1] = cs0 * st.coef[nmx + ci];
+    cc[c * 4 + 2] = cs0 * st.coef[2 * nmx + ci];
+    cc[c * 4 + 3] = cs1;
+  }
+  double dif[3] = {0.0, 0.0, 0.0}, cphi[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < ns; ++s) {
+    dif[s] = st.diff[inst * ns + s];
+    cphi[s] = a.ph.cs[inst * ns + s];
+  }
+  const ReactConst rcst = react_const(st, inst);
+  const bool react = st.reaction != 0;
+  const bool per_c = st.periodic_mask & 1;         // mode 1 wraps around
+  const bool per_r = (st.periodic_mask >> 1) & 1;  // mode 2 wraps around
+  const int nct = TN / 16, nsub1 = (NP / 16) * nct, nsub = ns * nsub1;
+  const T alpha = static_cast<T>(a.alpha);
+  // register-resident operands of this wave's output position (KR > 0)
+  using v4 = typename M16<T>::v4;
+  constexpr int KRr = KR > 0 ? KR : 1, KCr = KC > 0 ? KC : 1;
+  const int wr0 = KR > 0 ? (wave / KCr) * 16 : 0, wc0 = KR > 0 ? (wave % KCr) * 16 : 0;
+  v4 f1[1][KRr], f2[1][KRr], fp[NSR][1][KCr];
+  T ph[NSR][4];
+  if constexpr (KR > 0) {
+    load_rows_u<T, 1, KR>(f1, factor_of<T>(a.L1, inst * ns), a.L1.ld, wr0, lane);
+    load_rows_u<T, 1, KR>(f2, factor_of<T>(a.L2, inst * ns), a.L2.ld, wr0, lane);
+    const int col = wc0 + li;
+#pragma unroll
+    for (int s = 0; s < NSR; ++s) {
+      if (s < ns) load_cols_u<T, 1, KC>(fp[s], factor_of<T>(a.P, inst * ns + s), a.P.ld, wc0, lane);
+      const double fc = s < ns ? cphi[s] * (a.ph.pn ? a.ph.pn[min(col, na - 1)] : 1.0) : 0.0;
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int row = wr0 + M16<T>::row(g, q4);
+        const double fr = a.ph.pm ? a.ph.pm[min(row, nm - 1)] : 1.0;
+        ph[s][q4] = (s < ns && row < nm && col < na) ? M16<T>::phi1(static_cast<T>(fc * fr)) : T(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int step = 0; step < r.steps; ++step) {
+    // a. F = d M W + g(W), every species
+    for (int e = tid; e < nm * na; e += NT) {
+      int c;
+      const int k = dna.quot(e, c);
+      const int km = k > 0 ? k - 1 : (per_r ? nm - 1 : k);
+      const int kp = k + 1 < nm ? k + 1 : (per_r ? 0 : k);
+      const int cm = c > 0 ? c - 1 : (per_c ? na - 1 : c);
+      const int cp = c + 1 < na ? c + 1 : (per_c ? 0 : c);
+      const double* r5 = rc + k * 5;
+      const double* c4 = cc + c * 4;
+      double wv[3] = {0.0, 0.0, 0.0}, G[3] = {0.0, 0.0, 0.0};
+      for (int s = 0; s < ns; ++s) wv[s] = static_cast<double>(sW[s * tile + k * ld + c]);
+      if (react) reaction3c(rcst, wv[0], wv[1], wv[2], G[0], G[1], G[2]);
+      for (int s = 0; s < ns; ++s) {
+        const T* w = sW + s * tile;
+        const double w0 = wv[s];
+        double f = c4[3] * (r5[2] * static_cast<double>(w[km * ld + c]) + r5[3] * w0 +
+                            r5[4] * static_cast<double>(w[kp * ld + c]));
+        f += r5[0] * (c4[0] * static_cast<double>(w[k * ld + cm]) + c4[1] * w0 +
+                      c4[2] * static_cast<double>(w[k * ld + cp]));
+        sF[s * tile + k * ld + c] = static_cast<T>(dif[s] * f + G[s]);
+      }
+    }
+    __syncthreads();
+    if constexpr (KR > 0) {
+      const int col = wc0 + li;
+      // b. sT = Phi o (V^-1 F)
+#pragma unroll
+      for (int s = 0; s < NSR; ++s) {
+        if (s >= ns) break;
+        acc_t acc[1][1];
+        zero<T, 1, 1>(acc);
+        mma_rows_sB<T, 1, 1, KR>(acc, f1, sF + s * tile, ld, wc0, lane);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          sT[s * tile + (wr0 + M16<T>::row(g, q4)) * ld + col] = acc[0][0][q4] * ph[s][q4];
+      }
+      __syncthreads();
+      // c. sF = V sT
+#pragma unroll
+      for (int s = 0; s < NSR; ++s) {
+        if (s >= ns) break;
+        acc_t acc[1][1];
+        zero<T, 1, 1>(acc);
+        mma_rows_sB<T, 1, 1, KR>(acc, f2, sT + s * tile, ld, wc0, lane);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int row = wr0 + M16<T>::row(g, q4);
+          sF[s * tile + row * ld + col] = (row < nm && col < na) ? acc[0][0][q4] : T(0);
+        }
+      }
+      __syncthreads();
+      // d. sW += alpha (sF x_1 P)
+#pragma unroll
+      for (int s = 0; s < NSR; ++s) {
+        if (s >= ns) break;
+        acc_t acc[1][1];
+        zero<T, 1, 1>(acc);
+        mma_sA_cols<T, 1, 1, KC>(acc, sF + s * tile, ld, wr0, fp[s], lane);
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int row = wr0 + M16<T>::row(g, q4);
+          if (row < nm && col < na) {
+            T* w = sW + s * tile + row * ld + col;
+            *w = *w + alpha * acc[0][0][q4];
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    // b. sT = Phi o (V^-1 F)
+    for (int sub = wave; sub < nsub; sub += NW) {
+      const int s = sub / nsub1, q = sub - s * nsub1;
+      const int r0 = (q / nct) * 16, c0 = (q % nct) * 16, col = c0 + li;
+      acc_t acc[1][1];
+      zero<T, 1, 1>(acc);
+      gemm_gA_sB<T, 1, 1>(acc, factor_of<T>(a.L1, inst * ns + s), a.L1.ld, r0, sF + s * tile, ld, c0, NP, lane);
+      const double fc = cphi[s] * (a.ph.pn ? a.ph.pn[min(col, na - 1)] : 1.0);
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int row = r0 + M16<T>::row(g, q4);
+        const double fr = a.ph.pm ? a.ph.pm[min(row, nm - 1)] : 1.0;
+        const T v = acc[0][0][q4] * M16<T>::phi1(static_cast<T>(fc * fr));
+        sT[s * tile + row * ld + col] = (row < nm && col < na) ? v : T(0);
+      }
+    }
+    __syncthreads();
+    // c. sF = V sT
+    for (int sub = wave; sub < nsub; sub += NW) {
+      const int s = sub / nsub1, q = sub - s * nsub1;
+      const int r0 = (q / nct) * 16, c0 = (q % nct) * 16, col = c0 + li;
+      acc_t acc[1][1];
+      zero<T, 1, 1>(acc);
+      gemm_gA_sB<T, 1, 1>(acc, factor_of<T>(a.L2, inst * ns + s), a.L2.ld, r0, sT + s * tile, ld, c0, NP, lane);
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int row = r0 + M16<T>::row(g, q4);
+        sF[s * tile + row * ld + col] = (row < nm && col < na) ? acc[0][0][q4] : T(0);
+      }
+    }
+    __syncthreads();
+    // d. sW += alpha (sF x_1 P)
+    for (int sub = wave; sub < nsub; sub += NW) {
+      const int s = sub / nsub1, q = sub - s * nsub1;
+      const int r0 = (q / nct) * 16, c0 = (q % nct) * 16, col = c0 + li;
+      acc_t acc[1][1];
+      zero<T, 1, 1>(acc);
+      gemm_sA_gB<T, 1, 1>(acc, sF + s * tile, ld, r0, factor_of<T>(a.P, inst * ns + s), a.P.ld, c0, TN, lane);
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int row = r0 + M16<T>::row(g, q4);
+        if (row < nm && col < na) {
+          T* w = sW + s * tile + row * ld + col;
+          *w = *w + alpha * acc[0][0][q4];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // 2. the state back
+  bool bad = false;
+  for (int s = 0; s < ns; ++s)
+    for (int e = tid; e < nm * na; e += NT) {
+      int c;
+      const int k = dna.quot(e, c);
+      const T v = sW[s * tile + k * ld + c];
+      Wg[s * plane + e] = v;
+      bad |= !isfinite(v);
+    }
+  if (bad && a.flag) atomicOr(a.flag, 1);
+}
+
+// Padded rows and columns of the resident tiles: 64 x 32 (the register-
+// resident form) for grids up to that size, else nm and na rounded up to 16.
+int resident_np(int nm, int na) { return nm <= 64 && na <= 32 ? 64 : round_up(nm, 16); }
+int resident_tn(int nm, int na) { return nm <= 64 && na <= 32 ? 32 : round_up(na, 16); }
+
+template <typename T>
+size_t resident_lds_bytes(int ns, int nm, int na) {
+  if (ns < 1 || ns > 3 || nm < 1 || na < 1) return 0;
+  const int NP = resident_np(nm, na), TN = resident_tn(nm, na);
+  return static_cast<size_t>(3 * ns) * NP * pitch_kmajor<T>(TN) * sizeof(T) + sizeof(double) * (5 * NP + 4 * TN);
+}
+
+template <typename T>
+hipError_t launch_resident(const ResidentArgs& r, hipStream_t s) {
+  const StridedArgs& a = r.a;
+  const int ns = a.st.nspecies;
+  if (!a.stencil || !a.sandwich || !a.phi || !a.plane || !a.update || a.nb != 1 || a.st.ndim != 2)
+    return hipErrorInvalidValue;
+  if (ns < 1 || ns > 3 || r.ninst < 1 || r.ninst > 65535 || a.nslab != ns * r.ninst || r.steps < 1)
+    return hipErrorInvalidValue;
+  if (a.nm != a.st.n[1] || a.na != a.st.n[0] || a.W != a.st.W || !a.W) return hipErrorInvalidValue;
+  if (r.np != resident_np(a.nm, a.na) || r.tn != resident_tn(a.nm, a.na)) return hipErrorInvalidValue;
+  if (a.L1.ld < r.np || a.L2.ld < r.np || a.P.ld < r.tn) return hipErrorInvalidValue;
+  const size_t lds = resident_lds_bytes<T>(ns, a.nm, a.na);
+  if (lds == 0 || lds > kMaxLds) return hipErrorInvalidValue;
+  // the register-resident form for 64 x 32 padded tiles (8 waves) and up
+  // to two species, the general one otherwise
+  const bool reg = r.np == 64 && r.tn == 32 && a.L1.fmod == 1 && a.L2.fmod == 1 && ns <= 2;
+  auto k = reg ? resident_kernel<T, 8, 4, 2> : resident_kernel<T, 8, 0, 0>;
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(r.ninst), dim3(512), lds, s, r);
+  return hipGetLastError();
+}
+
 template hipError_t plan_strided_group<double>(StridedGroup&, GroupLaunch&);
 template hipError_t plan_strided_group<float>(StridedGroup&, GroupLaunch&);
 template hipError_t plan_first_group<double>(FirstGroup&, GroupLaunch&);
@@ -1455,5 +1734,9 @@ template size_t strided_lds_bytes<double>(int, int, int, int, int);
 template size_t strided_lds_bytes<float>(int, int, int, int, int);
 template size_t first_lds_bytes<double>(int, int, int);
 template size_t first_lds_bytes<float>(int, int, int);
+template hipError_t launch_resident<double>(const ResidentArgs&, hipStream_t);
+template hipError_t launch_resident<float>(const ResidentArgs&, hipStream_t);
+template size_t resident_lds_bytes<double>(int, int, int);
+template size_t resident_lds_bytes<float>(int, int, int);
 
 }  // namespace tg

@@ -121,6 +121,25 @@ size_t strided_lds_bytes(int nm, int tn, int sandwich, int plane, int stencil = 
 template <typename T>
 size_t first_lds_bytes(int nm, int tm, int sandwich);
 
+// Several split steps of a plan whose step is one fused strided op with the
+// stencil, the sandwich, its phi factor and the plane-tail update, on a 2D
+// grid (the disk), in one launch: one workgroup per instance keeps every
+// species' state in LDS for all `steps` steps.  a.W == a.st.W is the state
+// (read, then updated in place); np, tn: resident_np / resident_tn.
+struct ResidentArgs {
+  StridedArgs a;
+  int np, tn;
+  int ninst;
+  int steps;
+};
+template <typename T>
+hipError_t launch_resident(const ResidentArgs& r, hipStream_t s);
+int resident_np(int nm, int na);
+int resident_tn(int nm, int na);
+// LDS bytes of the resident launch (0 if the shape is not supported).
+template <typename T>
+size_t resident_lds_bytes(int ns, int nm, int na);
+
 // Split-bf16 variants (FP32 state and accumulation; nterms = 2 or 3 bf16
 // terms per operand).  Factors are NT-term bf16 stacks: term t of block f at
 // (bf16*) L + f * fstride + t * ld * ld.  A plane launch needs a sandwich
