@@ -1525,23 +1525,34 @@ __global__ __launch_bounds__(64 * NW) void resident_kernel(ResidentArgs r) {
   const T alpha = static_cast<T>(a.alpha);
   // register-resident operands of this wave's output position (KR > 0)
   using v4 = typename M16<T>::v4;
+  // KR > 0: wave w owns output position w % (KR KC) and the species
+  // w / (KR KC), w / (KR KC) + SPW, ... (SPW = NW / (KR KC) waves per
+  // position), NJ = NSR / SPW of them
   constexpr int KRr = KR > 0 ? KR : 1, KCr = KC > 0 ? KC : 1;
-  const int wr0 = KR > 0 ? (wave / KCr) * 16 : 0, wc0 = KR > 0 ? (wave % KCr) * 16 : 0;
-  v4 f1[1][KRr], f2[1][KRr], fp[NSR][1][KCr];
-  T ph[NSR][4];
+  constexpr int SPW = KR > 0 ? NW / (KR * KC) : 1, NJ = NSR / SPW;
+  static_assert(KR == 0 || (SPW >= 1 && NJ >= 1 && NJ * SPW == NSR), "resident: waves per position");
+  const int pos = wave % (KRr * KCr), s0 = wave / (KRr * KCr);
+  const int wr0 = KR > 0 ? (pos / KCr) * 16 : 0, wc0 = KR > 0 ? (pos % KCr) * 16 : 0;
+  v4 f1[1][KRr], f2[1][KRr], fp[NJ][1][KCr];
+  T ph[NJ][4];
   if constexpr (KR > 0) {
     load_rows_u<T, 1, KR>(f1, factor_of<T>(a.L1, inst * ns), a.L1.ld, wr0, lane);
     load_rows_u<T, 1, KR>(f2, factor_of<T>(a.L2, inst * ns), a.L2.ld, wr0, lane);
     const int col = wc0 + li;
 #pragma unroll
-    for (int s = 0; s < NSR; ++s) {
-      if (s < ns) load_cols_u<T, 1, KC>(fp[s], factor_of<T>(a.P, inst * ns + s), a.P.ld, wc0, lane);
-      const double fc = s < ns ? cphi[s] * (a.ph.pn ? a.ph.pn[min(col, na - 1)] : 1.0) : 0.0;
+    for (int j = 0; j < NJ; ++j) {
+      const int s = s0 + j * SPW;
+      if (s < ns) load_cols_u<T, 1, KC>(fp[j], factor_of<T>(a.P, inst * ns + s), a.P.ld, wc0, lane);
+      double cp = 0.0;
+#pragma unroll
+      for (int q = 0; q < NSR; ++q)
+        if (q == s) cp = cphi[q];
+      const double fc = cp * (a.ph.pn ? a.ph.pn[min(col, na - 1)] : 1.0);
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4) {
         const int row = wr0 + M16<T>::row(g, q4);
         const double fr = a.ph.pm ? a.ph.pm[min(row, nm - 1)] : 1.0;
-        ph[s][q4] = (s < ns && row < nm && col < na) ? M16<T>::phi1(static_cast<T>(fc * fr)) : T(0);
+        ph[j][q4] = (s < ns && row < nm && col < na) ? M16<T>::phi1(static_cast<T>(fc * fr)) : T(0);
       }
     }
   }
@@ -1576,19 +1587,21 @@ __global__ __launch_bounds__(64 * NW) void resident_kernel(ResidentArgs r) {
       const int col = wc0 + li;
       // b. sT = Phi o (V^-1 F)
 #pragma unroll
-      for (int s = 0; s < NSR; ++s) {
+      for (int j = 0; j < NJ; ++j) {
+        const int s = s0 + j * SPW;
         if (s >= ns) break;
         acc_t acc[1][1];
         zero<T, 1, 1>(acc);
         mma_rows_sB<T, 1, 1, KR>(acc, f1, sF + s * tile, ld, wc0, lane);
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4)
-          sT[s * tile + (wr0 + M16<T>::row(g, q4)) * ld + col] = acc[0][0][q4] * ph[s][q4];
+          sT[s * tile + (wr0 + M16<T>::row(g, q4)) * ld + col] = acc[0][0][q4] * ph[j][q4];
       }
       __syncthreads();
       // c. sF = V sT
 #pragma unroll
-      for (int s = 0; s < NSR; ++s) {
+      for (int j = 0; j < NJ; ++j) {
+        const int s = s0 + j * SPW;
         if (s >= ns) break;
         acc_t acc[1][1];
         zero<T, 1, 1>(acc);
@@ -1602,11 +1615,12 @@ __global__ __launch_bounds__(64 * NW) void resident_kernel(ResidentArgs r) {
       __syncthreads();
       // d. sW += alpha (sF x_1 P)
 #pragma unroll
-      for (int s = 0; s < NSR; ++s) {
+      for (int j = 0; j < NJ; ++j) {
+        const int s = s0 + j * SPW;
         if (s >= ns) break;
         acc_t acc[1][1];
         zero<T, 1, 1>(acc);
-        mma_sA_cols<T, 1, 1, KC>(acc, sF + s * tile, ld, wr0, fp[s], lane);
+        mma_sA_cols<T, 1, 1, KC>(acc, sF + s * tile, ld, wr0, fp[j], lane);
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int row = wr0 + M16<T>::row(g, q4);
@@ -1687,6 +1701,13 @@ __global__ __launch_bounds__(64 * NW) void resident_kernel(ResidentArgs r) {
 int resident_np(int nm, int na) { return nm <= 64 && na <= 32 ? 64 : round_up(nm, 16); }
 int resident_tn(int nm, int na) { return nm <= 64 && na <= 32 ? 32 : round_up(na, 16); }
 
+// Waves of the register-resident form: FP32, 16 (one per position and
+// species; measured 5.9 against 6.7 us per step on the 32 x 64 disk); FP64,
+// 8 (one per position, both species: at 16 waves the 128-register budget
+// spills and a step takes 10.4 against 9.5 us).
+template <typename T>
+constexpr int resident_reg_waves() { return sizeof(T) == 4 ? 16 : 8; }
+
 template <typename T>
 size_t resident_lds_bytes(int ns, int nm, int na) {
   if (ns < 1 || ns > 3 || nm < 1 || na < 1) return 0;
@@ -1710,10 +1731,11 @@ hipError_t launch_resident(const ResidentArgs& r, hipStream_t s) {
   // the register-resident form for 64 x 32 padded tiles (8 waves) and up
   // to two species, the general one otherwise
   const bool reg = r.np == 64 && r.tn == 32 && a.L1.fmod == 1 && a.L2.fmod == 1 && ns <= 2;
-  auto k = reg ? resident_kernel<T, 8, 4, 2> : resident_kernel<T, 8, 0, 0>;
+  constexpr int RW = resident_reg_waves<T>();
+  auto k = reg ? resident_kernel<T, RW, 4, 2> : resident_kernel<T, 8, 0, 0>;
   hipError_t e = allow_lds(k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(r.ninst), dim3(512), lds, s, r);
+  hipLaunchKernelGGL(k, dim3(r.ninst), dim3(reg ? 64 * RW : 512), lds, s, r);
   return hipGetLastError();
 }
 
