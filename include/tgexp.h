@@ -292,7 +292,9 @@ int tg_run_timed(tg_plan p, void* state, int64_t n_steps, void* stream, int32_t 
  * tiles remapped so each XCD walks a contiguous range); otherwise the
  * plans' launches follow each other.  Steps are replayed from a graph
  * captured on first use per (plans, configurations, states) and kept by
- * plans[0] until it is destroyed.  Synchronises the stream at the end;
+ * plans[0] until it is destroyed; when a plan is on route 4, every plan
+ * runs its n_steps as tg_run would (resident launches, or its own graph
+ * replays), one plan after the other.  Synchronises the stream at the end;
  * TG_ENONFINITE if any plan produced a non-finite value. */
 int tg_group_run(const tg_plan* plans, int32_t n_plans, void* const* states, int64_t n_steps,
                  void* stream);

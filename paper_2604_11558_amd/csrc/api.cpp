@@ -1919,9 +1919,17 @@ int tg_group_run(const tg_plan* plans, int32_t n_plans, void* const* states, int
     TG_REQUIRE(n_steps >= 0, TG_EINVAL, "tg_group_run: negative step count");
     tg_group_s* G = find_group(plans, n_plans, states);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t full = n_steps / kStepsPerGraph;
-    for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(G->graph, st), "tg_group_run: graph launch");
-    for (int64_t it = full * kStepsPerGraph; it < n_steps; ++it) group_step_any(G, st);
+    bool resident = false;
+    for (auto* P : G->plans) resident = resident || active_route(P) == 4;
+    if (resident) {
+      // members on route 4 run all their steps in resident launches, the
+      // others their own graph replays (the members are independent)
+      for (size_t q = 0; q < G->plans.size(); ++q) run_plain(G->plans[q], G->states[q], n_steps, st);
+    } else {
+      const int64_t full = n_steps / kStepsPerGraph;
+      for (int64_t it = 0; it < full; ++it) hip_check(hipGraphLaunch(G->graph, st), "tg_group_run: graph launch");
+      for (int64_t it = full * kStepsPerGraph; it < n_steps; ++it) group_step_any(G, st);
+    }
     std::vector<int> flags(G->plans.size(), 0);
     for (size_t q = 0; q < G->plans.size(); ++q)
       hip_check(hipMemcpyAsync(&flags[q], G->plans[q]->dflag, sizeof(int), hipMemcpyDeviceToHost, st),

@@ -140,3 +140,18 @@ def test_autotune_keeps_parity():
     print("autotuned", res, case.plan.route)
     case.plan.run(x, 6)
     assert rel_err(case.full_from_device(x), case.oracle_run(6)) < TOL["fp32"]
+
+
+def test_group_run_with_a_resident_member():
+    """A resident disk plan grouped with a sphere plan: each member runs its
+    steps as tg_run would, and both match the oracle."""
+    disk = Case("disk", (32, 64), "fp64", tau=1e-2, seed=50, batch=2,
+                params=[(0.1, 0.9), (0.15, 0.8)], diff=[(1.0, 20.0), (1.0, 12.0)])
+    sph = Case("sphere", (24, 20), "fp64", tau=1e-2, seed=51)
+    disk.plan.set_route("resident")
+    states = [disk.device_state(), sph.device_state()]
+    info = tg.group_info([disk.plan, sph.plan], states)
+    assert not info["grouped"]
+    tg.group_run([disk.plan, sph.plan], states, 11)
+    assert rel_err(disk.full_from_device(states[0]), disk.oracle_run(11)) < 1e-12
+    assert rel_err(sph.full_from_device(states[1]), sph.oracle_run(11)) < 1e-12
