@@ -1570,9 +1570,13 @@ __global__ __launch_bounds__(64 * NW) void resident_kernel(ResidentArgs r) {
       const double* r5 = rc + k * 5;
       const double* c4 = cc + c * 4;
       double wv[3] = {0.0, 0.0, 0.0}, G[3] = {0.0, 0.0, 0.0};
-      for (int s = 0; s < ns; ++s) wv[s] = static_cast<double>(sW[s * tile + k * ld + c]);
+#pragma unroll
+      for (int s = 0; s < NSR; ++s)
+        if (s < ns) wv[s] = static_cast<double>(sW[s * tile + k * ld + c]);
       if (react) reaction3c(rcst, wv[0], wv[1], wv[2], G[0], G[1], G[2]);
-      for (int s = 0; s < ns; ++s) {
+#pragma unroll
+      for (int s = 0; s < NSR; ++s) {
+        if (s >= ns) break;
         const T* w = sW + s * tile;
         const double w0 = wv[s];
         double f = c4[3] * (r5[2] * static_cast<double>(w[km * ld + c]) + r5[3] * w0 +
