@@ -212,12 +212,16 @@ def other_workloads(tg, torch, steps):
         plan.run(x, 16)
         sec = time_gpu_run(plan, x, nrun, 0, torch)
         route = plan.route
+        flops = sum(f for _, f in plan.chain())  # per step: (2 n_rho + 4 n_theta) per dof
+        peak = 78.6 if prec == "fp64" else 157.3
         plan.set_route("fused")
         plan.run(x, 16)
         sec_fused = time_gpu_run(plan, x, nrun, 0, torch)
         out[f"disk_32x64_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3,
                                      "steps_per_s": 1.0 / sec, "dof": wl.dof, "route": route,
                                      "steps_timed": nrun,
+                                     "mfma_tflops": flops / sec / 1e12,
+                                     "frac_of_one_cu_mfma_peak": flops / sec / 1e12 / (peak / 256),
                                      "fused_route": {"ms_per_step": sec_fused * 1e3,
                                                      "launches_per_step": len(plan.run_timed(x.clone(), 1))}}
         del plan, x
@@ -229,7 +233,9 @@ def other_workloads(tg, torch, steps):
         plan.run(x, 16)
         sec = time_gpu_run(plan, x, nrun, 0, torch)
         out[f"disk_32x64_batch256_resident_{prec}"] = {"value": B * wl.dof / sec, "unit": "dof-steps/s",
-                                                       "ms_per_step": sec * 1e3, "instances": B}
+                                                       "ms_per_step": sec * 1e3, "instances": B,
+                                                       "mfma_tflops": B * flops / sec / 1e12,
+                                                       "frac_of_mfma_peak": B * flops / sec / 1e12 / peak}
         del plan, x
     # 160 x 160 anomalous-diffusion disk (lambda = -1.95), FP64 and FP32
     wl = workloads.WORKLOADS["disk_lambda_160x160"]

@@ -1708,8 +1708,7 @@ int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* 
     tg::DiagArgs d = records > 0 ? diag_args(p, diag) : tg::DiagArgs{};
     int64_t done = 0;
     for (int64_t r = 0; r < records; ++r) {
-      // every - 1 plain steps (graph replays of kStepsPerGraph, then single
-      // launches), then the recorded step
+      // every - 1 plain steps (run_plain), then the recorded step
       run_plain(p, state, every - 1, st);
       d.out = diag + 2 * static_cast<int64_t>(p->nslab) * r;
       step_any(p, state, st, &d);
