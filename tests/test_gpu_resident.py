@@ -37,6 +37,30 @@ def test_resident_run_matches_oracle(geometry, n, precision):
     assert err < TOL[precision]
 
 
+# the general form (factors from L2, phi_1 per step): 40 x 48 is wider than
+# the 64 x 32 register-resident tiles in both precisions; three species
+# (the cubic activator-inhibitor-substrate kinetics) always take it.
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_general_form_matches_oracle(precision):
+    case = Case("disk", (40, 48), precision, tau=1e-2, seed=52)
+    case.plan.set_route("resident")
+    x = case.device_state()
+    case.plan.run(x, 9)
+    err = rel_err(case.full_from_device(x), case.oracle_run(9))
+    print("disk (40, 48)", precision, "general resident vs oracle %.2e" % err)
+    assert err < TOL[precision]
+
+
+def test_three_species_matches_oracle():
+    case = Case("disk", (32, 64), "fp32", tau=5e-3, seed=53, n_species=3)
+    case.plan.set_route("resident")
+    x = case.device_state()
+    case.plan.run(x, 9)
+    err = rel_err(case.full_from_device(x), case.oracle_run(9))
+    print("disk (32, 64) 3 species fp32 resident vs oracle %.2e" % err)
+    assert err < TOL["fp32"]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_single_steps_equal_one_multi_step_launch(precision):
     case = Case("disk", (32, 64), precision, tau=1e-2, seed=42)
