@@ -147,7 +147,10 @@ int tg_step(tg_plan p, void* state, void* stream);
  * last report wrote a non-finite value (TG_ENONFINITE; the flag is then
  * cleared).  For callers that step with tg_step / tg_step_diag. */
 int tg_sync_status(tg_plan p, void* stream);
-/* n_steps steps (in place); steps are replayed from a captured HIP graph.
+/* n_steps steps (in place): replays of captured HIP graphs of 32 and of 8
+ * steps (both captured per state pointer on the first run of 8 steps or
+ * more, kept until the plan is destroyed or reconfigured), single steps for
+ * the rest; on route 4, resident launches of up to 1024 steps.
  * Synchronises the stream at the end and returns TG_ENONFINITE if any
  * update produced a non-finite value. */
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -106,8 +107,8 @@ struct tg_plan_s {
   std::vector<tg::FusedOp> fused;   // fused route
   bool fused_ok = false;
   int route = 0;                     // 0 fused (when available), 1 generic
-  // captured step graphs keyed by state pointer
-  std::map<void*, hipGraphExec_t> graphs;
+  // captured step graphs keyed by (state pointer, steps per graph)
+  std::map<std::pair<void*, int>, hipGraphExec_t> graphs;
   hipStream_t capture_stream = nullptr;
   // unique id, and a counter bumped whenever the launch configuration
   // (route, tiles) changes; grouped runs are keyed on both
