@@ -167,7 +167,20 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
   const int xsz = a.plane ? max(NT * tstr, NT * rstr) : NT * tstr;
   __bf16* sX = reinterpret_cast<__bf16*>(smem);
   __bf16* sT = sX + xsz;
-  const int a0 = blockIdx.x * TN, b = blockIdx.y, s = blockIdx.z;
+  // 1D grid of 8 * per_xcd workgroups, dispatched round-robin over the 8
+  // XCDs: XCD x takes logical tiles x * per_xcd .. (x + 1) * per_xcd, in
+  // the order species, column tile, row block, instance, so that a tile's
+  // stencil neighbours and its other species share an XCD's L2
+  const int nbx = (na + TN - 1) / TN;
+  const int total = nbx * a.nb * a.nslab;
+  const int per_xcd = (total + 7) / 8;
+  const int L = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= total) return;
+  const int nsp = a.stencil ? a.st.nspecies : 1;
+  int rest = L / nsp;
+  const int bx = rest % nbx;
+  rest /= nbx;
+  const int a0 = bx * TN, b = rest % a.nb, s = (rest / a.nb) * nsp + L % nsp;
   const int64_t slab = static_cast<int64_t>(nm) * na * a.nb;
   const int64_t base = static_cast<int64_t>(s) * slab + static_cast<int64_t>(b) * nm * na;
 
@@ -176,6 +189,8 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
     const int inst = s / a.st.nspecies, sp = s % a.st.nspecies;
     const int n1 = a.st.n[0];
     const bool three = a.st.ndim == 3;
+    // four points per thread in flight (their loads overlap)
+#pragma unroll 4
     for (int e = tid; e < NP * TN; e += 256) {
       const int k = e / TN, c = e % TN;
       const int aa = a0 + c;
@@ -316,11 +331,9 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
         }
     if (bad && a.flag) atomicOr(a.flag, 1);
   }
-  if (diag) {
-    const int nbx = (na + TN - 1) / TN;
-    diag_flush<4>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + static_cast<int64_t>(b) * nbx + blockIdx.x,
+  if (diag)
+    diag_flush<4>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + static_cast<int64_t>(b) * nbx + bx,
                   reinterpret_cast<double*>(smem));
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -463,8 +476,10 @@ static hipError_t go_sbf(const StridedArgs& a, size_t lds, hipStream_t s) {
   auto k = strided_bf16_kernel<NT, FM, FN, KB>;
   hipError_t e = bf_allow(k, lds);
   if (e != hipSuccess) return e;
-  dim3 grid((a.na + a.tn - 1) / a.tn, a.nb, a.nslab);
-  hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);
+  const int64_t total = static_cast<int64_t>((a.na + a.tn - 1) / a.tn) * a.nb * a.nslab;
+  if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
+  const int per_xcd = static_cast<int>((total + 7) / 8);
+  hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
