@@ -151,8 +151,8 @@ __device__ __forceinline__ void put1(__bf16* s, int stride, int off, float v) {
 
 // ---------------------------------------------------------------------------
 // Strided mode (mu >= 2): data tile column c (k-contiguous) of NT terms.
-template <int NT, int FM, int FN, int KB>
-__global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
+template <int NT, int FM, int FN, int KB, int NW>
+__global__ __launch_bounds__(64 * NW) void strided_bf16_kernel(StridedArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
     const bool three = a.st.ndim == 3;
     // four points per thread in flight (their loads overlap)
 #pragma unroll 4
-    for (int e = tid; e < NP * TN; e += 256) {
+    for (int e = tid; e < NP * TN; e += 64 * NW) {
       const int k = e / TN, c = e % TN;
       const int aa = a0 + c;
       float v = 0.0f;
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
     }
   } else {
     const float* X = static_cast<const float*>(a.X) + base;
-    for (int e = tid; e < NP * TN; e += 256) {
+    for (int e = tid; e < NP * TN; e += 64 * NW) {
       const int k = e / TN, c = e % TN;
       const float v = (k < nm && a0 + c < na) ? X[static_cast<int64_t>(k) * na + a0 + c] : 0.0f;
       put1<NT>(sX, tstr, c * ldk + k, v);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
   const int kblocks = NP / 32;
 
   // 2. first product and the phi_1 factor
-  for (int sub = wave; sub < nsub; sub += 4) {
+  for (int sub = wave; sub < nsub; sub += NW) {
     const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
     float ph[FM][FN][4];
     if (a.phi) {
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
   if (a.sandwich) {
     const __bf16* L2 = bf_factor(a.L2, s);
     const int64_t t2 = static_cast<int64_t>(a.L2.ld) * a.L2.ld;
-    for (int sub = wave; sub < nsub; sub += 4) {
+    for (int sub = wave; sub < nsub; sub += NW) {
       const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
       fx4 acc[FM][FN];
       zero_acc<FM, FN>(acc);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
   const float alpha = static_cast<float>(a.alpha);
   const bool diag = a.dg.part != nullptr;
   double ds0 = 0.0, ds1 = 0.0;
-  for (int sub = wave; sub < nsub; sub += 4) {
+  for (int sub = wave; sub < nsub; sub += NW) {
     const int r0 = (sub / nct) * 16 * FM, c0 = (sub % nct) * 16 * FN;
     float wv[FM][FN][4];
 #pragma unroll
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void strided_bf16_kernel(StridedArgs a) {
     if (bad && a.flag) atomicOr(a.flag, 1);
   }
   if (diag)
-    diag_flush<4>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + static_cast<int64_t>(b) * nbx + bx,
+    diag_flush<NW>(a.dg, ds0, ds1, static_cast<int64_t>(s) * a.dg.tiles + static_cast<int64_t>(b) * nbx + bx,
                   reinterpret_cast<double*>(smem));
 }
 
@@ -471,15 +471,15 @@ static hipError_t bf_allow(K kernel, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
-template <int NT, int FM, int FN, int KB>
+template <int NT, int FM, int FN, int KB, int NW = 4>
 static hipError_t go_sbf(const StridedArgs& a, size_t lds, hipStream_t s) {
-  auto k = strided_bf16_kernel<NT, FM, FN, KB>;
+  auto k = strided_bf16_kernel<NT, FM, FN, KB, NW>;
   hipError_t e = bf_allow(k, lds);
   if (e != hipSuccess) return e;
   const int64_t total = static_cast<int64_t>((a.na + a.tn - 1) / a.tn) * a.nb * a.nslab;
   if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int per_xcd = static_cast<int>((total + 7) / 8);
-  hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * NW), lds, s, a);
   return hipGetLastError();
 }
 
@@ -487,6 +487,14 @@ template <int NT>
 static hipError_t sbf_dispatch(const StridedArgs& a, size_t lds, hipStream_t s) {
   const int kb = bf_kb(a.nm);
   const bool fn2 = a.tn % 32 == 0;
+  // 8 waves where a tile has 8 or more 16-wide sub-tiles (more waves per
+  // SIMD to overlap the latencies of the few workgroups of these launches)
+  // (NP = 32 kb rows: kb tn / 16 sub-tiles of 32 x 16, twice as many of 16 x 16)
+  const int c16 = a.tn / 16;
+  if (kb > 0 && kb * c16 >= 8)
+    return kb == 2 ? go_sbf<NT, 2, 1, 2, 8>(a, lds, s) : go_sbf<NT, 2, 1, 4, 8>(a, lds, s);
+  if (kb > 0 && 2 * kb * c16 >= 8)
+    return kb == 2 ? go_sbf<NT, 1, 1, 2, 8>(a, lds, s) : go_sbf<NT, 1, 1, 4, 8>(a, lds, s);
   if (kb == 2) return fn2 ? go_sbf<NT, 2, 2, 2>(a, lds, s) : go_sbf<NT, 2, 1, 2>(a, lds, s);
   if (kb == 4) return fn2 ? go_sbf<NT, 2, 2, 4>(a, lds, s) : go_sbf<NT, 2, 1, 4>(a, lds, s);
   return fn2 ? go_sbf<NT, 4, 2, 0>(a, lds, s) : go_sbf<NT, 4, 1, 0>(a, lds, s);
