@@ -304,6 +304,10 @@ template <typename T>
 void build_plan(tg_plan_s* P) {
   const tg_grid_s& G = P->grid;
   const int nd = G.ndim;
+  int dev = 0, num_cus = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  hip_check(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+  num_cus = std::max(num_cus, 1);
   const int n1 = G.n[0], n2 = G.n[1], n3 = nd == 3 ? G.n[2] : 1;
   const int nslab = P->nslab;
   const double tau = P->tau;
@@ -701,7 +705,18 @@ void build_plan(tg_plan_s* P) {
       bool plane = f.plane != 0;
       if (plane) {
         sa.tn = (f.na + 31) / 32 * 32;
-        if (strided_lds(f.nm, f.na, sa.tn, f.sandwich, 1, f.stencil) > kLdsLimit) plane = false;
+        const size_t lds = strided_lds(f.nm, f.na, sa.tn, f.sandwich, 1, f.stencil);
+        if (lds > kLdsLimit) {
+          plane = false;
+        } else {
+          // whole planes that take two rounds of workgroups, the second
+          // less than half full, run slower than the split tail (sandwich
+          // launch, then the mode-1 launch): the 100^3 cylinder's 300
+          // planes of 135-139 KB (one per CU) on 256 CUs
+          const int64_t slots = std::max<int64_t>(1, static_cast<int64_t>(kLdsLimit / lds)) * num_cus;
+          const int64_t wgs = static_cast<int64_t>(f.nb) * nslab;
+          if (wgs > slots && wgs - slots < slots / 2) plane = false;
+        }
       }
       if (!plane) {
         // 32-wide column tiles when that still gives ~512 workgroups, and
