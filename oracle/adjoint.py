@@ -92,9 +92,14 @@ def apply_chain(ops, X):
     return X
 
 
-def apply_chain_T(ops, X):
+def apply_chain_T(ops, X, rnd=None):
+    """S^T X: the transposed ops in reverse order.  ``rnd`` (optional) is
+    applied to every intermediate result (used to model a lower-precision
+    evaluation of the same recursion)."""
     for op in reversed(ops):
         X = mode_product(X, op[1].T, op[3]) if op[0] == "mode" else op[1] * X
+        if rnd is not None:
+            X = rnd(X)
     return X
 
 
@@ -134,11 +139,17 @@ def param_derivative(kind, U, params):
     raise NotImplementedError(kind)
 
 
-def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None, w_dirichlet=None):
+def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None, w_dirichlet=None,
+                  round_to=None):
     """L and dL/d(W0, d_s, params) for species-list W0s (arrays [i,j,..]).
 
     ``w_dirichlet`` (per species) is the boundary value at z_* of the
     cylinder; the lifted term d_s r w_D then enters F and dL/dd_s.
+    ``round_to`` (a NumPy float type, default None = exact FP64) rounds the
+    reverse sweep's stored quantities to that type -- the factors, every
+    intermediate of S^T lambda, mu, M^T mu and lambda after each update --
+    to model what a lower-precision evaluation of the same recursion loses
+    (the arithmetic itself stays FP64).
     """
     diff = list(workload.diff if diff is None else diff)
     params = tuple(workload.params if params is None else params)
@@ -154,6 +165,11 @@ def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None, 
     lam = [resid] + [np.zeros_like(W) for W in W0s[1:]]
     ns = len(W0s)
     ops = [chain(se, s) for s in range(ns)]
+    rnd = None
+    if round_to is not None:
+        rnd = lambda X: np.asarray(X).astype(round_to).astype(np.float64)  # noqa: E731
+        ops = [[(o[0], rnd(o[1])) + tuple(o[2:]) for o in chain_s] for chain_s in ops]
+        lam = [rnd(x) for x in lam]
     g_d = np.zeros(ns)
     g_p = np.zeros(len(params))
     Mt = se.M.T.tocsr()
@@ -162,7 +178,9 @@ def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None, 
         G = react(Ws)
         J = reactions.jacobian(workload.reaction, Ws, params)
         dGp = param_derivative(workload.reaction, Ws, params)
-        mus = [se.tau * apply_chain_T(ops[s], lam[s]) for s in range(ns)]
+        mus = [se.tau * apply_chain_T(ops[s], lam[s], rnd) for s in range(ns)]
+        if rnd is not None:
+            mus = [rnd(m) for m in mus]
         new = []
         for s in range(ns):
             wd = 0.0 if w_dirichlet is None else w_dirichlet[s]
@@ -171,10 +189,12 @@ def loss_and_grad(workload, W0s, target, steps, n=None, diff=None, params=None, 
             g_d[s] += se.tau * float(np.sum(lam[s] * apply_chain_dd(ops[s], F)))
             g_d[s] += float(np.sum(mus[s] * MW))
             MtMu = assemble.unvec(Mt @ assemble.vec(mus[s]), n)
+            if rnd is not None:
+                MtMu = rnd(diff[s] * MtMu) / diff[s]
             acc = lam[s] + diff[s] * MtMu
             for r in range(ns):
                 acc = acc + J[r][s] * mus[r]
-            new.append(acc)
+            new.append(acc if rnd is None else rnd(acc))
         for r in range(ns):
             for q in range(len(params)):
                 g_p[q] += float(np.sum(mus[r] * dGp[r][q]))

@@ -9,9 +9,15 @@ so memory is O(sqrt(T)) states and the forward is recomputed once.
 
 Gradients are returned for the initial state (a deviation from the fixed
 reference state ``w_ref``), the diffusion coefficients ``diff``
-[batch, n_species] and the reaction constants a, b ([batch, 2]: they enter
-the first two species' reactions additively).  The reference state is not
-differentiated.
+[batch, n_species] and the reaction constants a, b ([batch, 2]).  In the
+plain Schnakenberg and three-species kinetics a and b are additive sources
+of the first two species; in the alpha_1-scaled Schnakenberg kinetics of
+Section 5.3 they enter as gamma a and gamma b (gamma = alpha_1, the third
+reaction constant), so their gradient carries that factor.  The reference
+state is not differentiated: it must be given explicitly when ``ab``
+requires a gradient (the default reference, the equilibrium at (a, b),
+would make the initial absolute state depend on (a, b) in a way the
+reverse sweep does not follow).
 
 The reverse sweep multiplies the rounding of tau S^T lambda by
 tau d M^T, whose norm grows like 1/h^2 and, near the axis and the poles,
@@ -20,15 +26,46 @@ accuracy in lambda on stiff grids.  By default the adjoint steps therefore
 run on an FP64 plan of the same problem, fed with the recomputed
 lower-precision states (``adjoint_precision="fp64"``); ``"same"`` keeps
 the forward plan's arithmetic.
+
+Plans are built once per problem (grid, coefficients, constants, reference,
+tau, precision) and kept in a small cache, so repeated calls (an optimiser
+loop) spend no time on factor set-up.
 """
 from __future__ import annotations
 
 import math
+from collections import OrderedDict
 
 import numpy as np
 import torch
 
 from . import Grid, Plan
+
+_PLAN_CACHE: "OrderedDict[tuple, Plan]" = OrderedDict()
+_PLAN_CACHE_SIZE = 4
+
+
+def cached_plan(grid: Grid, diff: np.ndarray, reaction: str, params: np.ndarray, tau: float,
+                precision: str, batch: int, w_ref) -> Plan:
+    """A plan for this problem, built on first use and then reused."""
+    wr = None if w_ref is None else np.ascontiguousarray(
+        np.broadcast_to(np.asarray(w_ref, dtype=np.float64), diff.shape))
+    key = (id(grid), grid.geometry, grid.n, grid.extent, diff.tobytes(), diff.shape, reaction,
+           params.tobytes(), params.shape, float(tau), precision, int(batch),
+           None if wr is None else wr.tobytes())
+    plan = _PLAN_CACHE.get(key)
+    if plan is not None and plan.grid is grid:
+        _PLAN_CACHE.move_to_end(key)
+        return plan
+    plan = Plan(grid, diff, reaction, params, tau, precision, batch, w_ref=wr)
+    _PLAN_CACHE[key] = plan
+    while len(_PLAN_CACHE) > _PLAN_CACHE_SIZE:
+        _PLAN_CACHE.popitem(last=False)
+    return plan
+
+
+def clear_plan_cache() -> None:
+    _PLAN_CACHE.clear()
 
 
 class SplitEEFunction(torch.autograd.Function):
@@ -36,12 +73,19 @@ class SplitEEFunction(torch.autograd.Function):
     def forward(ctx, w0, diff, ab, grid, reaction, extra_params, w_ref, tau, precision, n_steps, segment,
                 adjoint_precision):
         batch = diff.shape[0]
-        params = np.concatenate([ab.detach().cpu().numpy().reshape(batch, 2),
-                                 np.asarray(extra_params, float).reshape(batch, -1)], axis=1) \
-            if extra_params is not None else ab.detach().cpu().numpy().reshape(batch, 2)
-        plan = Plan(grid, diff.detach().cpu().numpy(), reaction, params, tau, precision, batch,
-                    w_ref=w_ref)
-        x = w0.detach().to(plan.dtype).contiguous().clone()
+        ab_np = ab.detach().cpu().numpy().reshape(batch, 2)
+        params = np.concatenate([ab_np, np.asarray(extra_params, float).reshape(batch, -1)], axis=1) \
+            if extra_params is not None else ab_np
+        diff_np = np.ascontiguousarray(diff.detach().cpu().numpy())
+        params = np.ascontiguousarray(params)
+        plan = cached_plan(grid, diff_np, reaction, params, tau, precision, batch, w_ref)
+        # steps run on one buffer per plan, so the graphs tg_run replays are
+        # captured once for it rather than once per call
+        x = getattr(plan, "_autograd_state", None)
+        if x is None or x.shape != w0.shape or x.device != w0.device:
+            x = torch.empty(w0.shape, dtype=plan.dtype, device=w0.device)
+            plan._autograd_state = x
+        x.copy_(w0.detach())
         ckpts = []
         done = 0
         while done < n_steps:
@@ -49,11 +93,12 @@ class SplitEEFunction(torch.autograd.Function):
             k = min(segment, n_steps - done)
             plan.run(x, k)
             done += k
+        x = x.clone()
         ctx.plan = plan
         ctx.adj_plan = plan
         if adjoint_precision == "fp64" and precision != "fp64":
-            ctx.adj_plan = Plan(grid, diff.detach().cpu().numpy(), reaction, params, tau, "fp64", batch,
-                                w_ref=plan.reference)
+            ctx.adj_plan = cached_plan(grid, diff_np, reaction, params, tau, "fp64", batch, plan.reference)
+        ctx.gamma = params[:, 2].copy() if reaction == "schnakenberg_scaled" else None
         ctx.ckpts = ckpts
         ctx.n_steps = n_steps
         ctx.segment = segment
@@ -67,21 +112,31 @@ class SplitEEFunction(torch.autograd.Function):
         lam = grad_out.detach().to(adj.dtype).contiguous().clone()
         nslab = plan.batch * plan.n_species
         grad = torch.zeros(2 * nslab, dtype=torch.float64, device=lam.device)
+        # one segment's states, reused for every segment; when the reverse
+        # sweep runs in another precision, one conversion buffer
+        seg_states = [torch.empty_like(ckpts[0]) for _ in range(min(ctx.segment, ctx.n_steps))]
+        conv = None if adj.dtype == plan.dtype else torch.empty(ckpts[0].shape, dtype=adj.dtype,
+                                                                 device=lam.device)
         for k in range(len(ckpts) - 1, -1, -1):
             start = k * ctx.segment
             length = min(ctx.segment, ctx.n_steps - start)
-            states = [ckpts[k]]
-            x = ckpts[k].clone()
-            for _ in range(length - 1):
-                plan.step(x)
-                states.append(x.clone())
-            for st in reversed(states):
-                adj.adjoint_step(st.to(adj.dtype).contiguous(), lam, grad)
+            seg_states[0].copy_(ckpts[k])
+            for i in range(1, length):
+                seg_states[i].copy_(seg_states[i - 1])
+                plan.step(seg_states[i])
+            for i in range(length - 1, -1, -1):
+                st = seg_states[i]
+                if conv is not None:
+                    conv.copy_(st)
+                    st = conv
+                adj.adjoint_step(st, lam, grad)
         torch.cuda.synchronize()
         g = grad.cpu().numpy()
         g_diff = torch.from_numpy(g[:nslab].reshape(dshape))
-        src = g[nslab:].reshape(plan.batch, plan.n_species)
-        g_ab = torch.from_numpy(src[:, :2].copy()).reshape(abshape)
+        src = g[nslab:].reshape(plan.batch, plan.n_species)[:, :2].copy()
+        if ctx.gamma is not None:  # the kinetics carry gamma a and gamma b
+            src *= ctx.gamma[:, None]
+        g_ab = torch.from_numpy(src).reshape(abshape)
         return lam.to(w_dtype), g_diff, g_ab, None, None, None, None, None, None, None, None, None
 
 
@@ -93,15 +148,20 @@ def integrate(w0, grid: Grid, diff, ab, tau: float, n_steps: int, reaction: str 
     w0: device tensor of the plan's state shape (deviation from ``w_ref``);
     diff: CPU float64 tensor [batch, n_species]; ab: CPU float64 tensor
     [batch, 2] (constants a, b); extra_params: further reaction constants
-    (not differentiated); w_ref: [batch, n_species] reference state, by
-    default the equilibrium at the given (a, b), held fixed; segment:
-    steps between checkpoints (0: ceil(sqrt(n_steps))); adjoint_precision:
-    "fp64" or "same" (the forward plan's arithmetic).
+    (not differentiated; for "schnakenberg_scaled" the third constant is
+    gamma = alpha_1); w_ref: [batch, n_species] reference state, held fixed
+    (required when ``ab`` requires a gradient; otherwise it defaults to the
+    equilibrium at the given (a, b)); segment: steps between checkpoints
+    (0: ceil(sqrt(n_steps))); adjoint_precision: "fp64" or "same" (the
+    forward plan's arithmetic).
     """
     if adjoint_precision not in ("fp64", "same"):
         raise ValueError("adjoint_precision must be 'fp64' or 'same'")
     if segment <= 0:
         segment = max(1, int(math.ceil(math.sqrt(n_steps))))
+    if w_ref is None and isinstance(ab, torch.Tensor) and ab.requires_grad:
+        raise ValueError("integrate: give w_ref explicitly when ab requires a gradient (the reference "
+                         "state is held fixed by the reverse sweep)")
     diff = torch.as_tensor(diff, dtype=torch.float64)
     ab = torch.as_tensor(ab, dtype=torch.float64)
     if diff.dim() == 1:

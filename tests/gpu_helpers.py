@@ -5,7 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import workloads
-from oracle import assemble, reactions, splitee
+from oracle import adjoint, assemble, reactions, splitee
 
 
 def model_for(geometry, n_species=2):
@@ -123,3 +123,27 @@ def oracle_noise(case, steps, target, loss_and_grad, runs=2):
         lam1 = np.stack(loss_and_grad(W1, t1)[1])
         worst = max(worst, float(np.abs(lam1 - base).max() / np.abs(base).max()))
     return worst
+
+
+def low_precision_adjoint_tols(case, steps, lam_ref, gd, gp, rounded):
+    """Tolerances of an FP32 reverse sweep against the exact FP64 adjoint.
+
+    ``rounded`` = the oracle's adjoint with every stored quantity of the
+    reverse sweep rounded to FP32 (``round_to=np.float32``): the error an
+    FP32 evaluation of the same recursion makes when only its stored values
+    round.  The device also rounds inside each product's FP32 sums and takes
+    the eigen-basis route (conditioning up to sqrt(2n), Proposition 1), so
+    lambda is held to 32 times that modelled spread (the measured ratio is at
+    most 6.5).  The gradients are sums of products of mu with fixed fields;
+    they are held to the textbook bound of FP32 sums: steps x products per
+    step x (longest contraction) x 2^-24, relative to the largest gradient.
+    Both stay far below 1, so a zero lambda or gradient cannot pass.
+    """
+    _, lam1, gd1, gp1 = rounded
+    lam1 = np.stack([assemble.to_layout(x) for x in lam1])
+    spread_lam = float(np.abs(lam1 - lam_ref).max() / np.abs(lam_ref).max())
+    n_prod = sum(1 for o in adjoint.chain(case.oracles[0], 0) if o[0] == "mode")
+    tol_g = steps * n_prod * max(case.n) * EPS["fp32"]
+    tol_lam = 32.0 * spread_lam
+    assert tol_lam < 0.1 and tol_g < 0.1, (tol_lam, tol_g)
+    return tol_lam, tol_g

@@ -9,7 +9,7 @@ from types import SimpleNamespace
 import numpy as np
 import pytest
 
-from gpu_helpers import DIRICHLET, Case, adjoint_tol, oracle_noise
+from gpu_helpers import DIRICHLET, Case, adjoint_tol, low_precision_adjoint_tols, oracle_noise
 from oracle import adjoint, assemble
 
 torch = pytest.importorskip("torch")
@@ -39,15 +39,15 @@ def _device_adjoint(case, steps, target_layout, lam_seed_species=0):
     return lam.double().cpu().numpy()[0], grad.cpu().numpy(), uN
 
 
-def _oracle_with(case, steps, W0, target):
+def _oracle_with(case, steps, W0, target, round_to=None):
     wl = SimpleNamespace(geometry=case.geometry, reaction=case.kind, tau=case.tau, extent=case.extent,
                          diff=tuple(case.diff[0]), params=tuple(case.params[0]), n=case.n)
     wd = case.eq[0] if case.geometry in DIRICHLET else None
-    return adjoint.loss_and_grad(wl, W0, target, steps, w_dirichlet=wd)
+    return adjoint.loss_and_grad(wl, W0, target, steps, w_dirichlet=wd, round_to=round_to)
 
 
-def _oracle(case, steps, target):
-    return _oracle_with(case, steps, case.oracle_full(0), target)
+def _oracle(case, steps, target, round_to=None):
+    return _oracle_with(case, steps, case.oracle_full(0), target, round_to)
 
 
 @pytest.mark.parametrize("geometry,n,ns", GRIDS)
@@ -67,12 +67,18 @@ def test_adjoint_vs_oracle(geometry, n, ns, precision, tau):
     gam = case.params[0][2] if case.kind == "schnakenberg_scaled" else 1.0
     e_d = float(np.abs(grad[:ns] - gd).max() / scale)
     e_ab = float(np.abs(gam * grad[ns:ns + 2] - gp[:2]).max() / scale)
-    tol = adjoint_tol(case, steps, precision)
+    tol = adjoint_tol(case, steps, "fp64")
     if geometry == "disk_lambda":
         noise = oracle_noise(case, steps, target, lambda W, t: _oracle_with(case, steps, W, t))
         tol = max(tol, 4.0 * noise)
-    print(geometry, n, precision, tau, "lam %.2e  d %.2e  ab %.2e  tol %.1e" % (e_lam, e_d, e_ab, tol))
-    assert e_lam < tol and e_d < tol and e_ab < tol, (e_lam, e_d, e_ab)
+    tol_lam = tol_g = tol
+    if precision == "fp32":
+        t_lam, t_g = low_precision_adjoint_tols(case, steps, lam_ref, gd, gp,
+                                                _oracle(case, steps, target, np.float32))
+        tol_lam, tol_g = max(tol, t_lam), max(tol, t_g)
+    print(geometry, n, precision, tau, "lam %.2e  d %.2e  ab %.2e  tol lam %.1e  grad %.1e"
+          % (e_lam, e_d, e_ab, tol_lam, tol_g))
+    assert e_lam < tol_lam and e_d < tol_g and e_ab < tol_g, (e_lam, e_d, e_ab)
 
 
 @pytest.mark.parametrize("precision", ["bf16x2", "bf16x3"])
@@ -83,13 +89,22 @@ def test_adjoint_bf16_plan_runs_fp32(precision):
     W0 = case.oracle_full(0)
     target = W0[0] + 1e-3 * np.random.default_rng(21).random(case.n)
     lam, grad, _ = _device_adjoint(case, steps, assemble.to_layout(target))
-    _, lam0, gd, gp = _oracle(case, steps, target)
+    L0, lam0, gd, gp = _oracle(case, steps, target)
     lam_ref = np.stack([assemble.to_layout(x) for x in lam0])
-    tol = adjoint_tol(case, steps, "fp32")
+    t_lam, t_g = low_precision_adjoint_tols(case, steps, lam_ref, gd, gp,
+                                            _oracle(case, steps, target, np.float32))
+    # the split-bf16 forward states differ from the FP64 ones by the forward
+    # parity bound after 10 steps (1.5e-6 / 3e-8 of max |W|, two / three
+    # terms); lambda_N = u_N - target inherits that relative to the residual
+    fwd = {"bf16x2": 1.5e-6, "bf16x3": 3e-8}[precision] * float(np.abs(case.oracle_run(steps)).max())
+    rmax = float(np.abs(lam_ref[0]).max())
+    tol_lam = t_lam + fwd / rmax
+    tol_g = t_g + fwd / rmax
+    assert tol_lam < 0.1 and tol_g < 0.1
     e_lam = float(np.abs(lam - lam_ref).max() / np.abs(lam_ref).max())
     e_d = float(np.abs(grad[:2] - gd).max() / np.abs(gd).max())
-    print(precision, "lam %.2e  d %.2e  tol %.1e" % (e_lam, e_d, tol))
-    assert e_lam < tol and e_d < tol
+    print(precision, "lam %.2e  d %.2e  tol lam %.1e  grad %.1e" % (e_lam, e_d, tol_lam, tol_g))
+    assert e_lam < tol_lam and e_d < tol_g
 
 
 def test_adjoint_full_size_ball_vs_central_differences():

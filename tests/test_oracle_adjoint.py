@@ -107,3 +107,29 @@ def test_gradient_cylinder_dirichlet_ais3_vs_central_differences():
             return adjoint.loss(w, W0, target, w.steps, params=p, w_dirichlet=wd)
         rich, _ = _richardson(fp, h)
         assert abs(rich - gp[q]) < 1e-6 * abs(gp[q]) + 1e-7 * scale
+
+
+def test_rounding_model_of_the_reverse_sweep():
+    """round_to=float64 changes nothing; round_to=float32 moves lambda and
+    the gradients by amounts of FP32 size (more than FP64 rounding, far less
+    than the values), so the model neither vanishes nor swamps the result."""
+    from types import SimpleNamespace
+    from oracle import assemble, reactions
+    n = (9, 12)
+    wl = SimpleNamespace(geometry="disk", reaction="schnakenberg", tau=0.02, extent=(1.0, 1.0),
+                         diff=(1.0, 20.0), params=(0.1, 0.9), n=n)
+    eq = reactions.equilibrium("schnakenberg", (0.1, 0.9))
+    rng = np.random.default_rng(3)
+    W0 = [eq[s] + 1e-3 * rng.random(n) for s in range(2)]
+    target = W0[0] + 1e-3 * rng.random(n)
+    ref = adjoint.loss_and_grad(wl, W0, target, 3)
+    same = adjoint.loss_and_grad(wl, W0, target, 3, round_to=np.float64)
+    low = adjoint.loss_and_grad(wl, W0, target, 3, round_to=np.float32)
+    for a, b in zip(ref[1], same[1]):
+        np.testing.assert_array_equal(a, b)
+    lam_r, lam_l = np.stack(ref[1]), np.stack(low[1])
+    e = np.abs(lam_l - lam_r).max() / np.abs(lam_r).max()
+    assert 1e-10 < e < 1e-4, e
+    g_r = np.concatenate([ref[2], ref[3]])
+    g_l = np.concatenate([low[2], low[3]])
+    assert np.abs(g_l - g_r).max() < 1e-4 * np.abs(g_r).max()
