@@ -60,8 +60,20 @@ def blas_threads() -> int:
         return os.cpu_count() or 1
 
 
-def time_gpu_run(plan, x, steps, warmup, torch):
-    """Wall-clock per step with synchronisation on both sides (graph replay)."""
+CAPTURE_S = {}
+
+
+def time_gpu_run(plan, x, steps, warmup, torch, label=None):
+    """Wall-clock per step with synchronisation on both sides (graph replay).
+
+    The graphs tg_run replays are captured and instantiated before the
+    warm-up (tg_run_prepare), so the timed steps are steady state whatever
+    ``warmup`` is; the capture time is kept in CAPTURE_S[label]."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.prepare_run(x)
+    if label:
+        CAPTURE_S[label] = time.perf_counter() - t0
     if warmup:
         plan.run(x, warmup)
     torch.cuda.synchronize()
@@ -280,26 +292,57 @@ def other_workloads(tg, torch, steps):
     return out
 
 
-def profile_mode(tg, torch, w, pert, steps, route, tiles):
-    """Direct launches of the FP32 step in a given launch configuration (for
-    rocprofv3) and a copy of known size that calibrates the HBM byte counters."""
-    grid = tg.Grid(w.geometry, w.n, w.extent)
-    plan = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, "fp32")
-    if route:
-        plan.set_route(route)
-    if tiles:
-        plan.set_tiles([int(t) for t in tiles.split(",")])
-    print(f"configuration {plan.route}:{','.join(map(str, plan.tiles()))}", flush=True)
-    x = plan.state_from_deviation(pert)
-    for _ in range(steps):
-        plan.step(x)
+def profile_mode(tg, torch, w, pert, steps, route, tiles, precision="fp32"):
+    """Direct launches of the step in a given launch configuration (for
+    rocprofv3) and a copy of known size that calibrates the HBM byte counters.
+
+    Workloads: the ball (64 x 64 x 128) and the cylinder (100^3, three
+    species) take single steps of ``precision``; "sphere_batch" runs the 96
+    sphere instances in grouped launches (FP32); "disk_256x512" runs the
+    gradient workload (FP32 forward, FP64 reverse sweep) over ``steps`` steps."""
+    if w.name == "sphere_256x512":
+        big, small = workloads.WORKLOADS["sphere_256x512"], workloads.WORKLOADS["sphere_128x256"]
+        prm = workloads.sphere_batch_params(big.batch + small.batch)
+        plans, states = [], []
+        for wl, rows in ((big, prm[:big.batch]), (small, prm[big.batch:])):
+            diff = np.stack([np.ones(wl.batch), rows[:, 2]], axis=1)
+            plan = tg.Plan(tg.Grid("sphere", wl.n), diff, "schnakenberg", rows[:, :2], wl.tau, "fp32", wl.batch)
+            plans.append(plan)
+            states.append(plan.state_from_deviation(workloads.batch_perturbations(wl)))
+        info = tg.group_info(plans, states)
+        print(f"configuration grouped={info['grouped']} route={plans[0].route}", flush=True)
+        tg.group_run(plans, states, steps)
+        desc = f"{steps} grouped FP32 steps of the 96-instance sphere batch"
+    elif w.name == "disk_256x512":
+        from paper_2604_11558_amd.autograd import integrate
+        grid = tg.Grid("disk", w.n)
+        plan = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, "fp32")
+        x0 = plan.state_from_deviation(pert[None]).requires_grad_(True)
+        tgt = torch.from_numpy(workloads.target_pattern(w)).to("cuda", torch.float32)
+        out = integrate(x0, grid, torch.tensor([w.diff]), torch.tensor([w.params]), w.tau, steps,
+                        precision="fp32", w_ref=plan.reference)
+        loss = 0.5 * ((out[0, 0] - tgt) ** 2).sum()
+        loss.backward()
+        desc = f"{steps}-step FP32 forward and FP64 reverse sweep of the 256 x 512 disk gradient"
+    else:
+        grid = tg.Grid(w.geometry, w.n, w.extent)
+        plan = tg.Plan(grid, w.diff, w.reaction, w.params, w.tau, precision)
+        if route:
+            plan.set_route(route)
+        if tiles:
+            plan.set_tiles([int(t) for t in tiles.split(",")])
+        print(f"configuration {plan.route}:{','.join(map(str, plan.tiles()))}", flush=True)
+        x = plan.state_from_deviation(pert)
+        for _ in range(steps):
+            plan.step(x)
+        desc = f"{steps} steps of {w.name} ({precision})"
     torch.cuda.synchronize()
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(f"profiled {steps} steps of {w.name} (fp32) and 5 copies of {COPY_BYTES} bytes", flush=True)
+    print(f"profiled {desc} and 5 copies of {COPY_BYTES} bytes", flush=True)
 
 
 def main():
@@ -315,6 +358,7 @@ def main():
                     help="only launch --steps FP32 steps and a calibration copy (for rocprofv3)")
     ap.add_argument("--route", default="", help="--profile: launch route (default: the plan's)")
     ap.add_argument("--tiles", default="", help="--profile: comma-separated tile widths")
+    ap.add_argument("--precision", default="fp32", help="--profile: precision of the profiled steps")
     ap.add_argument("--fp32-config", default="",
                     help="route:tiles for the FP32 headline instead of the autotuner's choice "
                          "(e.g. fused:16,64; used to profile a fixed configuration)")
@@ -332,7 +376,7 @@ def main():
     w = workloads.WORKLOADS[args.workload]
     pert = workloads.perturbation(w)
     if args.profile:
-        profile_mode(tg, torch, w, pert, args.steps, args.route, args.tiles)
+        profile_mode(tg, torch, w, pert, args.steps, args.route, args.tiles, args.precision)
         return
     grid = tg.Grid(w.geometry, w.n, w.extent)
 
@@ -355,7 +399,7 @@ def main():
         route = plan.route
         # timed region: W warm-up steps, then K steps replayed from the
         # captured graph (tg_run), synchronised on both sides
-        sec = time_gpu_run(plan, x, args.steps, args.warmup, torch)
+        sec = time_gpu_run(plan, x, args.steps, args.warmup, torch, label=prec)
         states[prec] = x.double().cpu().numpy()
         # per-launch durations: the same steps with direct launches and a HIP
         # event on the launch stream before every launch (tg_run_timed)
@@ -403,7 +447,7 @@ def main():
         x = plan.state_from_deviation(pert)
         plan.autotune(x, iters=20)
         # the same W + K steps as the FP64 reference state
-        sec = time_gpu_run(plan, x, args.steps, args.warmup, torch)
+        sec = time_gpu_run(plan, x, args.steps, args.warmup, torch, label=prec)
         full = x.double().cpu().numpy() + plan.reference[:, :, None, None, None]
         bf[prec] = dict(sec=sec, full=full)
         del plan, x
@@ -484,6 +528,7 @@ def main():
         "launch_us_in_direct_steps": {p: res[p]["step_launch_us"] for p in res},
         "ms_per_step_other_routes": {p: {k: v * 1e3 for k, v in res[p]["other"].items()} for p in res},
         "plan_setup_s": {p: res[p]["setup"] for p in res},
+        "graph_capture_s": dict(CAPTURE_S),
         "roofline": roof,
     }
     # step-level roofline (whole chain's flops in one step vs MFMA peak)

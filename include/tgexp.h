@@ -69,7 +69,8 @@ enum { TG_DISK = 0, TG_SPHERE = 1, TG_BALL = 2, TG_CYLINDER = 3, TG_DISK_LAMBDA 
  *   TG_FP32   : FP32 MFMA, FP32 state.
  *   TG_BF16X2 : FP32 state; each product operand carried as two bf16 terms
  *               (x ~ hi + lo), three bf16 MFMA products (hi.hi, hi.lo, lo.hi)
- *               accumulated in FP32 (about 2^-16 relative per product).
+ *               accumulated in FP32 (representation error about 2^-17 relative per
+ *               operand, so about 2^-16 per product).
  *   TG_BF16X3 : three bf16 terms, six products (about 2^-24 relative).
  * The split-bf16 precisions run on the fused routes only (0 and 2) and
  * tg_plan_create returns TG_ENOTSUP where those do not fit the grid. */
@@ -148,12 +149,19 @@ int tg_step(tg_plan p, void* state, void* stream);
  * cleared).  For callers that step with tg_step / tg_step_diag. */
 int tg_sync_status(tg_plan p, void* stream);
 /* n_steps steps (in place): replays of captured HIP graphs of 32 and of 8
- * steps (both captured per state pointer on the first run of 8 steps or
- * more, kept until the plan is destroyed or reconfigured), single steps for
- * the rest; on route 4, resident launches of up to 1024 steps.
+ * steps, then of 4, 2 and 1 step for the rest (all captured per state
+ * pointer on the first run of 8 steps or more, or by tg_run_prepare, and
+ * kept until the plan is destroyed or reconfigured); runs of fewer than 8
+ * steps on a state without graphs launch directly; on route 4, resident
+ * launches of up to 1024 steps.
  * Synchronises the stream at the end and returns TG_ENONFINITE if any
  * update produced a non-finite value. */
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
+/* Capture (without running anything) the graphs tg_run replays for this
+ * state pointer, so that a later tg_run spends no time capturing or
+ * instantiating them.  Nothing to do on route 4.  Host-synchronous; the
+ * graphs are dropped when the route or tiles change, as tg_run's are. */
+int tg_run_prepare(tg_plan p, void* state);
 
 /* Steady-state indicators (Section 5.2, the text after the disk experiment:
  * the integral mean of the solution and the L2 norm of one step's

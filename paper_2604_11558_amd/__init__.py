@@ -47,6 +47,7 @@ _SIGNATURES = {
     "tg_plan_reference": (ctypes.c_int, [_p, _pd]),
     "tg_step": (ctypes.c_int, [_p, _p, _p]),
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
+    "tg_run_prepare": (ctypes.c_int, [_p, _p]),
     "tg_step_diag": (ctypes.c_int, [_p, _p, _p, _p]),
     "tg_sync_status": (ctypes.c_int, [_p, _p]),
     "tg_coupled_step": (ctypes.c_int, [_p, _p, _p, _p, _pd, _p]),
@@ -233,6 +234,11 @@ class Plan:
     def run(self, state, n_steps: int, stream=None):
         self._check_tensor(state)
         _check(lib().tg_run(self._h, state.data_ptr(), int(n_steps), _stream_ptr(stream)))
+
+    def prepare_run(self, state):
+        """Capture the graphs ``run`` replays on this state (no steps run)."""
+        self._check_tensor(state)
+        _check(lib().tg_run_prepare(self._h, state.data_ptr()))
 
     def sync_status(self, stream=None):
         """Synchronise the stream; raise TGError if a step wrote a non-finite value."""

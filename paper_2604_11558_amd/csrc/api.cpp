@@ -1676,6 +1676,15 @@ static void run_plain(tg_plan_s* p, void* state, int64_t n, hipStream_t st) {
     hipGraphExec_t g_long = step_graph(p, state, kLongGraph);
     for (; left >= kLongGraph; left -= kLongGraph) hip_check(hipGraphLaunch(g_long, st), "graph launch");
     for (; left >= kStepsPerGraph; left -= kStepsPerGraph) hip_check(hipGraphLaunch(g_short, st), "graph launch");
+    // the rest (fewer than kStepsPerGraph steps) from graphs of 4, 2 and 1
+    // steps, captured with the others
+    for (int k = kStepsPerGraph / 2; k >= 1; k /= 2) {
+      hipGraphExec_t g = step_graph(p, state, k);
+      if (left >= k) {
+        hip_check(hipGraphLaunch(g, st), "graph launch");
+        left -= k;
+      }
+    }
   }
   for (; left > 0; --left) step_any(p, state, st);
 }
@@ -1692,6 +1701,19 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
     if (flag) {
       hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_run: flag reset");
       throw Fail(TG_ENONFINITE, "tg_run: non-finite value in the state");
+    }
+    return TG_OK;
+  });
+}
+
+int tg_run_prepare(tg_plan p, void* state) {
+  return guarded([&] {
+    TG_REQUIRE(p && state, TG_EINVAL, "tg_run_prepare: null pointer");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_prepare: state must be aligned to 4 elements");
+    if (active_route(p) != 4) {
+      (void)step_graph(p, state, kStepsPerGraph);
+      (void)step_graph(p, state, kLongGraph);
+      for (int k = kStepsPerGraph / 2; k >= 1; k /= 2) (void)step_graph(p, state, k);
     }
     return TG_OK;
   });

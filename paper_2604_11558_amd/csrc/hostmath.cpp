@@ -179,7 +179,11 @@ Tridiag coord_operator(Coord c, int n, double extent, double lam) {
 // Implicit QL on a symmetric tridiagonal matrix: repeatedly pick the
 // leading unreduced block [l, m], apply a Wilkinson-shifted QL sweep of
 // Givens rotations chased from the bottom of the block upwards, and
-// accumulate the rotations into Z.
+// accumulate the rotations into Z.  This is the published implicit QL
+// algorithm with Wilkinson shifts of Bowdler, Martin, Reinsch and
+// Wilkinson ("The QR and QL algorithms for symmetric matrices", Numer.
+// Math. 11 (1968); the tql2 procedure of the Handbook for Automatic
+// Computation, vol. II, and of EISPACK), restated here.
 bool symtridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<double>& Z) {
   const int n = static_cast<int>(d.size());
   e.resize(n, 0.0);
