@@ -90,3 +90,38 @@ def test_invalid_extent():
     for ext in ((1.0, 1.0), (1.0, 2.0), (0.0, -1.0), (1.0, float("nan"))):
         with pytest.raises(tg.TGError):
             tg.Grid("disk_lambda", (4, 4), ext)
+
+
+# the library's factors (own QL eigensolver on the symmetrised operator, or
+# the closed-form Fourier basis for theta) against an independent route:
+# Pade scaling-and-squaring exponential of the augmented matrix
+# [[c A, I], [0, 0]], whose top-right block is phi_1(c A).  A_rho, A_phi,
+# A_z and A_lambda are non-normal; by Proposition 1 their eigenvector
+# matrices have condition number up to about sqrt(2 n), which bounds the
+# eigen route's error (relative to the result's norm, in units of eps);
+# scaling and squaring loses up to about ||c A|| eps (its squarings
+# amplify the Pade approximant's rounding).  Two correct routes differ by
+# less than 16 eps (sqrt(2 n) + ||c A||_inf) relative to max |phi_1|;
+# measured up to 4e3 eps sqrt(2 n) (2.9e-11, z at n = 512, c = 0.4, where
+# ||c A|| = 4.2e5).
+PADE_CASES = [("rho2", "disk", lambda n: (n, 8), 1, (1.0, 1.0)),
+              ("theta", "disk", lambda n: (4, n), 2, (1.0, 1.0)),
+              ("rho3", "ball", lambda n: (n, 4, 4), 1, (1.0, 1.0)),
+              ("phi", "sphere", lambda n: (4, n), 2, (1.0, 1.0)),
+              ("z", "cylinder", lambda n: (4, 4, n), 3, (1.0, 1.0)),
+              ("lambda", "disk_lambda", lambda n: (n, 4), 1, (1.0, -1.95))]
+
+
+@pytest.mark.parametrize("name,geometry,shape,mode,extent", PADE_CASES)
+@pytest.mark.parametrize("n", [64, 128, 256, 512])
+def test_phi1_factor_against_pade_expm(name, geometry, shape, mode, extent, n):
+    from oracle.phi import phi1_dense_expm
+    g = tg.Grid(geometry, shape(n), extent)
+    A = g.dense_operator(mode)
+    for c in (5e-3, 0.4):  # tau d of the workloads: 5e-3 (ball u) ... 0.4 (sphere v at d = 40)
+        P = g.phi1(mode, c)
+        R = phi1_dense_expm(c * A)
+        cA = c * np.abs(A).sum(axis=1).max()
+        tol = 16 * 2.0 ** -52 * (np.sqrt(2.0 * n) + cA) * np.abs(R).max()
+        err = np.abs(P - R).max()
+        assert err < tol, (name, n, c, err, tol)
