@@ -93,3 +93,108 @@ class BulkSurface:
         U1 = self.ball.step(U, lambda _: Gb)
         S1 = self.surface.step(S, lambda _: Gs)
         return U1, S1
+
+
+# ---------------------------------------------------------------------------
+# Bulk-surface DIB model on the cylinder (paper Section 5.6, eqs.
+# (bulkcylsys), (bulkcylnl)): u, v in a cylinder of radius rho_* and height
+# z_* with linear kinetics b(u) = -alpha1 (u - alpha2), c(v) = -beta1 (v -
+# beta2), Dirichlet data (alpha2, beta2) on the top disk, homogeneous Neumann
+# data on the lateral surface, and on the bottom disk Omega_B the flux
+# conditions grad u . n = -zeta1 alpha3 p(u, r, s), grad v . n = -zeta1 beta3
+# q(v, r, s); r, s diffuse on Omega_B (disk Laplacian, Neumann at its rim)
+# with kinetics zeta1 p(u, r, s), zeta1 q(v, r, s) (p, q of eq. (bulkcylnl)).
+#
+# The paper does not print the discretisation.  Reading taken here (as for
+# the ball, R20-style):
+#
+# * the disk's (rho, theta) grid is the cylinder's, so surface point (i, j)
+#   lies at the bottom of bulk column (i, j), on the bulk point (i, j, 1)
+#   with z_1 = 0;
+# * the flux enters the bulk's z = 0 row through the ghost point that makes
+#   A_z's Neumann row: with outward normal -e_z the condition reads
+#   du/dz(0) = zeta1 alpha3 p, and u_0 = u_2 - 2 h_z du/dz(0) adds
+#   -(2 / h_z) du/dz(0) to (A_z u)_1; the diffusion coefficient multiplies
+#   it (d_u = 1, d_v = delta), so F_u gains -(2 / h_z) zeta1 alpha3 p and
+#   F_v gains -delta (2 / h_z) zeta1 beta3 q on the layer z = 0;
+# * the coupling terms and all kinetics are evaluated at t_n and enter F;
+#   each domain then takes its plain split step (eq. (ee_cylinder) with the
+#   lifted Dirichlet data, eq. (ee_disk)).
+#
+# With the trapezoid weights h_z (1/2, 1, ..., 1) in z and the left null
+# vector of the disk operator in (rho, theta), the weighted sums satisfy
+# exactly  sum w_B F_u + alpha3 sum w_D F_r = sum w_D (u_D - u_n) / h_z
+# + sum w_B b(u)  (and delta beta3 for v, s): the exchange moves mass
+# between the bulk and the surface without creating any (pinned).
+
+DIB_CYL = dict(alpha1=1.0, alpha2=1.0, alpha3=0.1, beta1=1.0, beta2=1.0, beta3=0.1, delta=1.0,
+               epsilon=20.0, zeta1=1.0, zeta2=10.0, zeta3=1.0, zeta4=30.0, zeta5=0.5,
+               eta1=3.0, eta2=2.5, eta3=0.2, eta5=1.5)
+DIB_CYL["eta4"] = R.dib_eta4(DIB_CYL["zeta5"], DIB_CYL["eta1"], DIB_CYL["eta3"], DIB_CYL["beta2"])
+
+
+def dib_params(p=DIB_CYL):
+    """(zeta1, ..., zeta5, eta1, ..., eta5) in the order of reactions.dib."""
+    return tuple(p[k] for k in ("zeta1", "zeta2", "zeta3", "zeta4", "zeta5",
+                                "eta1", "eta2", "eta3", "eta4", "eta5"))
+
+
+def linear_params(p=DIB_CYL):
+    """(alpha1, alpha2, beta1, beta2) in the order of reactions.linear."""
+    return (p["alpha1"], p["alpha2"], p["beta1"], p["beta2"])
+
+
+def cylinder_equilibrium(p=DIB_CYL):
+    """(u_e, v_e), (r_e, s_e) = (alpha2, beta2), (0, zeta5)."""
+    return [p["alpha2"], p["beta2"]], [0.0, p["zeta5"]]
+
+
+class BulkSurfaceCylinder:
+    """Split exponential Euler for the Section 5.6 system: per time step one
+    cylinder split step for (u, v) and one disk split step for (r, s), with
+    every explicit term evaluated at t_n.
+
+    Fields are [i, j, k] (cylinder, k along z with z_1 = 0) and [i, j]
+    (bottom disk).  ``kinetics=False`` drops the bulk kinetics b, c (the
+    surface kinetics p, q are the exchange itself and stay).
+    """
+
+    def __init__(self, n, tau, extent=(15.0, 25.0), p=DIB_CYL, kinetics=True):
+        self.n, self.tau, self.p, self.kinetics = tuple(n), tau, dict(p), kinetics
+        self.extent = tuple(extent)
+        self.bulk = SplitEE("cylinder", self.n, [1.0, p["delta"]], tau, self.extent)
+        self.surface = SplitEE("disk", (self.n[0], self.n[1]), [1.0, p["epsilon"]], tau, (self.extent[0], 1.0))
+        self.hz = self.extent[1] / self.n[2]
+
+    def pq(self, U, S):
+        """p(u, r, s) and q(v, r, s) at the surface points (u, v on z = 0)."""
+        return R.dib_pq(U[0][:, :, 0], U[1][:, :, 0], S[0], S[1], *dib_params(self.p))
+
+    def reactions(self, U, S):
+        """Explicit terms of F: bulk kinetics plus the flux of the z = 0 row;
+        surface kinetics zeta1 (p, q)."""
+        p = self.p
+        pr, qs = self.pq(U, S)
+        if self.kinetics:
+            Gb = R.linear(U, *linear_params(p))
+        else:
+            Gb = [np.zeros_like(U[0]), np.zeros_like(U[1])]
+        Gb = [g.copy() for g in Gb]
+        Gb[0][:, :, 0] += -(2.0 / self.hz) * 1.0 * p["zeta1"] * p["alpha3"] * pr
+        Gb[1][:, :, 0] += -(2.0 / self.hz) * p["delta"] * p["zeta1"] * p["beta3"] * qs
+        Gs = [p["zeta1"] * pr, p["zeta1"] * qs]
+        return Gb, Gs
+
+    def F(self, U, S):
+        """The full right-hand sides d M W + g (with the lifted Dirichlet data)."""
+        Gb, Gs = self.reactions(U, S)
+        wd = [self.p["alpha2"], self.p["beta2"]]
+        Fb = [self.bulk.apply_M(U[s], s, wd[s]) + Gb[s] for s in range(2)]
+        Fs = [self.surface.apply_M(S[s], s) + Gs[s] for s in range(2)]
+        return Fb, Fs
+
+    def step(self, U, S):
+        Gb, Gs = self.reactions(U, S)
+        U1 = self.bulk.step(U, lambda _: Gb, w_dirichlet=[self.p["alpha2"], self.p["beta2"]])
+        S1 = self.surface.step(S, lambda _: Gs)
+        return U1, S1

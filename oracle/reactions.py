@@ -111,10 +111,78 @@ def ais3_jacobian(U, a, b, kappa, mu):
             [mu * one, 0.0 * one, -mu * one]]
 
 
+# --- DIB kinetics, eqs. (DIBnl) (Section 5.4) and (bulkcylnl) (Section 5.6) --
+# Surface species (r, s); p = (zeta1, zeta2, zeta3, zeta4, zeta5, eta1, eta2,
+# eta3, eta4, eta5).  g_r = zeta1 p(ub, r, s), g_s = zeta1 q(vb, r, s) with
+#   p(u, r, s) = zeta2 u (1 - s) r - zeta3 r^3 - zeta4 (s - zeta5),
+#   q(v, r, s) = eta1 v (1 + eta2 r)(1 - s)(1 - eta3 (1 - s))
+#                - eta4 (1 + eta5 r) s (1 + eta3 s),
+# where (ub, vb) are the bulk values below the surface point in the
+# bulk-surface model of Section 5.6 and 1 in the surface-only model of
+# Section 5.4 (whose p, q are the same with u = v = 1).
+
+def dib_pq(ub, vb, r, s, zeta1, zeta2, zeta3, zeta4, zeta5, eta1, eta2, eta3, eta4, eta5):
+    """(p, q) of eq. (bulkcylnl) (without the factor zeta1)."""
+    pr = zeta2 * ub * (1.0 - s) * r - zeta3 * r**3 - zeta4 * (s - zeta5)
+    qs = (eta1 * vb * (1.0 + eta2 * r) * (1.0 - s) * (1.0 - eta3 * (1.0 - s))
+          - eta4 * (1.0 + eta5 * r) * s * (1.0 + eta3 * s))
+    return pr, qs
+
+
+def dib(U, *p):
+    r, s = U
+    pr, qs = dib_pq(1.0, 1.0, r, s, *p)
+    return [p[0] * pr, p[0] * qs]
+
+
+def dib_eta4(zeta5, eta1, eta3, beta2=1.0):
+    """eta4 that makes (r, s) = (0, zeta5) an equilibrium when v = beta2
+    (the formula after eq. (DIBnl), with beta2 = 1, and the one of Section
+    5.6)."""
+    return beta2 * eta1 * (1.0 - zeta5) * (1.0 - eta3 + eta3 * zeta5) / (zeta5 * (1.0 + eta3 * zeta5))
+
+
+def dib_equilibrium(*p):
+    return [0.0, p[4]]
+
+
+def dib_jacobian(U, *p):
+    r, s = U
+    z1, z2, z3, z4, _, e1, e2, e3, e4, e5 = p
+    one = np.ones_like(r)
+    dp_dr = z2 * (1.0 - s) - 3.0 * z3 * r * r
+    dp_ds = -z2 * r - z4 * one
+    g = (1.0 - s) * (1.0 - e3 * (1.0 - s))  # d/ds of g: -(1 - e3 (1 - s)) + e3 (1 - s)
+    dq_dr = e1 * e2 * g - e4 * e5 * s * (1.0 + e3 * s)
+    dq_ds = (e1 * (1.0 + e2 * r) * (-(1.0 - e3 * (1.0 - s)) + e3 * (1.0 - s))
+             - e4 * (1.0 + e5 * r) * (1.0 + 2.0 * e3 * s))
+    return [[z1 * dp_dr, z1 * dp_ds], [z1 * dq_dr, z1 * dq_ds]]
+
+
+# --- linear relaxation kinetics, eq. (bulkcylnl): g_s = -k_s (w_s - c_s) -----
+# p = (k_0, c_0, k_1, c_1, ...): Section 5.6's b(u) = -alpha1 (u - alpha2),
+# c(v) = -beta1 (v - beta2) with p = (alpha1, alpha2, beta1, beta2).
+
+def linear(U, *p):
+    return [-p[2 * s] * (U[s] - p[2 * s + 1]) for s in range(len(U))]
+
+
+def linear_equilibrium(*p):
+    return [p[2 * s + 1] for s in range(len(p) // 2)]
+
+
+def linear_jacobian(U, *p):
+    ns = len(U)
+    one = np.ones_like(U[0])
+    return [[(-p[2 * r] * one if r == s else 0.0 * one) for s in range(ns)] for r in range(ns)]
+
+
 MODELS = {
     "schnakenberg": (schnakenberg, schnakenberg_equilibrium, schnakenberg_jacobian),
     "ais3": (ais3, ais3_equilibrium, ais3_jacobian),
     "schnakenberg_scaled": (schnakenberg_scaled, schnakenberg_scaled_equilibrium, schnakenberg_scaled_jacobian),
+    "dib": (dib, dib_equilibrium, dib_jacobian),
+    "linear": (linear, linear_equilibrium, linear_jacobian),
 }
 
 
