@@ -183,6 +183,18 @@ int tg_run_prepare(tg_plan p, void* state);
  * doubles per slab, kept by the plan; calls on one plan from different
  * streams must not overlap.  TG_ENOTSUP for a grouped run (not offered). */
 int tg_step_diag(tg_plan p, void* state, double* diag, void* stream);
+/* tg_step_diag for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same step
+ * and indicators, bit for bit, but the per-tile partial sums live in the
+ * library's static device scratch (16 MiB per GPU, held until the process
+ * ends) instead of a buffer the plan allocates, and the call allocates
+ * nothing.  Limit: 2 (n1 n2 n3 / 8 + 64) batch n_species doubles of
+ * partial sums must fit the 16 MiB (e.g. the 64 x 64 x 128 ball with two
+ * species needs 2.1 MB); larger plans get TG_EINVAL.  All calls on one GPU
+ * share the scratch: calls that overlap in time on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  Call with the
+ * plan's device current. */
+int tg_step_diag_noalloc(tg_plan p, void* state, double* diag, void* stream);
 /* n_steps steps; after steps every, 2 every, ... records the indicators of
  * that step into diag[r][batch][n_species][2] (device memory for
  * n_steps / every records; may be NULL when that is 0).  The steps between records replay captured

@@ -48,6 +48,7 @@ _SIGNATURES = {
     "tg_step": (ctypes.c_int, [_p, _p, _p]),
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
     "tg_run_prepare": (ctypes.c_int, [_p, _p]),
+    "tg_step_diag_noalloc": (ctypes.c_int, [_p, _p, _p, _p]),
     "tg_step_diag": (ctypes.c_int, [_p, _p, _p, _p]),
     "tg_sync_status": (ctypes.c_int, [_p, _p]),
     "tg_coupled_step": (ctypes.c_int, [_p, _p, _p, _p, _pd, _p]),
@@ -252,6 +253,17 @@ class Plan:
         out = torch.empty((self.batch, self.n_species, 2), dtype=torch.float64, device=state.device)
         _check(lib().tg_step_diag(self._h, state.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
         return out
+
+    def step_diag_noalloc(self, state, out, stream=None):
+        """``step_diag`` into a caller-given [batch, n_species, 2] float64 device
+        tensor, with the partial sums in the library's static scratch (the call
+        allocates nothing)."""
+        self._check_tensor(state)
+        import torch
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() \
+                or out.numel() != 2 * self.batch * self.n_species:
+            raise ValueError("out must be a contiguous cuda float64 tensor of 2 * batch * n_species entries")
+        _check(lib().tg_step_diag_noalloc(self._h, state.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
 
     def run_diag(self, state, n_steps: int, every: int = 1, stream=None):
         """``n_steps`` steps; the indicators of steps every, 2 every, ... as a

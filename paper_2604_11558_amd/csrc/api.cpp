@@ -1744,6 +1744,34 @@ int tg_step_diag(tg_plan p, void* state, double* diag, void* stream) {
   });
 }
 
+int tg_step_diag_noalloc(tg_plan p, void* state, double* diag, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state && diag, TG_EINVAL, "tg_step_diag_noalloc: null pointer");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_step_diag_noalloc: state must be aligned to 4 elements");
+    // the same partial-sum layout as tg_step_diag: cap slots of two doubles
+    // per slab, every slot a launch reads written by that launch (nothing
+    // has to start at zero)
+    const int64_t cap = p->npts / 8 + 64;
+    const int64_t need = 2 * cap * static_cast<int64_t>(p->nslab) * static_cast<int64_t>(sizeof(double));
+    TG_REQUIRE(need <= static_cast<int64_t>(tg::kStaticScratchBytes), TG_EINVAL,
+               "tg_step_diag_noalloc: the plan needs " + std::to_string(need) +
+                   " bytes of indicator partial sums, more than the static scratch of " +
+                   std::to_string(tg::kStaticScratchBytes) + " bytes (use tg_step_diag)");
+    void* part = nullptr;
+    hip_check(tg::static_scratch(&part), "tg_step_diag_noalloc: static scratch address");
+    tg::DiagArgs d{};
+    d.part = static_cast<double*>(part);
+    d.out = diag;
+    d.w1 = p->d_w1;
+    d.w23 = p->d_w23;
+    d.wref = p->d_wref;
+    d.wsum_inv = p->wsum_inv;
+    d.cap = static_cast<int>(cap);
+    step_any(p, state, static_cast<hipStream_t>(stream), &d);
+    return TG_OK;
+  });
+}
+
 int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* diag, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && state && n_steps >= 0 && every >= 1, TG_EINVAL, "tg_run_diag: bad argument");

@@ -6,8 +6,35 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
+#include <vector>
+
+// Static device scratch of the entry points that allocate nothing (partial
+// sums of the indicators).  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[tg::kStaticScratchBytes / sizeof(double)];
 
 namespace tg {
+
+hipError_t static_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;  // per device ordinal
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<size_t>(dev) >= addr.size()) addr.resize(static_cast<size_t>(dev) + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));

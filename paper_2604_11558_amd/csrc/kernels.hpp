@@ -33,6 +33,14 @@ struct DiagArgs {
 // Sum each slab's `tiles` partial pairs and write the indicators.
 hipError_t launch_diag_finish(const DiagArgs& d, int nslab, hipStream_t s);
 
+// The library's static device scratch (a file-scope array of
+// kStaticScratchBytes, one copy per GPU, held until the process ends), for
+// entry points that allocate nothing.  Returns the current device's address
+// of the array, resolved once per device (with that device current) and
+// cached.  Host code must use this address, never the array's name.
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+hipError_t static_scratch(void** out);
+
 // One mu-mode product over a batch of "slabs" (species x instances), as a
 // GEMM C = A * B per (slab, batch b):
 //   strided mode (mu >= 2):  A = factor L (M x K, row-major), B = X_b (K x N,
