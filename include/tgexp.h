@@ -85,8 +85,29 @@ enum { TG_FP64 = 0, TG_FP32 = 1, TG_BF16X2 = 2, TG_BF16X3 = 3 };
  *   TG_REACT_SCHNAKENBERG_SCALED: (a, b, gamma): gamma times the
  *       Schnakenberg terms (eqs. (schnaksys), (schnaknl): a = alpha_2,
  *       b = beta_1, gamma = alpha_1); same equilibrium.
- *   TG_REACT_NONE: g = 0 (pure diffusion). */
-enum { TG_REACT_NONE = 0, TG_REACT_SCHNAKENBERG = 1, TG_REACT_AIS3 = 2, TG_REACT_SCHNAKENBERG_SCALED = 3 };
+ *   TG_REACT_LINEAR: (k_0, c_0, k_1, c_1, ...), up to three species:
+ *       g_s = -k_s (w_s - c_s) (the bulk kinetics b, c of eq. (bulkcylnl),
+ *       Section 5.6, with (alpha1, alpha2, beta1, beta2)); equilibrium c_s.
+ *   TG_REACT_DIB: (zeta1, zeta2, zeta3, zeta4, zeta5, eta1, eta2, eta3,
+ *       eta4, eta5), two species (r, s): g_r = zeta1 p, g_s = zeta1 q with
+ *       p = zeta2 (1 - s) r - zeta3 r^3 - zeta4 (s - zeta5),
+ *       q = eta1 (1 + eta2 r)(1 - s)(1 - eta3 (1 - s))
+ *           - eta4 (1 + eta5 r) s (1 + eta3 s)
+ *       (eqs. (DIB), Section 5.4; in the bulk-surface step of Section 5.6
+ *       the factors u of p and v of q are the cylinder's values below the
+ *       point, eq. (bulkcylnl)); reference (0, zeta5).
+ *   TG_REACT_NONE: g = 0 (pure diffusion).
+ * Plans with TG_REACT_LINEAR or TG_REACT_DIB compute F in a stencil launch
+ * of their own (route 0 behaves as route 2, route 4 is not offered) and have
+ * no adjoint (TG_ENOTSUP). */
+enum {
+  TG_REACT_NONE = 0,
+  TG_REACT_SCHNAKENBERG = 1,
+  TG_REACT_AIS3 = 2,
+  TG_REACT_SCHNAKENBERG_SCALED = 3,
+  TG_REACT_LINEAR = 4,
+  TG_REACT_DIB = 5
+};
 
 /* tg_apply_operator selectors */
 enum { TG_APPLY_F = 0, TG_APPLY_DIFFUSION = 1, TG_APPLY_REACTION = 2 };
@@ -218,6 +239,21 @@ int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* 
  * exchange is evaluated at t_n with the kinetics; then each side takes its
  * own split step (route 0 plans run route 2 here: the exchange is added by
  * a separate stencil launch).  States: each plan's layout, in place.
+ *
+ * Bulk-surface DIB system on the cylinder (Section 5.6, eqs. (bulkcylsys),
+ * (bulkcylnl)): u, v in a cylinder (plan `bulk`: TG_CYLINDER, two species,
+ * d = (1, delta), TG_REACT_LINEAR with (alpha1, alpha2, beta1, beta2), its
+ * reference -- the Dirichlet data of the top disk -- (alpha2, beta2)) and
+ * r, s on its bottom disk (plan `surface`: TG_DISK with the cylinder's
+ * (n_rho, n_theta) and radius, d = (1, epsilon), TG_REACT_DIB with
+ * (zeta1, ..., zeta5, eta1, ..., eta5)), same batch and precision.
+ * coupling = {alpha3, beta3, -, -, -} (the last three are not read but must
+ * be finite).  The flux conditions du/dz = zeta1 alpha3 p(u, r, s),
+ * dv/dz = zeta1 beta3 q(v, r, s) at z = 0 enter A_z's Neumann row through
+ * its ghost point: on the layer z = 0, F_u -= (2 / h_z) zeta1 alpha3 p and
+ * F_v -= delta (2 / h_z) zeta1 beta3 q, h_z = z_* / n_z; the disk's DIB
+ * kinetics take the cylinder's z = 0 values u, v.  Evaluated at t_n, then
+ * one split step per domain, as above.
  * TG_EINVAL when the plans do not match as described. */
 int tg_coupled_step(tg_plan bulk, tg_plan surface, void* bulk_state, void* surface_state, const double* coupling,
                     void* stream);

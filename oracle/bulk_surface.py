@@ -198,3 +198,17 @@ class BulkSurfaceCylinder:
         U1 = self.bulk.step(U, lambda _: Gb, w_dirichlet=[self.p["alpha2"], self.p["beta2"]])
         S1 = self.surface.step(S, lambda _: Gs)
         return U1, S1
+
+    def step_deviation(self, dU, dS):
+        """The same step on the deviations from the equilibrium: the
+        equilibrium is a fixed point of the linear part (M takes constants
+        to zero, and the lifted Dirichlet value equals the bulk equilibrium),
+        so W_e + dW steps to W_e + (dW stepped with the kinetics evaluated
+        at W_e + dW and homogeneous Dirichlet data).  Stepping full values,
+        the FP64 rounding of M (W_e + dW) costs eps |W_e| ||tau d M||, which
+        the deviation form does not."""
+        ub, us = cylinder_equilibrium(self.p)
+        Gb, Gs = self.reactions([ub[s] + dU[s] for s in range(2)], [us[s] + dS[s] for s in range(2)])
+        dU1 = self.bulk.step(dU, lambda _: Gb, w_dirichlet=[0.0, 0.0])
+        dS1 = self.surface.step(dS, lambda _: Gs)
+        return dU1, dS1

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtgexp.so")
 
 GEOMETRY = {"disk": 0, "sphere": 1, "ball": 2, "cylinder": 3, "disk_lambda": 4}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16x3": 3}
-REACTION = {"none": 0, "schnakenberg": 1, "ais3": 2, "schnakenberg_scaled": 3}
+REACTION = {"none": 0, "schnakenberg": 1, "ais3": 2, "schnakenberg_scaled": 3, "linear": 4, "dib": 5}
 APPLY = {"F": 0, "diffusion": 1, "reaction": 2}
 NDIM = {"disk": 2, "sphere": 2, "ball": 3, "cylinder": 3, "disk_lambda": 2}
 ROUTES = {"fused": 0, "generic": 1, "fused_stencil_apart": 2, "per_slice": 3, "resident": 4}
@@ -367,13 +367,19 @@ def _group_args(plans, states):
 
 
 def _coupling(coupling):
-    c = np.ascontiguousarray(np.asarray(coupling, dtype=np.float64).reshape(5))
+    """The five coupling constants (fewer are padded with zeros)."""
+    c = np.zeros(5)
+    v = np.asarray(coupling, dtype=np.float64).ravel()
+    if v.size > 5:
+        raise ValueError("at most five coupling constants")
+    c[:v.size] = v
     return c, _dptr(c)
 
 
 def coupled_step(bulk, surface, bulk_state, surface_state, coupling, stream=None):
-    """One bulk-surface step (ball plan + sphere plan); coupling =
-    (zeta1, zeta2, zeta3, eta1, eta2)."""
+    """One bulk-surface step: a ball plan + sphere plan with coupling =
+    (zeta1, zeta2, zeta3, eta1, eta2) (Section 5.5), or a cylinder plan +
+    bottom-disk plan with coupling = (alpha3, beta3) (Section 5.6)."""
     bulk._check_tensor(bulk_state)
     surface._check_tensor(surface_state)
     c, cp = _coupling(coupling)

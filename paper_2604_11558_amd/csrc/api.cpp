@@ -246,6 +246,11 @@ std::vector<double> default_reference(int reaction, int ns, const double* rp) {
     w[0] = ue;
     w[1] = b / (ue * ue);
     w[2] = ue;
+  } else if (reaction == TG_REACT_LINEAR) {
+    for (int s = 0; s < ns; ++s) w[s] = rp[2 * s + 1];
+  } else if (reaction == TG_REACT_DIB) {
+    w[0] = 0.0;
+    w[1] = rp[4];
   }
   return w;
 }
@@ -266,6 +271,8 @@ std::vector<double> reaction_at(int reaction, int ns, const double* rp, const do
     g[1] = rp[1] - u2v;
     g[2] = rp[3] * (w[0] - w[2]);
   }
+  // TG_REACT_LINEAR and TG_REACT_DIB: the stencil launch evaluates the whole
+  // kinetics at w_ref + deviation, so no value at the reference is kept
   return g;
 }
 
@@ -1061,6 +1068,7 @@ void run_chain(const tg_plan_s* P, const void* in, void* out, bool final_update,
 // of every species of an instance fit in LDS together.
 bool resident_ok(const tg_plan_s* P) {
   if (bf16_terms(P->precision) || !P->fused_ok || P->fused.size() != 1 || P->grid.ndim != 2) return false;
+  if (P->reaction >= TG_REACT_LINEAR) return false;  // kinetics of the stencil launch only
   const tg::FusedOp& op = P->fused.front();
   if (op.kind != 0) return false;
   const tg::StridedArgs& a = op.sa;
@@ -1091,6 +1099,7 @@ bool use_fused(const tg_plan_s* P) {
 bool stencil_apart(const tg_plan_s* P) {
   const int r = active_route(P);
   if (r != 0) return r == 2;
+  if (P->reaction >= TG_REACT_LINEAR) return true;  // kinetics of the stencil launch only
   const auto& op = P->fused.front();
   return P->ns > 1 && op.kind == 0 && op.sa.stencil && op.sa.plane;
 }
@@ -1314,7 +1323,7 @@ hipGraphExec_t step_graph(tg_plan_s* P, void* state, int steps) {
 struct Coupled {
   tg_plan_s* bulk;
   tg_plan_s* surf;
-  double c[5];  // zeta1, zeta2, zeta3, eta1, eta2
+  double c[5];  // ball + sphere: zeta1, zeta2, zeta3, eta1, eta2; cylinder + disk: alpha3, beta3
 };
 
 template <typename T>
@@ -1324,15 +1333,22 @@ void coupled_impl(const Coupled& C, void* ub, void* us, hipStream_t st) {
   const int rb = active_route(B), rs = active_route(S);
   void* fb = !use_fused(B) ? B->scratch[0] : B->scratch[1];
   void* fs = !use_fused(S) ? S->scratch[0] : S->scratch[1];
-  const double h = B->grid.extent[0] / B->grid.n[0];
   tg::StencilArgs ab = stencil_args(B, ub, fb, TG_APPLY_F);
   tg::StencilArgs as = stencil_args(S, us, fs, TG_APPLY_F);
-  tg::CoupleArgs cb{1, us, S->d_wref, B->grid.n[0], (2.0 / h) * (1.0 + h / B->grid.extent[0]),
-                    C.c[0], C.c[1], C.c[2], C.c[3], C.c[4]};
-  tg::CoupleArgs cs = cb;
-  cs.kind = 2;
-  cs.other = ub;
-  cs.oref = B->d_wref;
+  tg::CoupleArgs cb{}, cs{};
+  if (B->grid.geometry == TG_CYLINDER) {  // Section 5.6: flux through the z = 0 row's ghost point
+    const double hz = B->grid.extent[1] / B->grid.n[2];
+    cb = tg::CoupleArgs{3, us, S->d_wref, 0, 2.0 / hz, C.c[0], C.c[1], 0.0, 0.0, 0.0, S->d_rparams};
+    cs = tg::CoupleArgs{4, ub, B->d_wref, B->grid.n[2], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, nullptr};
+  } else {  // Section 5.5: Robin terms through the ball's boundary row
+    const double h = B->grid.extent[0] / B->grid.n[0];
+    cb = tg::CoupleArgs{1, us, S->d_wref, B->grid.n[0], (2.0 / h) * (1.0 + h / B->grid.extent[0]),
+                        C.c[0], C.c[1], C.c[2], C.c[3], C.c[4], nullptr};
+    cs = cb;
+    cs.kind = 2;
+    cs.other = ub;
+    cs.oref = B->d_wref;
+  }
   ab.cp = cb;
   as.cp = cs;
   mark_launch(st);
@@ -1572,6 +1588,8 @@ int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* di
       case TG_REACT_SCHNAKENBERG: need_ns = 2; need_np = 2; break;
       case TG_REACT_AIS3: need_ns = 3; need_np = 4; break;
       case TG_REACT_SCHNAKENBERG_SCALED: need_ns = 2; need_np = 3; break;
+      case TG_REACT_LINEAR: need_ns = -1; need_np = 2 * n_species; break;
+      case TG_REACT_DIB: need_ns = 2; need_np = 10; break;
       default: throw Fail(TG_EINVAL, "tg_plan_create: unknown reaction");
     }
     TG_REQUIRE(n_species >= 1 && n_species <= 3, TG_EINVAL, "tg_plan_create: 1 to 3 species");
@@ -1593,15 +1611,19 @@ int tg_plan_create(tg_grid g, int32_t n_species, int32_t batch, const double* di
     P->state_elems = P->npts * P->nslab;
     P->diff.assign(diff, diff + P->nslab);
     for (double d : P->diff) TG_REQUIRE(std::isfinite(d) && d > 0.0, TG_EINVAL, "tg_plan_create: diffusion must be positive");
-    P->rparams.assign(static_cast<size_t>(batch) * 4, 0.0);
+    TG_REQUIRE(n_params <= tg::kRParams, TG_EINVAL, "tg_plan_create: too many reaction parameters");
+    TG_REQUIRE(reaction != TG_REACT_LINEAR || n_species <= 3, TG_EINVAL,
+               "tg_plan_create: linear kinetics take at most three species");
+    P->rparams.assign(static_cast<size_t>(batch) * tg::kRParams, 0.0);
     for (int b = 0; b < batch; ++b)
-      for (int q = 0; q < n_params && q < 4; ++q) P->rparams[b * 4 + q] = params[b * n_params + q];
+      for (int q = 0; q < n_params; ++q) P->rparams[b * tg::kRParams + q] = params[b * n_params + q];
+    for (double v : P->rparams) TG_REQUIRE(std::isfinite(v), TG_EINVAL, "tg_plan_create: non-finite reaction parameter");
     P->wref.resize(P->nslab);
     P->g0.resize(P->nslab);
     for (int b = 0; b < batch; ++b) {
       std::vector<double> w = w_ref ? std::vector<double>(w_ref + b * n_species, w_ref + (b + 1) * n_species)
-                                    : default_reference(reaction, n_species, &P->rparams[b * 4]);
-      auto g0 = reaction_at(reaction, n_species, &P->rparams[b * 4], w.data());
+                                    : default_reference(reaction, n_species, &P->rparams[b * tg::kRParams]);
+      auto g0 = reaction_at(reaction, n_species, &P->rparams[b * tg::kRParams], w.data());
       for (int s = 0; s < n_species; ++s) {
         P->wref[b * n_species + s] = w[s];
         P->g0[b * n_species + s] = g0[s];
@@ -1802,15 +1824,26 @@ int tg_run_diag(tg_plan p, void* state, int64_t n_steps, int32_t every, double* 
 
 static Coupled check_coupled(tg_plan bulk, tg_plan surface, void* ub, void* us, const double* coupling) {
   TG_REQUIRE(bulk && surface && ub && us && coupling, TG_EINVAL, "bulk-surface step: null pointer");
-  TG_REQUIRE(bulk->grid.geometry == TG_BALL && surface->grid.geometry == TG_SPHERE, TG_EINVAL,
-             "bulk-surface step: needs a ball plan and a sphere plan");
+  const bool ball = bulk->grid.geometry == TG_BALL && surface->grid.geometry == TG_SPHERE;
+  const bool cyl = bulk->grid.geometry == TG_CYLINDER && surface->grid.geometry == TG_DISK;
+  TG_REQUIRE(ball || cyl, TG_EINVAL,
+             "bulk-surface step: needs a ball plan and a sphere plan, or a cylinder plan and a disk plan");
   TG_REQUIRE(bulk->ns == 2 && surface->ns == 2, TG_EINVAL, "bulk-surface step: two species on each side");
   TG_REQUIRE(bulk->batch == surface->batch, TG_EINVAL, "bulk-surface step: batch sizes differ");
   TG_REQUIRE(bulk->precision == surface->precision, TG_EINVAL, "bulk-surface step: precisions differ");
-  TG_REQUIRE(bulk->grid.n[1] == surface->grid.n[0] && bulk->grid.n[2] == surface->grid.n[1], TG_EINVAL,
-             "bulk-surface step: the sphere grid must be the ball's (theta, phi) grid");
-  TG_REQUIRE(bulk->grid.extent[0] == surface->grid.extent[0], TG_EINVAL,
-             "bulk-surface step: the sphere's radius must be the ball's");
+  if (ball) {
+    TG_REQUIRE(bulk->grid.n[1] == surface->grid.n[0] && bulk->grid.n[2] == surface->grid.n[1], TG_EINVAL,
+               "bulk-surface step: the sphere grid must be the ball's (theta, phi) grid");
+    TG_REQUIRE(bulk->grid.extent[0] == surface->grid.extent[0], TG_EINVAL,
+               "bulk-surface step: the sphere's radius must be the ball's");
+  } else {
+    TG_REQUIRE(bulk->grid.n[0] == surface->grid.n[0] && bulk->grid.n[1] == surface->grid.n[1], TG_EINVAL,
+               "bulk-surface step: the disk grid must be the cylinder's (rho, theta) grid");
+    TG_REQUIRE(bulk->grid.extent[0] == surface->grid.extent[0], TG_EINVAL,
+               "bulk-surface step: the disk's radius must be the cylinder's");
+    TG_REQUIRE(surface->reaction == TG_REACT_DIB, TG_EINVAL,
+               "bulk-surface step: the bottom disk needs the DIB kinetics (their p, q are the exchange)");
+  }
   TG_REQUIRE(bulk != surface && ub != us, TG_EINVAL, "bulk-surface step: distinct plans and states");
   TG_REQUIRE(aligned(bulk, ub) && aligned(surface, us), TG_EINVAL,
              "bulk-surface step: states must be aligned to 4 elements");
@@ -1953,6 +1986,8 @@ int tg_adjoint_step(tg_plan p, const void* state_n, void* lambda, double* grad, 
   return guarded([&] {
     TG_REQUIRE(p && state_n && lambda && grad && state_n != lambda, TG_EINVAL, "tg_adjoint_step: bad pointers");
     TG_REQUIRE(aligned(p, state_n) && aligned(p, lambda), TG_EINVAL, "tg_adjoint_step: buffers must be aligned");
+    TG_REQUIRE(p->reaction <= TG_REACT_SCHNAKENBERG_SCALED, TG_ENOTSUP,
+               "tg_adjoint_step: no adjoint for the linear and DIB kinetics");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->precision == TG_FP64) adjoint_impl<double>(p, state_n, lambda, grad, st);
     else adjoint_impl<float>(p, state_n, lambda, grad, st);

@@ -270,6 +270,30 @@ __device__ __forceinline__ void exchange(const StencilArgs& a, int inst, int p, 
   const T* other = static_cast<const T*>(c.other);
   const double* wr = a.wref + inst * 2;
   const double* orf = c.oref + inst * 2;
+  if (c.kind == 3) {  // cylinder: the z = 0 layer takes the bottom disk's flux
+    const int64_t m = static_cast<int64_t>(a.n[0]) * a.n[1];  // points per z layer
+    if (p >= m) return;
+    const double* orp = c.orp + inst * kRParams;
+    const double r = orf[0] + static_cast<double>(other[(inst * 2) * m + p]);
+    const double s = orf[1] + static_cast<double>(other[(inst * 2 + 1) * m + p]);
+    double pp, qq;
+    dib_pq(orp, wr[0] + du, wr[1] + dv, r, s, pp, qq);
+    const double* dd = a.diff + inst * 2;
+    G0 -= c.kappa * dd[0] * orp[0] * c.z1 * pp;
+    G1 -= c.kappa * dd[1] * orp[0] * c.z2 * qq;
+    return;
+  }
+  if (c.kind == 4) {  // bottom disk: the DIB kinetics see the cylinder's z = 0 values
+    const int64_t nb = static_cast<int64_t>(c.on1) * npts;  // cylinder points per species
+    const double ub1 = (orf[0] - 1.0) + static_cast<double>(other[(inst * 2) * nb + p]);  // u - 1
+    const double vb1 = (orf[1] - 1.0) + static_cast<double>(other[(inst * 2 + 1) * nb + p]);
+    const double* rp = a.rparams + inst * kRParams;
+    const double r = wr[0] + du, s = wr[1] + dv;
+    // the plain DIB kinetics were evaluated with u = v = 1: add the difference
+    G0 += rp[0] * rp[1] * ub1 * (1.0 - s) * r;
+    G1 += rp[0] * rp[5] * vb1 * (1.0 + rp[6] * r) * (1.0 - s) * (1.0 - rp[7] * (1.0 - s));
+    return;
+  }
   if (c.kind == 1) {  // bulk: only the boundary layer exchanges
     const int n1 = a.n[0];
     if (i != n1 - 1) return;
@@ -312,7 +336,10 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
   double G[3] = {0, 0, 0};
-  if (a.what != 1 && a.reaction != 0) reaction3c(rc, w[0], w[1], w[2], G[0], G[1], G[2]);
+  if (a.what != 1 && a.reaction != 0) {
+    if (a.reaction >= 4) reaction_ext(a, inst, w[0], w[1], w[2], G[0], G[1], G[2]);
+    else reaction3c(rc, w[0], w[1], w[2], G[0], G[1], G[2]);
+  }
   if constexpr (NS == 2) {
     if (a.cp.kind != 0 && a.what != 1) exchange<T>(a, inst, p, i, npts, w[0], w[1], G[0], G[1]);
   }
@@ -431,13 +458,13 @@ __global__ __launch_bounds__(256) void adjoint_combine_kernel(AdjointArgs a) {
   double m[3] = {0, 0, 0}, jt[3] = {0, 0, 0};
   for (int q = 0; q < ns && q < 3; ++q) m[q] = static_cast<double>(mu[q * a.npts]);
   if (a.reaction == 1 || a.reaction == 3) {  // (gamma times) g_u = a - u + u^2 v,  g_v = b - u^2 v
-    const double gam = a.reaction == 3 ? a.rparams[inst * 4 + 2] : 1.0;
+    const double gam = a.reaction == 3 ? a.rparams[inst * kRParams + 2] : 1.0;
     const double u = wr[0] + static_cast<double>(st[0]);
     const double v = wr[1] + static_cast<double>(st[a.npts]);
     jt[0] = gam * ((-1.0 + 2.0 * u * v) * m[0] - 2.0 * u * v * m[1]);
     jt[1] = gam * (u * u * m[0] - u * u * m[1]);
   } else if (a.reaction == 2) {  // + kappa u w and mu (u - w) terms
-    const double* rp = a.rparams + inst * 4;
+    const double* rp = a.rparams + inst * kRParams;
     const double kap = rp[2], mup = rp[3];
     const double u = wr[0] + static_cast<double>(st[0]);
     const double v = wr[1] + static_cast<double>(st[a.npts]);

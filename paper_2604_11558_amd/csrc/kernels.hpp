@@ -83,12 +83,25 @@ hipError_t launch_mode_gemm(const GemmArgs& g, hipStream_t s);
 //     F_u += kappa z1 (z2 r - z3 u),   F_v += kappa z1 (e1 s - e2 v)
 //   surface point q:   F_r -= z1 (z2 r - z3 u_b),   F_s -= z1 (e1 s - e2 v_b)
 // with u_b, v_b the bulk values at (n_rho - 1, q).
+// Reaction constants per instance (stride of StencilArgs::rparams).
+constexpr int kRParams = 12;
+
+// Bulk-surface exchange, added to F by the stencil launch.
+//   kind 1 / 2: ball / its sphere (Section 5.5): Robin terms with kappa =
+//     (2 / h)(1 + h / rho_*) and (z1, z2, z3, e1, e2) = (zeta1, zeta2,
+//     zeta3, eta1, eta2); on1 = n_rho of the ball (sphere side).
+//   kind 3 / 4: cylinder / its bottom disk (Section 5.6): on the cylinder's
+//     z = 0 layer F_s -= kappa d_s zeta1 c_s (p, q)(u, v, r, s) with kappa =
+//     2 / h_z, (c_u, c_v) = (z1, z2) = (alpha3, beta3) and zeta1, p, q from
+//     the disk plan's DIB constants (orp); on the disk the DIB kinetics take
+//     the cylinder's z = 0 values (u, v) instead of 1; on1 = n_z (disk side).
 struct CoupleArgs {
-  int kind;               // 0 none, 1 bulk side, 2 surface side
+  int kind;               // 0 none, 1 ball, 2 sphere, 3 cylinder, 4 bottom disk
   const void* other;      // partner state (same element type) [batch][2][...]
   const double* oref;     // partner reference [batch][2]
-  int on1;                // n_rho of the bulk (surface side)
+  int on1;                // n_rho of the ball (kind 2), n_z of the cylinder (kind 4)
   double kappa, z1, z2, z3, e1, e2;
+  const double* orp;      // partner reaction constants [batch][kRParams] (kind 3)
 };
 
 // F = d_s * M W (+ G(W)) pointwise stencil over all modes, deviation form.

@@ -7,14 +7,50 @@
 
 namespace tg {
 
+// p(ub, r, s) and q(vb, r, s) of the DIB kinetics (eq. (bulkcylnl); with
+// ub = vb = 1 the surface-only model of eq. (DIBnl)); rp = (zeta1, ...,
+// zeta5, eta1, ..., eta5).
+__device__ __forceinline__ void dib_pq(const double* rp, double ub, double vb, double r, double s, double& p,
+                                       double& q) {
+  p = rp[1] * ub * (1.0 - s) * r - rp[2] * r * r * r - rp[3] * (s - rp[4]);
+  q = rp[5] * vb * (1.0 + rp[6] * r) * (1.0 - s) * (1.0 - rp[7] * (1.0 - s)) -
+      rp[8] * (1.0 + rp[9] * r) * s * (1.0 + rp[7] * s);
+}
+
+// Kinetics that only the stencil launch evaluates (plans with them compute
+// F in a launch of its own): linear relaxation g_s = -k_s (w_s - c_s),
+// constants (k_0, c_0, k_1, c_1, ...), and the DIB kinetics zeta1 (p, q) of
+// two surface species with the bulk values set to 1.
+__device__ __forceinline__ void reaction_ext(const StencilArgs& a, int inst, double d0, double d1, double d2,
+                                             double& G0, double& G1, double& G2) {
+  const int ns = a.nspecies;
+  const double* rp = a.rparams + inst * kRParams;
+  const double* wr = a.wref + inst * ns;
+  G0 = G1 = G2 = 0.0;
+  if (a.reaction == 4) {
+    G0 = -rp[0] * ((wr[0] - rp[1]) + d0);
+    if (ns > 1) G1 = -rp[2] * ((wr[1] - rp[3]) + d1);
+    if (ns > 2) G2 = -rp[4] * ((wr[2] - rp[5]) + d2);
+  } else if (a.reaction == 5) {
+    double p, q;
+    dib_pq(rp, 1.0, 1.0, wr[0] + d0, wr[1] + d1, p, q);
+    G0 = rp[0] * p;
+    G1 = rp[0] * q;
+  }
+}
+
 // The reaction terms of all species at a point, expanded around the
 // reference state w_ref so that no O(1) terms cancel: with deviations
 // (p, q, r) from (u_r, v_r, w_r),
 //   u^2 v - u_r^2 v_r = u_r^2 q + 2 u_r v_r p + 2 u_r p q + v_r p^2 + p^2 q.
 __device__ __forceinline__ void reaction3(const StencilArgs& a, int inst, double dp, double dq, double dr,
                                           double& G0, double& G1, double& G2) {
+  if (a.reaction >= 4) {
+    reaction_ext(a, inst, dp, dq, dr, G0, G1, G2);
+    return;
+  }
   const int ns = a.nspecies;
-  const double* rp = a.rparams + inst * 4;
+  const double* rp = a.rparams + inst * kRParams;
   const double* wr = a.wref + inst * ns;
   const double* g0 = a.g0 + inst * ns;
   const double ur = wr[0], vr = wr[1];
@@ -44,7 +80,7 @@ __device__ __forceinline__ ReactConst react_const(const StencilArgs& a, int inst
   ReactConst c;
   c.reaction = a.reaction;
   const int ns = a.nspecies;
-  const double* rp = a.rparams + inst * 4;
+  const double* rp = a.rparams + inst * kRParams;
   const double* wr = a.wref + inst * ns;
   const double* g0 = a.g0 + inst * ns;
   c.ur = wr[0];

@@ -149,3 +149,19 @@ def test_flux_row_against_an_explicit_ghost_layer():
         rt = disk.apply_M(u0, 0)
         np.testing.assert_allclose(Fb[s][:, :, 0], d * (zpart + rt), rtol=1e-12,
                                    atol=1e-12 * np.abs(d * zpart).max())
+
+
+def test_deviation_form_steps_the_same_map():
+    n = (8, 10, 7)
+    sys = BS.BulkSurfaceCylinder(n, 0.025)
+    ub, us = BS.cylinder_equilibrium()
+    rng = np.random.default_rng(11)
+    dU = [1e-2 * rng.random(n) for _ in range(2)]
+    dS = [1e-2 * rng.random(n[:2]) for _ in range(2)]
+    U = [ub[s] + dU[s] for s in range(2)]
+    S = [us[s] + dS[s] for s in range(2)]
+    for _ in range(5):
+        U, S = sys.step(U, S)
+        dU, dS = sys.step_deviation(dU, dS)
+    for a, d, v in zip(U + S, dU + dS, ub + us):
+        np.testing.assert_allclose(a, v + d, rtol=0, atol=1e-12)
