@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 METRIC = "dof-steps/s per GPU (FP32-MFMA vs FP64) at stated rel. error vs FP64 oracle"
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}  # dense MFMA FLOP/s, MI355X
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}  # dense MFMA FLOP/s, MI355X
 HBM_PEAK = 8.0e12
 KERNEL_SOURCES = ("fused.hip", "fused.hpp", "stencil_dev.hpp", "kernels.hpp", "phi_dev.hpp")
 COPY_BYTES = 256 << 20
@@ -118,6 +118,16 @@ def cpu_baseline(w, pert, budget_s):
     return w.dof / per_step, per_step, n, splitee.stack_layout(Ws)
 
 
+def step_roofline(flops, sec, peak, what, nbytes=None):
+    """Fraction of the MFMA peak (and of HBM, given the algorithmic bytes)
+    that one step's algorithmic work reaches in ``sec`` seconds."""
+    r = {"what": what, "flops": flops, "achieved_tflops": flops / sec / 1e12, "peak_tflops": peak / 1e12,
+         "frac": flops / sec / peak}
+    if nbytes is not None:
+        r.update({"bytes": nbytes, "achieved_gbs": nbytes / sec / 1e9, "hbm_frac": nbytes / sec / HBM_PEAK})
+    return r
+
+
 def kernel_sources_digest() -> str:
     """SHA-256 of the HIP sources the fused launches are built from."""
     import hashlib
@@ -149,23 +159,72 @@ def other_workloads(tg, torch, steps):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     dof = big.dof + small.dof
+    flops = sum(f for p in plans for _, f in p.chain())  # per step, both grids
     out["sphere_64x256x512_32x128x256_fp32_grouped"] = {
         "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
-        "launches_per_step": info["launches_per_step"], "grouped": info["grouped"], "route": plans[0].route}
+        "launches_per_step": info["launches_per_step"], "grouped": info["grouped"], "route": plans[0].route,
+        "roofline": step_roofline(flops, sec, PEAK["fp32"], "step: every grouped launch of one step")}
     del plans, states
     torch.cuda.empty_cache()
-    # 100^3 cylinder, 3 species, split-bf16
+    # 100^3 cylinder, 3 species: split-bf16 (the configured precision) with
+    # FP32 and plain FP64 beside it, each after the same W + K steps; the
+    # reduced precisions' deviation from FP64 against the scheme's own
+    # time-discretisation error (step doubling in FP64)
     wl = workloads.WORKLOADS["cylinder_100x100x100"]
     grid = tg.Grid(wl.geometry, wl.n, wl.extent)
-    for prec in ("bf16x2", "bf16x3"):
+    pert = workloads.perturbation(wl)[None]
+    cyl, full = {}, {}
+    for prec in ("fp64", "fp32", "bf16x2", "bf16x3"):
         plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, prec)
-        x = plan.state_from_deviation(workloads.perturbation(wl)[None])
+        x = plan.state_from_deviation(pert)
         plan.autotune(x, iters=10)
-        plan.run(x, 16)
-        sec = time_gpu_run(plan, x, steps, 0, torch)
-        out[f"cylinder_100x100x100_{prec}"] = {"value": wl.dof / sec, "unit": "dof-steps/s",
-                                               "ms_per_step": sec * 1e3, "dof": wl.dof}
+        x = plan.state_from_deviation(pert)
+        sec = time_gpu_run(plan, x, steps, 16, torch)
+        full[prec] = x.double().cpu().numpy() + plan.reference[:, :, None, None, None]
+        chain = plan.chain()
+        bufs = [plan.state_from_deviation(pert), torch.empty_like(x), torch.empty_like(x)]
+        op_t = [time_chain_op(plan, i, bufs[0] if i == 0 else bufs[1 + (i - 1) % 2], bufs[1 + i % 2], 50, torch)
+                for i in range(len(chain))]
+        del bufs
+        dom = int(np.argmax(op_t))
+        terms = {"bf16x2": 3, "bf16x3": 6}.get(prec, 1)  # MFMA products per algorithmic product
+        peak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"]}.get(prec, PEAK["bf16"])
+        ebytes = 8 if prec == "fp64" else 4
+        # one read of the launch's input and one write of its output (the
+        # update launch also reads the state)
+        nbytes = wl.dof * ebytes * (3 if dom == len(chain) - 1 else 2)
+        cyl[prec] = {"value": wl.dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": wl.dof,
+                     "route": plan.route, "tiles": plan.tiles(), "launch_us": [t * 1e6 for t in op_t],
+                     "roofline": {
+                         "kernel": f"launch {dom} (leading mode {chain[dom][0]})",
+                         "mfma": {"achieved": terms * chain[dom][1] / op_t[dom] / 1e12, "peak": peak / 1e12,
+                                  "unit": "TFLOP/s", "frac": terms * chain[dom][1] / op_t[dom] / peak,
+                                  "flops_per_launch": terms * chain[dom][1]},
+                         "hbm": {"achieved": nbytes / op_t[dom] / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                 "frac": nbytes / op_t[dom] / HBM_PEAK, "algorithmic_bytes_per_launch": nbytes},
+                         "avg_launch_us": op_t[dom] * 1e6},
+                     "step_roofline": step_roofline(terms * sum(f for _, f in chain), sec, peak,
+                                                    "step: every launch", 2 * wl.dof * ebytes)}
         del plan, x
+        torch.cuda.empty_cache()
+    half = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau / 2, "fp64")
+    xh = half.state_from_deviation(pert)
+    half.run(xh, 2 * (steps + 16))
+    ref = full["fp64"]
+    dev = np.abs(ref - half.reference[:, :, None, None, None]).max()
+    t_err = 2.0 * float(np.abs(ref - (xh.double().cpu().numpy() + half.reference[:, :, None, None, None])).max()
+                        / np.abs(ref).max())
+    del half, xh
+    for prec in ("fp32", "bf16x2", "bf16x3"):
+        e = float(np.abs(full[prec] - ref).max())
+        cyl[prec]["rel_err_vs_fp64"] = {"after_steps": steps + 16, "vs_max_state": e / np.abs(ref).max(),
+                                        "vs_max_deviation": e / dev}
+        cyl[prec]["equal_accuracy"] = bool(e / np.abs(ref).max() < t_err)
+        cyl[prec]["speedup_vs_fp64"] = cyl[prec]["value"] / cyl["fp64"]["value"]
+    for prec in cyl:
+        out[f"cylinder_100x100x100_{prec}"] = cyl[prec]
+    out["cylinder_100x100x100_time_discretisation_error"] = {
+        "after_steps": steps + 16, "vs_max_state": t_err, "method": "2 |W_tau - W_tau/2| / |W| (FP64)"}
     # steady-state indicators on the 64 x 64 x 128 ball, FP32 (fused into the
     # update launch plus one small summing launch per recorded step)
     wl = workloads.WORKLOADS["ball_64x64x128"]
@@ -207,6 +266,35 @@ def other_workloads(tg, torch, steps):
         out[f"ball_sphere_30x50x30_coupled_{prec}"] = {
             "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
             "paper_run_seconds_at_this_rate": bs["steps"] * sec}
+        del bulk, surf, xb, xs
+    # bulk-surface DIB system, cylinder 140 x 140 x 25 + bottom disk 140 x 140
+    # (Section 5.6): linear bulk kinetics (alpha1, alpha2, beta1, beta2) =
+    # (1, 1, 1, 1), delta = 1; DIB surface kinetics with zeta = (1, 10, 1,
+    # 30, 0.5), eta = (3, 2.5, 0.2, eta4, 1.5), epsilon = 20, and the
+    # coupling (alpha3, beta3) = (0.1, 0.1); eta4 is the value the paper
+    # prints as a formula, which makes (u, v, r, s) = (1, 1, 0, 0.5) an
+    # equilibrium
+    bc = workloads.BULK_SURFACE_CYLINDER
+    nc = bc["n"]
+    eta4 = 1.0 * 3.0 * (1.0 - 0.5) * (1.0 - 0.2 + 0.2 * 0.5) / (0.5 * (1.0 + 0.2 * 0.5))
+    dib = (1.0, 10.0, 1.0, 30.0, 0.5, 3.0, 2.5, 0.2, eta4, 1.5)
+    dbc, dsc = workloads.bulk_surface_cylinder_perturbations(nc, bc["seed"], bc["amplitude"])
+    for prec in ("fp64", "fp32"):
+        bulk = tg.Plan(tg.Grid("cylinder", nc, bc["extent"]), [(1.0, 1.0)], "linear", (1.0, 1.0, 1.0, 1.0),
+                       bc["tau"], prec)
+        surf = tg.Plan(tg.Grid("disk", nc[:2], (bc["extent"][0], 1.0)), [(1.0, 20.0)], "dib", dib, bc["tau"], prec)
+        xb = bulk.state_from_deviation(dbc[None])
+        xs = surf.state_from_deviation(dsc[None])
+        tg.coupled_run(bulk, surf, xb, xs, (0.1, 0.1), 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tg.coupled_run(bulk, surf, xb, xs, (0.1, 0.1), steps)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        dof = 2 * int(np.prod(nc)) + 2 * nc[0] * nc[1]
+        out[f"cylinder_disk_140x140x25_coupled_{prec}"] = {
+            "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
+            "routes": [bulk.route, surf.route], "paper_run_seconds_at_this_rate": bc["steps"] * sec}
         del bulk, surf, xb, xs
     # 32 x 64 disk, 100 steps of 1e-2 (a latency-bound 4096-dof problem):
     # autotuned, which picks the resident route (every step of a run in one
@@ -269,23 +357,40 @@ def other_workloads(tg, torch, steps):
     plan = tg.Plan(grid, wl.diff, wl.reaction, wl.params, wl.tau, "fp32")
     x0 = plan.state_from_deviation(workloads.perturbation(wl)[None])
     tgt = torch.from_numpy(workloads.target_pattern(wl)).to("cuda", torch.float32)
+    fwd_flops = sum(f for _, f in plan.chain())  # per step
     res = {}
-    for adj in ("fp64", "same"):
+
+    def grad_run(adj, n_steps):
         w0 = x0.clone().requires_grad_(True)
         diff = torch.tensor([wl.diff], dtype=torch.float64, requires_grad=True)
         ab = torch.tensor([wl.params], dtype=torch.float64, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outx = integrate(w0, grid, diff, ab, wl.tau, wl.steps, precision="fp32",
+        outx = integrate(w0, grid, diff, ab, wl.tau, n_steps, precision="fp32",
                          w_ref=plan.reference, adjoint_precision=adj)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss = 0.5 * ((outx[0, 0] - tgt) ** 2).sum()
         loss.backward()
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        res[adj] = {"forward_ms_per_step": (t1 - t0) * 1e3 / wl.steps,
-                    "gradient_ms_per_step": (t2 - t1) * 1e3 / wl.steps}
+        return t1 - t0, time.perf_counter() - t1, w0.grad
+
+    for adj in ("fp64", "same"):
+        t0 = time.perf_counter()
+        grad_run(adj, 20)  # builds and caches the plans, captures the graphs
+        setup = time.perf_counter() - t0
+        tf, tb, g = grad_run(adj, wl.steps)
+        g2 = grad_run(adj, wl.steps)[2]
+        # reverse sweep: the segment's forward recomputed (1x) and per step the
+        # adjoint's transposed chain plus its d-tangent chain (2x the
+        # forward's products) in the adjoint plan's arithmetic
+        res[adj] = {"forward_ms_per_step": tf * 1e3 / wl.steps, "gradient_ms_per_step": tb * 1e3 / wl.steps,
+                    "gradient_over_forward": tb / tf, "first_call_s": setup,
+                    "repeat_bitwise_equal": bool(torch.equal(g, g2)),
+                    "forward_roofline": step_roofline(fwd_flops, tf / wl.steps, PEAK["fp32"], "forward step"),
+                    "gradient_roofline": step_roofline(
+                        3 * fwd_flops, tb / wl.steps, PEAK["fp64" if adj == "fp64" else "fp32"],
+                        "reverse step (recompute + adjoint, 3x the forward's products)")}
     out["disk_256x512_gradient_400_steps"] = {
         "checkpoint_segment": int(math.ceil(math.sqrt(wl.steps))),
         "fp32_forward_fp64_adjoint": res["fp64"], "fp32_forward_fp32_adjoint": res["same"]}
@@ -512,8 +617,18 @@ def main():
         "split_bf16": {p: {"value": dof / bf[p]["sec"], "ms_per_step": bf[p]["sec"] * 1e3,
                            "after_steps": args.warmup + args.steps,
                            "rel_err_vs_fp64_after_steps": float(np.abs(bf[p]["full"] - ref64).max()
-                                                                / np.abs(ref64).max())}
+                                                                / np.abs(ref64).max()),
+                           "rel_err_vs_fp64_vs_max_deviation": float(np.abs(bf[p]["full"] - ref64).max()
+                                                                     / max(np.abs(dev64).max(), 1e-300))}
                        for p in bf},
+        # every speed-up over the plain FP64 step with its accuracy: the error
+        # against the FP64 trajectory relative to the largest deviation from
+        # the equilibrium (the part of the state the steps change)
+        "speedups_vs_fp64_at_accuracy": {
+            "fp32": {"speedup": v32 / v64, "rel_err_vs_max_deviation": err_32_64_dev},
+            **{p: {"speedup": dof / bf[p]["sec"] / v64,
+                   "rel_err_vs_max_deviation": float(np.abs(bf[p]["full"] - ref64).max()
+                                                     / max(np.abs(dev64).max(), 1e-300))} for p in bf}},
         "rel_err_fp32_vs_fp64": {"after_steps": args.warmup + args.steps, "vs_max_state": err_32_64,
                                  "vs_max_deviation": err_32_64_dev},
         "time_discretisation_error": {"after_steps": nsteps, "vs_max_state": t_err,
@@ -562,7 +677,7 @@ def main():
         got = x.double().cpu().numpy() + g32.reference[:, :, None, None, None]
         out["rel_err_fp32_vs_oracle"] = {"after_steps": n_cpu + 1,
                                          "vs_max_state": float(np.abs(got[0] - ws).max() / np.abs(ws).max())}
-    print(json.dumps(out))
+    print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
 
 
 if __name__ == "__main__":

@@ -118,6 +118,20 @@ def bulk_surface_perturbations(n: Tuple[int, int, int], seed: int, amplitude: fl
     return bulk, surf
 
 
+# Section 5.6: bulk-surface DIB model, cylinder (n_rho, n_theta, n_z) =
+# (140, 140, 25) of radius 15 and height 25 with its bottom disk (140, 140);
+# t_* = 250 in m = 10000 steps; the bulk starts at its equilibrium and the
+# surface species at theirs plus 1e-2 U(0, 1) per point.
+BULK_SURFACE_CYLINDER = dict(name="cylinder_disk_140x140x25", n=(140, 140, 25), extent=(15.0, 25.0),
+                             tau=0.025, steps=10000, seed=10, amplitude=1e-2)
+
+
+def bulk_surface_cylinder_perturbations(n: Tuple[int, int, int], seed: int, amplitude: float = 1e-2):
+    """(bulk [2][n3][n2][n1] zeros, surface [2][n2][n1] amplitude * U(0, 1))."""
+    rng = np.random.default_rng(seed)
+    return np.zeros((2, n[2], n[1], n[0])), amplitude * rng.random((2, n[1], n[0]))
+
+
 def scaled(w: Workload, n: Tuple[int, ...], steps: Optional[int] = None,
            name: Optional[str] = None) -> Workload:
     """Same physics on a different grid (used for small parity cases)."""
