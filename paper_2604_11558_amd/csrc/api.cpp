@@ -32,8 +32,13 @@ struct Fail : std::runtime_error {
   } while (0)
 
 void hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess)
-    throw Fail(TG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  if (e == hipSuccess) return;
+  // the runtime also keeps the error as the thread's last error, which the
+  // next launch's hipGetLastError would report again: read it off here
+  (void)hipGetLastError();
+  if (e == hipErrorOutOfMemory)
+    throw Fail(TG_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+  throw Fail(TG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
 template <typename F>
@@ -716,13 +721,15 @@ void build_plan(tg_plan_s* P) {
         if (lds > kLdsLimit) {
           plane = false;
         } else {
-          // whole planes that take two rounds of workgroups, the second
-          // less than half full, run slower than the split tail (sandwich
-          // launch, then the mode-1 launch): the 100^3 cylinder's 300
-          // planes of 135-139 KB (one per CU) on 256 CUs
+          // 3D grids: whole planes that take two rounds of workgroups, the
+          // second less than half full, run slower than the split tail
+          // (sandwich launch, then the mode-1 launch): the 100^3 cylinder's
+          // 300 planes of 135-139 KB (one per CU) on 256 CUs.  The disk
+          // (one plane per slab) keeps its plane launch at any batch: its
+          // resident route is built from it.
           const int64_t slots = std::max<int64_t>(1, static_cast<int64_t>(kLdsLimit / lds)) * num_cus;
           const int64_t wgs = static_cast<int64_t>(f.nb) * nslab;
-          if (wgs > slots && wgs - slots < slots / 2) plane = false;
+          if (f.nb > 1 && wgs > slots && wgs - slots < slots / 2) plane = false;
         }
       }
       if (!plane) {
@@ -1158,8 +1165,10 @@ void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg
 template <typename T>
 void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipStream_t st) {
   const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
-  if (!P->adj_ws) hip_check(hipMalloc(&P->adj_ws, 8 * bytes), "hipMalloc(adjoint workspace)");
+  const size_t pbytes = sizeof(double) * tg::kDotBlocks * static_cast<size_t>(P->nslab);
+  if (!P->adj_ws) hip_check(hipMalloc(&P->adj_ws, 8 * bytes + pbytes), "hipMalloc(adjoint workspace)");
   char* w = static_cast<char*>(P->adj_ws);
+  double* part = reinterpret_cast<double*>(w + 8 * bytes);  // dot-product partial sums
   void* F = w;
   void* DMW = w + bytes;
   void* xbuf[2] = {w + 2 * bytes, w + 3 * bytes};
@@ -1210,7 +1219,7 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   }
   TG_REQUIRE(t != nullptr, TG_EINVAL, "adjoint: chain without a d-dependent factor");
   // dL/dd_s += tau <lambda_s, (dS/dd) F_s>
-  hip_check(tg::launch_dot<T>(lam, t, npts, nslab, P->d_tau, grad, st), "adjoint dot");
+  hip_check(tg::launch_dot<T>(lam, t, npts, nslab, P->d_tau, grad, part, st), "adjoint dot");
 
   // mu = S^T lambda: transposed factors in reverse order; each Hadamard
   // factor moves to the product that precedes it in the reversed chain
@@ -1234,8 +1243,8 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
     yb ^= 1;
   }
   // dL/dd_s += (tau / d_s) <mu_s, d_s M W_s>;  dL/dc_s += tau sum mu_s
-  hip_check(tg::launch_dot<T>(MU, DMW, npts, nslab, P->d_taurd, grad, st), "adjoint dot");
-  hip_check(tg::launch_dot<T>(MU, nullptr, npts, nslab, P->d_tau, grad + nslab, st), "adjoint sum");
+  hip_check(tg::launch_dot<T>(MU, DMW, npts, nslab, P->d_taurd, grad, part, st), "adjoint dot");
+  hip_check(tg::launch_dot<T>(MU, nullptr, npts, nslab, P->d_tau, grad + nslab, part, st), "adjoint sum");
   // lambda += tau (d M^T mu + J^T mu)
   tg::StencilArgs a = stencil_args(P, MU, MTMU, TG_APPLY_DIFFUSION);
   a.coef = P->d_coefT;

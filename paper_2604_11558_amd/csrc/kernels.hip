@@ -408,10 +408,12 @@ hipError_t launch_diag_finish(const DiagArgs& d, int nslab, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-slab dot products (double accumulation, block reduction in LDS).
+// Per-slab dot products (double accumulation, block reduction in LDS): each
+// block stores its partial sum, and one finishing block per slab adds the
+// partials in a fixed order, so repeated runs give identical results.
 template <typename T>
 __global__ __launch_bounds__(256) void dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t npts,
-                                                  const double* scale, double* out) {
+                                                  double* part) {
   __shared__ double red[256];
   const int s = blockIdx.y;
   const T* as = a + static_cast<int64_t>(s) * npts;
@@ -426,21 +428,35 @@ __global__ __launch_bounds__(256) void dot_kernel(const T* __restrict__ a, const
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(out + s, red[0] * (scale ? scale[s] : 1.0));
+  if (threadIdx.x == 0) part[static_cast<int64_t>(s) * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(64) void dot_finish_kernel(const double* __restrict__ part, int blocks,
+                                                        const double* scale, double* out) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int i = 0; i < blocks; ++i) acc += part[static_cast<int64_t>(s) * blocks + i];
+  out[s] += acc * (scale ? scale[s] : 1.0);
 }
 
 template <typename T>
 hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
-                      hipStream_t s) {
-  if (npts <= 0 || nslab <= 0 || nslab > 65535) return hipErrorInvalidValue;
-  const int blocks = static_cast<int>(std::min<int64_t>((npts + 255) / 256, 64));
+                      double* part, hipStream_t s) {
+  if (npts <= 0 || nslab <= 0 || nslab > 65535 || !part) return hipErrorInvalidValue;
+  const int blocks = static_cast<int>(std::min<int64_t>((npts + 255) / 256, kDotBlocks));
   hipLaunchKernelGGL(dot_kernel<T>, dim3(blocks, nslab), dim3(256), 0, s, static_cast<const T*>(a),
-                     static_cast<const T*>(b), npts, scale, out);
+                     static_cast<const T*>(b), npts, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dot_finish_kernel, dim3(nslab), dim3(64), 0, s, part, blocks, scale, out);
   return hipGetLastError();
 }
 
-template hipError_t launch_dot<double>(const void*, const void*, int64_t, int, const double*, double*, hipStream_t);
-template hipError_t launch_dot<float>(const void*, const void*, int64_t, int, const double*, double*, hipStream_t);
+template hipError_t launch_dot<double>(const void*, const void*, int64_t, int, const double*, double*, double*,
+                                       hipStream_t);
+template hipError_t launch_dot<float>(const void*, const void*, int64_t, int, const double*, double*, double*,
+                                      hipStream_t);
 
 // lam_s += tau (mtmu_s + sum_r J[r][s] mu_r), J = dG/dW at W = w_ref + state.
 template <typename T>

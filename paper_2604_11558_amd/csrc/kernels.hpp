@@ -130,11 +130,12 @@ template <typename T>
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t s);
 
 // out[s] += scale[s] * sum_p a[s][p] * b[s][p] (b == nullptr: b = 1) over the
-// npts points of each of nslab slabs (double accumulation, one atomic add
-// per workgroup).
+// npts points of each of nslab slabs (double accumulation; per-block partial
+// sums in part[nslab][kDotBlocks], added in a fixed order, no atomics).
+constexpr int kDotBlocks = 64;
 template <typename T>
 hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
-                      hipStream_t s);
+                      double* part, hipStream_t s);
 
 // Adjoint combination per point, all species of an instance:
 //   lam_s += tau * (mtmu_s + sum_r dG_r/dw_s (W) mu_r)

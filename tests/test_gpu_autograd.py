@@ -115,3 +115,15 @@ def test_integrate_requires_reference_for_ab_gradient():
     ab = torch.tensor(case.params[:, :2], dtype=torch.float64, requires_grad=True)
     with pytest.raises(ValueError):
         integrate(w0, case.grid, torch.tensor(case.diff), ab, case.tau, 2)
+
+
+def test_gradients_are_bitwise_reproducible():
+    """The reverse sweep's sums use per-block partials added in a fixed
+    order: two identical runs give identical gradients."""
+    case = Case("disk", (37, 70), "fp32", tau=2e-2, seed=4)
+    target = case.full_from_device(case.device_state())[0, 0] + 1e-3 * np.random.default_rng(24).random(
+        tuple(reversed(case.n)))
+    a = _grads(case, 9, 3, target)
+    b = _grads(case, 9, 3, target)
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y)

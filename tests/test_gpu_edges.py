@@ -71,3 +71,19 @@ def test_misaligned_and_mismatched_buffers_are_refused():
         case.plan.step(x.float())       # wrong element type
     with pytest.raises(ValueError):
         case.plan.step(x[..., :-1].contiguous())  # wrong size
+
+
+def test_oversized_plan_reports_enomem_and_the_device_stays_usable():
+    """A plan whose scratch buffers exceed the device memory: 9000 instances
+    of two species on a 128^3 cylinder in FP64 need two state-sized buffers
+    of 302 GB each, more than the 288 GB of HBM; the first allocation fails
+    without touching memory.  TG_ENOMEM, and later plans work."""
+    g = tg.Grid("cylinder", (128, 128, 128))
+    B = 9000
+    with pytest.raises(tg.TGError) as err:
+        tg.Plan(g, np.tile([1.0, 20.0], (B, 1)), "schnakenberg", np.tile([0.1, 0.9], (B, 1)), 1e-2, "fp64", B)
+    assert err.value.code == -2, err.value
+    small = tg.Plan(tg.Grid("disk", (8, 12)), [(1.0, 20.0)], "schnakenberg", (0.1, 0.9), 1e-2, "fp64")
+    x = small.state_from_deviation(1e-3 * np.ones(small.state_shape))
+    small.run(x, 3)
+    assert torch.isfinite(x).all()

@@ -179,3 +179,21 @@ def test_group_run_with_a_resident_member():
     tg.group_run([disk.plan, sph.plan], states, 11)
     assert rel_err(disk.full_from_device(states[0]), disk.oracle_run(11)) < 1e-12
     assert rel_err(sph.full_from_device(states[1]), sph.oracle_run(11)) < 1e-12
+
+
+@pytest.mark.parametrize("precision,B", [("fp64", 600), ("fp32", 1000)])
+def test_resident_route_just_past_one_round_of_plane_workgroups(precision, B):
+    """Batches whose plane launch takes a little more than one round of
+    workgroups (FP64: 40 KB of LDS each, 4 per CU, 1024 on 256 CUs, so 600
+    instances of two species give 1200; FP32: 22 KB, 7 per CU, 1792, so 1000
+    give 2000) keep the plane launch, so the resident route stays offered."""
+    one = Case("disk", (32, 64), precision, tau=1e-2, seed=46)
+    plan = tg.Plan(one.grid, np.repeat(one.diff, B, axis=0), one.kind, np.repeat(one.params, B, axis=0),
+                   one.tau, precision, B)
+    plan.set_route("resident")
+    assert plan.route == "resident"
+    x = plan.state_from_deviation(np.repeat(one.pert, B, axis=0))
+    plan.run(x, 3)
+    dev = x.detach().double().cpu().numpy().reshape((B, 2, 64, 32))
+    got = dev[B - 1] + plan.reference[B - 1][:, None, None]
+    assert rel_err(got, one.oracle_run(3)[0]) < TOL[precision]
