@@ -28,8 +28,9 @@ lower-precision states (``adjoint_precision="fp64"``); ``"same"`` keeps
 the forward plan's arithmetic.
 
 Plans are built once per problem (grid, coefficients, constants, reference,
-tau, precision) and kept in a small cache, so repeated calls (an optimiser
-loop) spend no time on factor set-up.
+tau, precision), the forward plan autotuned on the first call's initial
+state, and kept in a small cache, so repeated calls (an optimiser loop)
+spend no time on set-up.
 """
 from __future__ import annotations
 
@@ -46,8 +47,9 @@ _PLAN_CACHE_SIZE = 4
 
 
 def cached_plan(grid: Grid, diff: np.ndarray, reaction: str, params: np.ndarray, tau: float,
-                precision: str, batch: int, w_ref) -> Plan:
-    """A plan for this problem, built on first use and then reused."""
+                precision: str, batch: int, w_ref, tune_state=None) -> Plan:
+    """A plan for this problem, built on first use (and autotuned on a copy
+    of ``tune_state`` if given) and then reused."""
     wr = None if w_ref is None else np.ascontiguousarray(
         np.broadcast_to(np.asarray(w_ref, dtype=np.float64), diff.shape))
     key = (id(grid), grid.geometry, grid.n, grid.extent, diff.tobytes(), diff.shape, reaction,
@@ -58,6 +60,8 @@ def cached_plan(grid: Grid, diff: np.ndarray, reaction: str, params: np.ndarray,
         _PLAN_CACHE.move_to_end(key)
         return plan
     plan = Plan(grid, diff, reaction, params, tau, precision, batch, w_ref=wr)
+    if tune_state is not None:
+        plan.autotune(tune_state.detach().to(plan.dtype).contiguous(), iters=10)
     _PLAN_CACHE[key] = plan
     while len(_PLAN_CACHE) > _PLAN_CACHE_SIZE:
         _PLAN_CACHE.popitem(last=False)
@@ -78,7 +82,7 @@ class SplitEEFunction(torch.autograd.Function):
             if extra_params is not None else ab_np
         diff_np = np.ascontiguousarray(diff.detach().cpu().numpy())
         params = np.ascontiguousarray(params)
-        plan = cached_plan(grid, diff_np, reaction, params, tau, precision, batch, w_ref)
+        plan = cached_plan(grid, diff_np, reaction, params, tau, precision, batch, w_ref, tune_state=w0)
         # steps run on one buffer per plan, so the graphs tg_run replays are
         # captured once for it rather than once per call
         x = getattr(plan, "_autograd_state", None)

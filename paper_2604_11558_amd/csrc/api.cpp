@@ -1187,28 +1187,31 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   const void* x = F;
   const void* t = nullptr;
   int xb = 0, tb = 0;
-  for (const auto& c : P->chain) {
+  const size_t nops = P->chain.size();
+  for (size_t o = 0; o < nops; ++o) {
+    const auto& c = P->chain[o];
+    const bool need_x = o + 1 < nops;  // S F itself is not needed, only its tangent
     void* xn = xbuf[xb];
     void* tn = tbuf[tb];
     bool t_written = false;
     if (c.epi == tg::EPI_PHI) {  // y = Phi o (L x): t' = Phi o (L t) + dPhi/dd o (L x)
       launch_op<T>(P, c, x, tn, tg::EPI_DPHI, st);
       if (t) launch_op<T>(P, c, t, tn, tg::EPI_PHI_ACC, st);
-      launch_op<T>(P, c, x, xn, tg::EPI_PHI, st);
+      if (need_x) launch_op<T>(P, c, x, xn, tg::EPI_PHI, st);
       t_written = true;
     } else if (c.dL) {  // y = L(d) x: t' = L t + (dL/dd) x
       tg::ChainOp cd = c;
       cd.L = c.dL;
       launch_op<T>(P, cd, x, tn, tg::EPI_STORE, st);
       if (t) launch_op<T>(P, c, t, tn, tg::EPI_UPDATE, st, 1.0);
-      launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
+      if (need_x) launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
       t_written = true;
     } else {
       if (t) {
         launch_op<T>(P, c, t, tn, tg::EPI_STORE, st);
         t_written = true;
       }
-      launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
+      if (need_x) launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
     }
     x = xn;
     xb ^= 1;

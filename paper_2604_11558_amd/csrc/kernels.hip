@@ -75,7 +75,9 @@ __device__ __forceinline__ float phi2_t(float x) {
 // Workgroup of 4 waves computes a TM x TN tile of C; each wave a
 // (TM/2) x (TN/2) quarter made of 16x16 MFMA blocks.  The K range is walked
 // in chunks of KC staged through LDS (k-major so MFMA operand reads are
-// unit-stride across lanes).
+// unit-stride across lanes); the global loads of the next chunk are issued
+// before the MFMAs of the current one, so their latency overlaps the
+// products instead of adding to every chunk.
 template <typename T, int TM, int TN, int KC>
 __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
   using acc_t = typename Mfma<T>::acc_t;
@@ -108,8 +110,8 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   const int li = lane & 15, lk = lane >> 4;
-  for (int k0 = 0; k0 < g.K; k0 += KC) {
-    T ra[LA], rb[LB];
+  T ra[LA], rb[LB];
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < LA; ++e) {
       const int idx = tid + 256 * e;
@@ -130,7 +132,10 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
         rb[e] = (gn < g.N && gk < g.K) ? B[gk * g.ldb + gn * bcol] : T(0);
       }
     }
-    __syncthreads();
+  };
+  gload(0);
+  for (int k0 = 0; k0 < g.K; k0 += KC) {
+    __syncthreads();  // the previous chunk's products have read the LDS tiles
 #pragma unroll
     for (int e = 0; e < LA; ++e) {
       const int idx = tid + 256 * e;
@@ -143,6 +148,7 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
       else sB[idx / TN][idx % TN] = rb[e];
     }
     __syncthreads();
+    if (k0 + KC < g.K) gload(k0 + KC);  // in flight during this chunk's MFMAs
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       T av[FM], bv[FN];
@@ -203,7 +209,7 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
 
 template <typename T, int TM, int TN>
 static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
-  constexpr int KC = 16;
+  constexpr int KC = 32;
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
   GemmArgs h = g;
   if (h.dg.part) {  // indicators: first-mode updates, one partial pair per tile
