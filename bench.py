@@ -36,9 +36,8 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11039420, "fused:1:16,64": 13307047,
-           "fused_stencil_apart:0:32,64": 9797249, "fused_stencil_apart:1:32,64": 13307041}
-TRAFFIC_DIGEST = "be775d454a1178643c8adc6ce4e0abf0ae8d750545b73a30a3a24a35cb41d4a0"
+TRAFFIC = {"fused:0:16,64": 11039431, "fused:1:16,64": 13307045}
+TRAFFIC_DIGEST = "46a0e781de4b3c9ac46b906e6eef182ba823b0587ace35b669c9a9d839c63a63"
 
 
 def cpu_model() -> str:
