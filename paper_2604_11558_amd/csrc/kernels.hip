@@ -72,26 +72,41 @@ __device__ __forceinline__ float phi2_t(float x) {
   return (expm1f(x) - x) / (x * x);
 }
 
-// Workgroup of 4 waves computes a TM x TN tile of C; each wave a
-// (TM/2) x (TN/2) quarter made of 16x16 MFMA blocks.  The K range is walked
-// in chunks of KC staged through LDS (k-major so MFMA operand reads are
-// unit-stride across lanes); the global loads of the next chunk are issued
-// before the MFMAs of the current one, so their latency overlaps the
-// products instead of adding to every chunk.
-template <typename T, int TM, int TN, int KC>
-__global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
+// Workgroup of 4 SK waves computes a TM x TN tile of C; wave w owns the
+// (TM/2) x (TN/2) quarter w % 4 of the tile, made of 16x16 MFMA blocks, over
+// every SK-th k-step starting at w / 4.  The K range is walked in chunks of
+// KC staged through LDS (k-major so MFMA operand reads are unit-stride
+// across lanes); the global loads of the next chunk are issued before the
+// MFMAs of the current one, so their latency overlaps the products instead
+// of adding to every chunk.  SK > 1 is for grids with few tiles: a single
+// wave per SIMD leaves every load, LDS and MFMA latency exposed, SK waves
+// per quarter hide them for one another.  Their partial quarters are summed
+// through LDS (over the staging tiles) in the fixed order 0, 1, ..., SK - 1,
+// so results are reproducible.
+template <typename T, int TM, int TN, int KC, int SK>
+__global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   using acc_t = typename Mfma<T>::acc_t;
+  constexpr int NT = 256 * SK;
   constexpr int WM = TM / 2, WN = TN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int LA = TM * KC / 256, LB = TN * KC / 256;
-  static_assert(LA >= 1 && LB >= 1, "tile too small for 256 threads");
-  __shared__ T sA[KC][TM + 4];
-  __shared__ T sB[KC][TN + 4];
+  constexpr int LA = TM * KC / NT, LB = TN * KC / NT;
+  static_assert(LA >= 1 && LB >= 1 && LA * NT == TM * KC && LB * NT == TN * KC, "tile does not fit the threads");
+  static_assert(KC % (4 * SK) == 0, "K chunk not a multiple of the k-step split");
+  __shared__ union {
+    struct {
+      T a[KC][TM + 4];
+      T b[KC][TN + 4];
+    } st;
+    acc_t red[SK > 1 ? SK - 1 : 1][4 * FM * FN][64];
+  } sm;
+  auto& sA = sm.st.a;
+  auto& sB = sm.st.b;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int quarter = SK > 1 ? wave & 3 : wave, kq = SK > 1 ? wave >> 2 : 0;
+  const int wm = quarter >> 1, wn = quarter & 1;
   const int tiles_n = (g.N + TN - 1) / TN;
   const int m0 = (blockIdx.x / tiles_n) * TM;
   const int n0 = (blockIdx.x % tiles_n) * TN;
@@ -111,46 +126,60 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
 
   const int li = lane & 15, lk = lane >> 4;
   T ra[LA], rb[LB];
-  auto gload = [&](int k0) {
+  // The split takes contiguous K ranges of Kq (a multiple of the k-step)
+  // per wave group, so each partial sums neighbouring terms in order as the
+  // unsplit product does (operands such as stencil differences cancel
+  // locally; interleaved partials would grow and then cancel).  Row c of a
+  // chunk's LDS tile holds k = (c / KCQ) Kq + t KCQ + c % KCQ of chunk t.
+  constexpr int KCQ = KC / SK;
+  const int Kq = SK == 1 ? g.K : (g.K + 4 * SK - 1) / (4 * SK) * 4;
+  auto kmap = [&](int t, int c, int& gk) {
+    const int kl = t * KCQ + c % KCQ;
+    gk = (c / KCQ) * Kq + kl;
+    return kl < Kq && gk < g.K;
+  };
+  auto gload = [&](int t) {
 #pragma unroll
     for (int e = 0; e < LA; ++e) {
-      const int idx = tid + 256 * e;
+      const int idx = tid + NT * e;
       const int r = idx / KC, c = idx % KC;
-      const int gm = m0 + r, gk = k0 + c;
-      ra[e] = (gm < g.M && gk < g.K) ? A[gm * g.lda + gk] : T(0);
+      const int gm = m0 + r;
+      int gk;
+      ra[e] = (kmap(t, c, gk) && gm < g.M) ? A[gm * g.lda + gk] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < LB; ++e) {
-      const int idx = tid + 256 * e;
+      const int idx = tid + NT * e;
+      int gk;
       if (g.b_kcontig) {
         const int nn = idx / KC, kk = idx % KC;
-        const int gn = n0 + nn, gk = k0 + kk;
-        rb[e] = (gn < g.N && gk < g.K) ? B[gn * g.ldb + gk] : T(0);
+        const int gn = n0 + nn;
+        rb[e] = (kmap(t, kk, gk) && gn < g.N) ? B[gn * g.ldb + gk] : T(0);
       } else {
         const int kk = idx / TN, nn = idx % TN;
-        const int gn = n0 + nn, gk = k0 + kk;
-        rb[e] = (gn < g.N && gk < g.K) ? B[gk * g.ldb + gn * bcol] : T(0);
+        const int gn = n0 + nn;
+        rb[e] = (kmap(t, kk, gk) && gn < g.N) ? B[gk * g.ldb + gn * bcol] : T(0);
       }
     }
   };
   gload(0);
-  for (int k0 = 0; k0 < g.K; k0 += KC) {
+  for (int t = 0; t * KCQ < Kq; ++t) {
     __syncthreads();  // the previous chunk's products have read the LDS tiles
 #pragma unroll
     for (int e = 0; e < LA; ++e) {
-      const int idx = tid + 256 * e;
+      const int idx = tid + NT * e;
       sA[idx % KC][idx / KC] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < LB; ++e) {
-      const int idx = tid + 256 * e;
+      const int idx = tid + NT * e;
       if (g.b_kcontig) sB[idx % KC][idx / KC] = rb[e];
       else sB[idx / TN][idx % TN] = rb[e];
     }
     __syncthreads();
-    if (k0 + KC < g.K) gload(k0 + KC);  // in flight during this chunk's MFMAs
+    if ((t + 1) * KCQ < Kq) gload(t + 1);  // in flight during this chunk's MFMAs
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
+    for (int kk = kq * KCQ; kk < (kq + 1) * KCQ; kk += 4) {
       T av[FM], bv[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) av[i] = sA[kk + lk][wm * WM + i * 16 + li];
@@ -160,6 +189,25 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
+    }
+  }
+  if constexpr (SK > 1) {
+    auto& red = sm.red;
+    __syncthreads();  // every wave is done with the staging tiles
+    if (kq > 0) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) red[kq - 1][(quarter * FM + i) * FN + j][lane] = acc[i][j];
+    }
+    __syncthreads();
+    if (kq == 0) {
+#pragma unroll
+      for (int p = 0; p < SK - 1; ++p)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = acc[i][j] + red[p][(quarter * FM + i) * FN + j][lane];
     }
   }
 
@@ -176,7 +224,7 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * WM + i * 16 + Mfma<T>::row(lk, r);
         const int col = n0 + wn * WN + j * 16 + li;
-        if (row < g.M && col < g.N) {
+        if ((SK == 1 || kq == 0) && row < g.M && col < g.N) {
           T v = acc[i][j][r];
           T* dst = C + static_cast<int64_t>(row) * g.ldc + col * ccol;
           if (g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC) {
@@ -203,13 +251,13 @@ __global__ __launch_bounds__(256) void mode_gemm_kernel(GemmArgs g) {
         }
       }
   if (diag)
-    diag_flush<4>(g.dg, ds0, ds1, static_cast<int64_t>(s) * g.dg.tiles + blockIdx.x,
-                  reinterpret_cast<double*>(&sA[0][0]));
+    diag_flush<4 * SK>(g.dg, ds0, ds1, static_cast<int64_t>(s) * g.dg.tiles + blockIdx.x,
+                  reinterpret_cast<double*>(&sm));
 }
 
-template <typename T, int TM, int TN>
-static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
-  constexpr int KC = 32;
+template <typename T, int TM, int TN, int SK>
+static hipError_t launch_tile_sk(const GemmArgs& g, hipStream_t s) {
+  constexpr int KC = SK > 2 ? 64 : 32;
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
   GemmArgs h = g;
   if (h.dg.part) {  // indicators: first-mode updates, one partial pair per tile
@@ -217,10 +265,42 @@ static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
     if (g.epi != EPI_UPDATE || !g.b_kcontig || g.nbatch != 1 || tiles > h.dg.cap) return hipErrorInvalidValue;
   }
   dim3 grid(tiles, g.nbatch, g.nslab);
-  hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC>), grid, dim3(256), 0, s, h);
+  hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK>), grid, dim3(256 * SK), 0, s, h);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !h.dg.part) return e;
   return launch_diag_finish(h.dg, g.nslab, s);
+}
+
+// LDS of one workgroup: the two staging tiles, or the partial quarters of
+// the split, whichever is larger.
+template <typename T, int TM, int TN, int SK>
+constexpr size_t gemm_lds() {
+  constexpr int KC = SK > 2 ? 64 : 32;
+  const size_t st = static_cast<size_t>(KC) * (TM + 4 + TN + 4) * sizeof(T);
+  const size_t red = static_cast<size_t>(SK - 1) * TM * TN * sizeof(T);
+  return st > red ? st : red;
+}
+
+// Waves per SIMD: SK = 4 while the tiles give at most one workgroup of
+// 4 waves per compute unit, SK = 2 while they give at most two, else 1
+// (each within 64 KB of LDS).
+template <typename T, int TM, int TN>
+static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  const int64_t wgs = static_cast<int64_t>((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN) * g.nbatch * g.nslab;
+  if constexpr (gemm_lds<T, TM, TN, 4>() <= 65536)
+    if (wgs <= cus) return launch_tile_sk<T, TM, TN, 4>(g, s);
+  if constexpr (gemm_lds<T, TM, TN, 2>() <= 65536)
+    if (wgs <= 2 * cus) return launch_tile_sk<T, TM, TN, 2>(g, s);
+  return launch_tile_sk<T, TM, TN, 1>(g, s);
 }
 
 template <typename T>
