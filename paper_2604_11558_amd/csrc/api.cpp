@@ -842,10 +842,11 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
 }
 
 template <typename T>
-void launch_stencil_stage(const tg_plan_s* P, const void* W, void* F, int what, hipStream_t st) {
+void launch_stencil_stage(const tg_plan_s* P, const void* W, void* F, int what, hipStream_t st, void* F2 = nullptr) {
   tg::StencilArgs a{};
   a.W = W;
   a.F = F;
+  a.F2 = F2;
   a.ndim = P->grid.ndim;
   a.n[0] = P->grid.n[0];
   a.n[1] = P->grid.n[1];
@@ -1165,10 +1166,17 @@ void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg
 template <typename T>
 void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipStream_t st) {
   const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
-  const size_t pbytes = sizeof(double) * tg::kDotBlocks * static_cast<size_t>(P->nslab);
-  if (!P->adj_ws) hip_check(hipMalloc(&P->adj_ws, 8 * bytes + pbytes), "hipMalloc(adjoint workspace)");
+  const size_t pbytes = sizeof(double) * 2 * tg::kDotBlocks * static_cast<size_t>(P->nslab);
+  const size_t cbytes = sizeof(unsigned) * static_cast<size_t>(P->nslab);
   char* w = static_cast<char*>(P->adj_ws);
+  if (!w) {
+    hip_check(hipMalloc(&P->adj_ws, 8 * bytes + pbytes + cbytes), "hipMalloc(adjoint workspace)");
+    w = static_cast<char*>(P->adj_ws);
+    // the dot products' finishing counters start at zero and are left there
+    hip_check(hipMemsetAsync(w + 8 * bytes + pbytes, 0, cbytes, st), "hipMemsetAsync(adjoint counters)");
+  }
   double* part = reinterpret_cast<double*>(w + 8 * bytes);  // dot-product partial sums
+  unsigned* count = reinterpret_cast<unsigned*>(w + 8 * bytes + pbytes);
   void* F = w;
   void* DMW = w + bytes;
   void* xbuf[2] = {w + 2 * bytes, w + 3 * bytes};
@@ -1178,9 +1186,8 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   const int nslab = P->nslab;
   const int64_t npts = P->npts;
 
-  // F = d M W + g(W) and d M W at step n
-  launch_stencil_stage<T>(P, state, F, TG_APPLY_F, st);
-  launch_stencil_stage<T>(P, state, DMW, TG_APPLY_DIFFUSION, st);
+  // F = d M W + g(W) and d M W at step n (one launch)
+  launch_stencil_stage<T>(P, state, F, 3, st, DMW);
 
   // tangent of the split action along d: t = (dS/dd) F, carried through the
   // chain next to x = partial products of S F
@@ -1222,7 +1229,8 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   }
   TG_REQUIRE(t != nullptr, TG_EINVAL, "adjoint: chain without a d-dependent factor");
   // dL/dd_s += tau <lambda_s, (dS/dd) F_s>
-  hip_check(tg::launch_dot<T>(lam, t, npts, nslab, P->d_tau, grad, part, st), "adjoint dot");
+  hip_check(tg::launch_dot<T>(lam, t, npts, nslab, P->d_tau, grad, nullptr, nullptr, part, count, st),
+            "adjoint dot");
 
   // mu = S^T lambda: transposed factors in reverse order; each Hadamard
   // factor moves to the product that precedes it in the reversed chain
@@ -1246,8 +1254,8 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
     yb ^= 1;
   }
   // dL/dd_s += (tau / d_s) <mu_s, d_s M W_s>;  dL/dc_s += tau sum mu_s
-  hip_check(tg::launch_dot<T>(MU, DMW, npts, nslab, P->d_taurd, grad, part, st), "adjoint dot");
-  hip_check(tg::launch_dot<T>(MU, nullptr, npts, nslab, P->d_tau, grad + nslab, part, st), "adjoint sum");
+  hip_check(tg::launch_dot<T>(MU, DMW, npts, nslab, P->d_taurd, grad, P->d_tau, grad + nslab, part, count, st),
+            "adjoint dot");
   // lambda += tau (d M^T mu + J^T mu)
   tg::StencilArgs a = stencil_args(P, MU, MTMU, TG_APPLY_DIFFUSION);
   a.coef = P->d_coefT;

@@ -429,9 +429,11 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   if constexpr (NS == 2) {
     if (a.cp.kind != 0 && a.what != 1) exchange<T>(a, inst, p, i, npts, w[0], w[1], G[0], G[1]);
   }
+  T* F2 = a.what == 3 ? static_cast<T*>(a.F2) + static_cast<int64_t>(inst) * NS * npts : nullptr;
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
     double f = a.what != 2 ? diffusion_fast<T, NDIM>(a, Wi + sp * npts, w[sp], sp, inst, p, i, j, k) : 0.0;
+    if (F2) F2[sp * npts + p] = static_cast<T>(f);
     if (a.what != 1) f += G[sp];
     F[sp * npts + p] = static_cast<T>(f);
   }
@@ -452,6 +454,7 @@ template <typename T>
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
   const int64_t npts = static_cast<int64_t>(a.n[0]) * a.n[1] * a.n[2];
   if (npts <= 0 || npts >= (int64_t(1) << 31) || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
+  if (a.what < 0 || a.what > 3 || (a.what == 3 && (!a.F2 || a.cp.kind != 0))) return hipErrorInvalidValue;
   dim3 grid(static_cast<unsigned>((npts + 255) / 256), a.batch);
   return a.ndim == 3 ? go_stencil<T, 3>(a, grid, s) : go_stencil<T, 2>(a, grid, s);
 }
@@ -495,54 +498,77 @@ hipError_t launch_diag_finish(const DiagArgs& d, int nslab, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Per-slab dot products (double accumulation, block reduction in LDS): each
-// block stores its partial sum, and one finishing block per slab adds the
-// partials in a fixed order, so repeated runs give identical results.
+// block stores its partial pair, and the last block of a slab to finish
+// adds the partials by a tree over the block index, so repeated runs give
+// identical results whatever the order the blocks ran in.
 template <typename T>
 __global__ __launch_bounds__(256) void dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t npts,
-                                                  double* part) {
-  __shared__ double red[256];
-  const int s = blockIdx.y;
+                                                  double* part, unsigned* count, const double* scale, double* out,
+                                                  const double* scale2, double* out2) {
+  __shared__ double red[2][256];
+  __shared__ int last;
+  const int s = blockIdx.y, t = threadIdx.x;
   const T* as = a + static_cast<int64_t>(s) * npts;
   const T* bs = b ? b + static_cast<int64_t>(s) * npts : nullptr;
-  double acc = 0.0;
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; p < npts;
-       p += static_cast<int64_t>(gridDim.x) * 256)
-    acc += static_cast<double>(as[p]) * (bs ? static_cast<double>(bs[p]) : 1.0);
-  red[threadIdx.x] = acc;
+  double acc = 0.0, sum = 0.0;
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + t; p < npts; p += static_cast<int64_t>(gridDim.x) * 256) {
+    const double av = static_cast<double>(as[p]);
+    acc += av * (bs ? static_cast<double>(bs[p]) : 1.0);
+    sum += av;
+  }
+  red[0][t] = acc;
+  red[1][t] = sum;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[static_cast<int64_t>(s) * gridDim.x + blockIdx.x] = red[0];
-}
-
-__global__ __launch_bounds__(64) void dot_finish_kernel(const double* __restrict__ part, int blocks,
-                                                        const double* scale, double* out) {
-  const int s = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double acc = 0.0;
-  for (int i = 0; i < blocks; ++i) acc += part[static_cast<int64_t>(s) * blocks + i];
-  out[s] += acc * (scale ? scale[s] : 1.0);
+  const int nb = gridDim.x;
+  double* ps = part + 2 * static_cast<int64_t>(s) * nb;
+  if (t == 0) {
+    ps[2 * blockIdx.x] = red[0][0];
+    ps[2 * blockIdx.x + 1] = red[1][0];
+    __threadfence();  // the partials are visible device-wide before the count
+    last = atomicAdd(&count[s], 1u) == static_cast<unsigned>(nb - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  // the last block: every partial pair loaded at once, then the same
+  // fixed-order tree over the block index
+  __threadfence();
+  red[0][t] = t < nb ? ps[2 * t] : 0.0;
+  red[1][t] = t < nb ? ps[2 * t + 1] : 0.0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  out[s] += red[0][0] * (scale ? scale[s] : 1.0);
+  if (out2) out2[s] += red[1][0] * (scale2 ? scale2[s] : 1.0);
+  count[s] = 0u;  // ready for the next launch
 }
 
 template <typename T>
 hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
-                      double* part, hipStream_t s) {
-  if (npts <= 0 || nslab <= 0 || nslab > 65535 || !part) return hipErrorInvalidValue;
+                      const double* scale2, double* out2, double* part, unsigned* count, hipStream_t s) {
+  if (npts <= 0 || nslab <= 0 || nslab > 65535 || !part || !count || !out) return hipErrorInvalidValue;
   const int blocks = static_cast<int>(std::min<int64_t>((npts + 255) / 256, kDotBlocks));
   hipLaunchKernelGGL(dot_kernel<T>, dim3(blocks, nslab), dim3(256), 0, s, static_cast<const T*>(a),
-                     static_cast<const T*>(b), npts, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dot_finish_kernel, dim3(nslab), dim3(64), 0, s, part, blocks, scale, out);
+                     static_cast<const T*>(b), npts, part, count, scale, out, scale2, out2);
   return hipGetLastError();
 }
 
-template hipError_t launch_dot<double>(const void*, const void*, int64_t, int, const double*, double*, double*,
-                                       hipStream_t);
-template hipError_t launch_dot<float>(const void*, const void*, int64_t, int, const double*, double*, double*,
-                                      hipStream_t);
+template hipError_t launch_dot<double>(const void*, const void*, int64_t, int, const double*, double*, const double*,
+                                       double*, double*, unsigned*, hipStream_t);
+template hipError_t launch_dot<float>(const void*, const void*, int64_t, int, const double*, double*, const double*,
+                                      double*, double*, unsigned*, hipStream_t);
 
 // lam_s += tau (mtmu_s + sum_r J[r][s] mu_r), J = dG/dW at W = w_ref + state.
 template <typename T>

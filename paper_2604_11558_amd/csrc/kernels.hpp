@@ -112,7 +112,8 @@ struct StencilArgs {
   int n[3];
   int nspecies;
   int batch;
-  int what;                 // 0: operator + reaction, 1: operator only, 2: reaction only
+  int what;                 // 0: operator + reaction, 1: operator only, 2: reaction only,
+                            // 3: operator + reaction into F and the operator alone into F2
   const double* coef;       // [3 modes][3][nmax]: lo, dg, up of each mode's operator
   const double* scale;      // [3 modes][3 coords][nmax]: per-coordinate scale factors
   int nmax;
@@ -124,18 +125,25 @@ struct StencilArgs {
   const double* wref;       // [batch][nspecies] reference state (deviation origin)
   const double* g0;         // [batch][nspecies] reaction at the reference state
   CoupleArgs cp;            // bulk-surface exchange (separate stencil launch only)
+  void* F2;                 // what == 3 only
 };
 
 template <typename T>
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t s);
 
 // out[s] += scale[s] * sum_p a[s][p] * b[s][p] (b == nullptr: b = 1) over the
-// npts points of each of nslab slabs (double accumulation; per-block partial
-// sums in part[nslab][kDotBlocks], added in a fixed order, no atomics).
-constexpr int kDotBlocks = 64;
+// npts points of each of nslab slabs, and, where out2 is given,
+// out2[s] += scale2[s] * sum_p a[s][p] (null scales: 1).  Double
+// accumulation; each block stores its partial pair in
+// part[nslab][kDotBlocks][2], and the block that finishes last in a slab
+// (counted in count[nslab], which must start at zero and is left at zero)
+// adds the partials by a fixed tree over the block index, so results do
+// not depend on timing.
+constexpr int kDotBlocks = 64;  // at most the block size (the finishing tree); each
+                                // block pays a device-scope release, so few
 template <typename T>
 hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
-                      double* part, hipStream_t s);
+                      const double* scale2, double* out2, double* part, unsigned* count, hipStream_t s);
 
 // Adjoint combination per point, all species of an instance:
 //   lam_s += tau * (mtmu_s + sum_r dG_r/dw_s (W) mu_r)
