@@ -36,8 +36,8 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11039431, "fused:1:16,64": 13307045}
-TRAFFIC_DIGEST = "46a0e781de4b3c9ac46b906e6eef182ba823b0587ace35b669c9a9d839c63a63"
+TRAFFIC = {"fused:0:16,64": 11039419, "fused:1:16,64": 13307046}
+TRAFFIC_DIGEST = "ce88c3487c40cc4c7d55d33b5ca51d18917730954ec104c44f40d0af9e7d7f03"
 
 
 def cpu_model() -> str:
