@@ -774,9 +774,18 @@ void build_plan(tg_plan_s* P) {
 }
 
 // Launch one chain op reading X and writing Y (or updating Y += tau * acc).
+// Fusions for the adjoint: Y2 also receives the same product through epi2;
+// with L2 and X2 the product runs over the concatenated contraction,
+// Y = L X + L2 X2 (L2 a factor of the same shape as c.L).
+struct OpExtra {
+  void* Y2 = nullptr;
+  int epi2 = tg::EPI_STORE;
+  const void* L2 = nullptr;
+  const void* X2 = nullptr;
+};
 template <typename T>
 void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y, int epi, hipStream_t st,
-               double alpha = -1.0, const tg::DiagArgs* dg = nullptr) {
+               double alpha = -1.0, const tg::DiagArgs* dg = nullptr, const OpExtra& ex = OpExtra{}) {
   const int nd = P->grid.ndim;
   const int nn[3] = {P->grid.n[0], P->grid.n[1], nd == 3 ? P->grid.n[2] : 1};
   int64_t na = 1, nb = 1;
@@ -797,6 +806,7 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
   const int64_t slab = P->npts;
   const int big = std::numeric_limits<int>::max();
   if (c.slice) {
+    TG_REQUIRE(!ex.Y2 && !ex.L2, TG_ENOTSUP, "product fusions need a per-mode op");
     // per slice i (grid y) and slab: C_i (nm x ncol) = P_i (nm x nm) X_i, where
     // X_i[k][n] = X[k sk + n sn + i]
     g.A = c.L; g.B = X; g.C = Y;
@@ -816,6 +826,7 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
   if (c.mode == 1) {
     // C (nb x nm) = X (nb x nm, K-contiguous) * L^T
     g.A = X; g.B = c.L; g.C = Y;
+    if (ex.L2) { g.A2 = ex.X2; g.B2 = ex.L2; }
     g.M = static_cast<int>(nb); g.N = nm; g.K = nm; g.nbatch = 1;
     g.lda = nm; g.ldb = nm; g.ldc = nm;
     g.a_sstride = slab; g.a_smod = big;
@@ -825,6 +836,7 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
   } else {
     // per b: C (nm x na) = L (nm x nm) * X_b (nm x na)
     g.A = c.L; g.B = X; g.C = Y;
+    if (ex.L2) { g.A2 = ex.L2; g.B2 = ex.X2; }
     g.M = nm; g.N = static_cast<int>(na); g.K = nm; g.nbatch = static_cast<int>(nb);
     g.lda = nm; g.ldb = na; g.ldc = na;
     g.a_bstride = 0; g.b_bstride = nm * na; g.c_bstride = nm * na;
@@ -837,6 +849,8 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
     TG_REQUIRE(c.mode == 1 && epi == tg::EPI_UPDATE, TG_ENOTSUP, "indicators need a first-mode update");
     g.dg = *dg;
   }
+  g.C2 = ex.Y2;
+  g.epi2 = ex.epi2;
   mark_launch(st);
   hip_check(tg::launch_mode_gemm<T>(g, st), "mode product launch");
 }
@@ -1202,15 +1216,24 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
     void* tn = tbuf[tb];
     bool t_written = false;
     if (c.epi == tg::EPI_PHI) {  // y = Phi o (L x): t' = Phi o (L t) + dPhi/dd o (L x)
-      launch_op<T>(P, c, x, tn, tg::EPI_DPHI, st);
+      // dPhi/dd o (L x) and, from the same product, y itself
+      OpExtra ex;
+      if (need_x) {
+        ex.Y2 = xn;
+        ex.epi2 = tg::EPI_PHI;
+      }
+      launch_op<T>(P, c, x, tn, tg::EPI_DPHI, st, -1.0, nullptr, ex);
       if (t) launch_op<T>(P, c, t, tn, tg::EPI_PHI_ACC, st);
-      if (need_x) launch_op<T>(P, c, x, xn, tg::EPI_PHI, st);
       t_written = true;
-    } else if (c.dL) {  // y = L(d) x: t' = L t + (dL/dd) x
+    } else if (c.dL) {  // y = L(d) x: t' = (dL/dd) x + L t, one contraction over both pairs
       tg::ChainOp cd = c;
       cd.L = c.dL;
-      launch_op<T>(P, cd, x, tn, tg::EPI_STORE, st);
-      if (t) launch_op<T>(P, c, t, tn, tg::EPI_UPDATE, st, 1.0);
+      OpExtra ex;
+      if (t) {
+        ex.L2 = c.L;
+        ex.X2 = t;
+      }
+      launch_op<T>(P, cd, x, tn, tg::EPI_STORE, st, -1.0, nullptr, ex);
       if (need_x) launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
       t_written = true;
     } else {

@@ -83,7 +83,9 @@ __device__ __forceinline__ float phi2_t(float x) {
 // per quarter hide them for one another.  Their partial quarters are summed
 // through LDS (over the staging tiles) in the fixed order 0, 1, ..., SK - 1,
 // so results are reproducible.
-template <typename T, int TM, int TN, int KC, int SK>
+//   FUSE = 0: plain product; 1: also C2 through epi2; 2: the contraction
+//   concatenated with A2 B2.
+template <typename T, int TM, int TN, int KC, int SK, int FUSE>
 __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   using acc_t = typename Mfma<T>::acc_t;
   constexpr int NT = 256 * SK;
@@ -116,6 +118,11 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   const T* B = static_cast<const T*>(g.B) + b * g.b_bstride +
                static_cast<int64_t>(s % g.b_smod) * g.b_sstride;
   T* C = static_cast<T*>(g.C) + b * g.c_bstride + static_cast<int64_t>(s) * g.c_sstride;
+  // second pair of the concatenated contraction (k >= K), same offsets
+  constexpr bool cat = FUSE == 2;
+  const T* A2 = cat ? static_cast<const T*>(g.A2) + (A - static_cast<const T*>(g.A)) : nullptr;
+  const T* B2 = cat ? static_cast<const T*>(g.B2) + (B - static_cast<const T*>(g.B)) : nullptr;
+  const int Kt = cat ? 2 * g.K : g.K;
   const int64_t bcol = g.b_ncol ? g.b_ncol : 1, ccol = g.c_ncol ? g.c_ncol : 1;
 
   acc_t acc[FM][FN];
@@ -132,65 +139,73 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   // locally; interleaved partials would grow and then cancel).  Row c of a
   // chunk's LDS tile holds k = (c / KCQ) Kq + t KCQ + c % KCQ of chunk t.
   constexpr int KCQ = KC / SK;
-  const int Kq = SK == 1 ? g.K : (g.K + 4 * SK - 1) / (4 * SK) * 4;
+  const int Kq = SK == 1 ? Kt : (Kt + 4 * SK - 1) / (4 * SK) * 4;
   auto kmap = [&](int t, int c, int& gk) {
     const int kl = t * KCQ + c % KCQ;
     gk = (c / KCQ) * Kq + kl;
-    return kl < Kq && gk < g.K;
+    return kl < Kq && gk < Kt;
   };
-  auto gload = [&](int t) {
+  {
+    auto gload = [&](int t) {
 #pragma unroll
-    for (int e = 0; e < LA; ++e) {
-      const int idx = tid + NT * e;
-      const int r = idx / KC, c = idx % KC;
-      const int gm = m0 + r;
-      int gk;
-      ra[e] = (kmap(t, c, gk) && gm < g.M) ? A[gm * g.lda + gk] : T(0);
-    }
+      for (int e = 0; e < LA; ++e) {
+        const int idx = tid + NT * e;
+        const int r = idx / KC, c = idx % KC;
+        const int gm = m0 + r;
+        int gk;
+        const bool ok = kmap(t, c, gk) && gm < g.M;
+        const bool hi = cat && gk >= g.K;
+        ra[e] = ok ? (hi ? A2 : A)[gm * g.lda + (hi ? gk - g.K : gk)] : T(0);
+      }
 #pragma unroll
-    for (int e = 0; e < LB; ++e) {
-      const int idx = tid + NT * e;
-      int gk;
-      if (g.b_kcontig) {
-        const int nn = idx / KC, kk = idx % KC;
-        const int gn = n0 + nn;
-        rb[e] = (kmap(t, kk, gk) && gn < g.N) ? B[gn * g.ldb + gk] : T(0);
-      } else {
-        const int kk = idx / TN, nn = idx % TN;
-        const int gn = n0 + nn;
-        rb[e] = (kmap(t, kk, gk) && gn < g.N) ? B[gk * g.ldb + gn * bcol] : T(0);
+      for (int e = 0; e < LB; ++e) {
+        const int idx = tid + NT * e;
+        int gk;
+        if (g.b_kcontig) {
+          const int nn = idx / KC, kk = idx % KC;
+          const int gn = n0 + nn;
+          const bool ok = kmap(t, kk, gk) && gn < g.N;
+          const bool hi = cat && gk >= g.K;
+          rb[e] = ok ? (hi ? B2 : B)[gn * g.ldb + (hi ? gk - g.K : gk)] : T(0);
+        } else {
+          const int kk = idx / TN, nn = idx % TN;
+          const int gn = n0 + nn;
+          const bool ok = kmap(t, kk, gk) && gn < g.N;
+          const bool hi = cat && gk >= g.K;
+          rb[e] = ok ? (hi ? B2 : B)[(hi ? gk - g.K : gk) * g.ldb + gn * bcol] : T(0);
+        }
+      }
+    };
+    gload(0);
+    for (int t = 0; t * KCQ < Kq; ++t) {
+      __syncthreads();  // the previous chunk's products have read the LDS tiles
+#pragma unroll
+      for (int e = 0; e < LA; ++e) {
+        const int idx = tid + NT * e;
+        sA[idx % KC][idx / KC] = ra[e];
+      }
+#pragma unroll
+      for (int e = 0; e < LB; ++e) {
+        const int idx = tid + NT * e;
+        if (g.b_kcontig) sB[idx % KC][idx / KC] = rb[e];
+        else sB[idx / TN][idx % TN] = rb[e];
+      }
+      __syncthreads();
+      if ((t + 1) * KCQ < Kq) gload(t + 1);  // in flight during this chunk's MFMAs
+#pragma unroll
+      for (int kk = kq * KCQ; kk < (kq + 1) * KCQ; kk += 4) {
+        T av[FM], bv[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) av[i] = sA[kk + lk][wm * WM + i * 16 + li];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bv[j] = sB[kk + lk][wn * WN + j * 16 + li];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
       }
     }
   };
-  gload(0);
-  for (int t = 0; t * KCQ < Kq; ++t) {
-    __syncthreads();  // the previous chunk's products have read the LDS tiles
-#pragma unroll
-    for (int e = 0; e < LA; ++e) {
-      const int idx = tid + NT * e;
-      sA[idx % KC][idx / KC] = ra[e];
-    }
-#pragma unroll
-    for (int e = 0; e < LB; ++e) {
-      const int idx = tid + NT * e;
-      if (g.b_kcontig) sB[idx % KC][idx / KC] = rb[e];
-      else sB[idx / TN][idx % TN] = rb[e];
-    }
-    __syncthreads();
-    if ((t + 1) * KCQ < Kq) gload(t + 1);  // in flight during this chunk's MFMAs
-#pragma unroll
-    for (int kk = kq * KCQ; kk < (kq + 1) * KCQ; kk += 4) {
-      T av[FM], bv[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) av[i] = sA[kk + lk][wm * WM + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) bv[j] = sB[kk + lk][wn * WN + j * 16 + li];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
-    }
-  }
   if constexpr (SK > 1) {
     auto& red = sm.red;
     __syncthreads();  // every wave is done with the staging tiles
@@ -211,7 +226,8 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
     }
   }
 
-  const bool phi_epi = g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC;
+  T* C2 = FUSE == 1 ? static_cast<T*>(g.C2) + (C - static_cast<T*>(g.C)) : nullptr;
+  const bool phi_epi = g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC || (FUSE == 1 && g.epi2 == EPI_PHI);
   const double cs = phi_epi ? g.cs[s] : 0.0;
   const double pbv = (phi_epi && g.pb) ? g.pb[b] : 1.0;
   const bool diag = g.dg.part != nullptr;  // EPI_UPDATE of a first-mode product
@@ -226,11 +242,16 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
         const int col = n0 + wn * WN + j * 16 + li;
         if ((SK == 1 || kq == 0) && row < g.M && col < g.N) {
           T v = acc[i][j][r];
-          T* dst = C + static_cast<int64_t>(row) * g.ldc + col * ccol;
-          if (g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC) {
-            double x = cs * pbv;
+          const int64_t off = static_cast<int64_t>(row) * g.ldc + col * ccol;
+          T* dst = C + off;
+          double x = 0.0;
+          if (phi_epi) {
+            x = cs * pbv;
             if (g.pm) x *= g.pm[row];
             if (g.pn) x *= g.pn[col];
+          }
+          if constexpr (FUSE == 1) C2[off] = g.epi2 == EPI_PHI ? v * phi1_t(static_cast<T>(x)) : v;
+          if (g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC) {
             const T xt = static_cast<T>(x);
             if (g.epi == EPI_PHI) {
               *dst = v * phi1_t(xt);
@@ -265,7 +286,9 @@ static hipError_t launch_tile_sk(const GemmArgs& g, hipStream_t s) {
     if (g.epi != EPI_UPDATE || !g.b_kcontig || g.nbatch != 1 || tiles > h.dg.cap) return hipErrorInvalidValue;
   }
   dim3 grid(tiles, g.nbatch, g.nslab);
-  hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK>), grid, dim3(256 * SK), 0, s, h);
+  if (g.A2) hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, 2>), grid, dim3(256 * SK), 0, s, h);
+  else if (g.C2) hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, 1>), grid, dim3(256 * SK), 0, s, h);
+  else hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, 0>), grid, dim3(256 * SK), 0, s, h);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !h.dg.part) return e;
   return launch_diag_finish(h.dg, g.nslab, s);
@@ -306,6 +329,8 @@ static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
 template <typename T>
 hipError_t launch_mode_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.nbatch <= 0 || g.nslab <= 0) return hipErrorInvalidValue;
+  if ((g.A2 != nullptr) != (g.B2 != nullptr) || (g.A2 && g.C2)) return hipErrorInvalidValue;
+  if (g.C2 && (g.dg.part || (g.epi2 != EPI_STORE && g.epi2 != EPI_PHI))) return hipErrorInvalidValue;
   if (g.nbatch > 65535 || g.nslab > 65535) return hipErrorInvalidValue;
   switch (g.tile) {
     case 1: return launch_tile<T, 32, 64>(g, s);
@@ -404,7 +429,8 @@ __device__ __forceinline__ void exchange(const StencilArgs& a, int inst, int p, 
 
 // Same computation with the mode count and species count fixed at compile
 // time: every neighbour load of every species is issued before use.
-template <typename T, int NDIM, int NS>
+// DUAL: also the operator part alone into F2 (what == 3).
+template <typename T, int NDIM, int NS, bool DUAL>
 __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
   const int npts = n1 * n2 * n3;
@@ -429,22 +455,21 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   if constexpr (NS == 2) {
     if (a.cp.kind != 0 && a.what != 1) exchange<T>(a, inst, p, i, npts, w[0], w[1], G[0], G[1]);
   }
-  T* F2 = a.what == 3 ? static_cast<T*>(a.F2) + static_cast<int64_t>(inst) * NS * npts : nullptr;
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
     double f = a.what != 2 ? diffusion_fast<T, NDIM>(a, Wi + sp * npts, w[sp], sp, inst, p, i, j, k) : 0.0;
-    if (F2) F2[sp * npts + p] = static_cast<T>(f);
+    if constexpr (DUAL) static_cast<T*>(a.F2)[static_cast<int64_t>(inst) * NS * npts + sp * npts + p] = static_cast<T>(f);
     if (a.what != 1) f += G[sp];
     F[sp * npts + p] = static_cast<T>(f);
   }
 }
 
-template <typename T, int NDIM>
+template <typename T, int NDIM, bool DUAL>
 static hipError_t go_stencil(const StencilArgs& a, dim3 grid, hipStream_t s) {
   switch (a.nspecies) {
-    case 1: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 1>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 2>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 3>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 1, DUAL>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 2, DUAL>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stencil_fast_kernel<T, NDIM, 3, DUAL>), grid, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -456,7 +481,8 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
   if (npts <= 0 || npts >= (int64_t(1) << 31) || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
   if (a.what < 0 || a.what > 3 || (a.what == 3 && (!a.F2 || a.cp.kind != 0))) return hipErrorInvalidValue;
   dim3 grid(static_cast<unsigned>((npts + 255) / 256), a.batch);
-  return a.ndim == 3 ? go_stencil<T, 3>(a, grid, s) : go_stencil<T, 2>(a, grid, s);
+  if (a.what == 3) return a.ndim == 3 ? go_stencil<T, 3, true>(a, grid, s) : go_stencil<T, 2, true>(a, grid, s);
+  return a.ndim == 3 ? go_stencil<T, 3, false>(a, grid, s) : go_stencil<T, 2, false>(a, grid, s);
 }
 
 template hipError_t launch_stencil<double>(const StencilArgs&, hipStream_t);

@@ -49,10 +49,18 @@ hipError_t static_scratch(void** out);
 //                            B(k, n) = L[n][k] (factor stored N x K), C = Y.
 // Epilogues: EPI_STORE C = acc; EPI_PHI C = acc * phi_1(cs[s] pm[m] pn[n] pb[b])
 // (any of pm/pn/pb may be null = 1); EPI_UPDATE C += alpha * acc.
+// Two fusions for the adjoint: with A2 and B2 set (same shapes, strides and
+// slab moduli as A and B) the contraction runs over both pairs,
+// acc = A B + A2 B2; with C2 set (B2 null) the same product is also written
+// to C2 through epilogue epi2 (EPI_STORE or EPI_PHI; no indicators).
 struct GemmArgs {
   const void* A;
   const void* B;
   void* C;
+  const void* A2;
+  const void* B2;
+  void* C2;
+  int epi2;
   int M, N, K;
   int nbatch;   // b range (strided mode); 1 otherwise
   int nslab;
