@@ -2,10 +2,13 @@
 
 ``integrate(...)`` runs ``n_steps`` split exponential Euler steps on the GPU
 and returns the final state; its backward pass applies ``tg_adjoint_step``
-in reverse with sqrt(T) checkpointing: the forward keeps one state every
-``segment`` steps, and the backward recomputes each segment from its
-checkpoint (storing that segment's states) before walking it in reverse,
-so memory is O(sqrt(T)) states and the forward is recomputed once.
+in reverse.  When the T states fit a memory budget (at most a quarter of
+the free device memory, and 8 GiB) the forward keeps every one of them and
+the reverse sweep recomputes nothing; otherwise it checkpoints: the forward
+keeps one state every ``segment`` steps (sqrt(T) by default), and the
+backward recomputes each segment from its checkpoint (storing that
+segment's states) before walking it in reverse, so memory is O(sqrt(T))
+states and the forward is recomputed once.
 
 Gradients are returned for the initial state (a deviation from the fixed
 reference state ``w_ref``), the diffusion coefficients ``diff``
@@ -72,6 +75,20 @@ def clear_plan_cache() -> None:
     _PLAN_CACHE.clear()
 
 
+_STORE_ALL_CAP = 8 << 30
+
+
+def checkpoint_segment(w0, n_steps: int) -> int:
+    """Steps between checkpoints: 1 (keep every state) when n_steps states
+    of w0's size fit min(8 GiB, a quarter of the free device memory), else
+    ceil(sqrt(n_steps))."""
+    need = int(n_steps) * w0.numel() * w0.element_size()
+    free, _ = torch.cuda.mem_get_info(w0.device)
+    if need <= min(_STORE_ALL_CAP, free // 4):
+        return 1
+    return max(1, int(math.ceil(math.sqrt(n_steps))))
+
+
 class SplitEEFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, w0, diff, ab, grid, reaction, extra_params, w_ref, tau, precision, n_steps, segment,
@@ -90,13 +107,18 @@ class SplitEEFunction(torch.autograd.Function):
             x = torch.empty(w0.shape, dtype=plan.dtype, device=w0.device)
             plan._autograd_state = x
         x.copy_(w0.detach())
-        ckpts = []
-        done = 0
-        while done < n_steps:
-            ckpts.append(x.clone())
-            k = min(segment, n_steps - done)
-            plan.run(x, k)
-            done += k
+        if segment == 1:  # every state, in one allocation
+            hist = torch.empty((n_steps,) + tuple(x.shape), dtype=x.dtype, device=x.device)
+            plan.run_history(x, n_steps, hist)
+            ckpts = list(hist.unbind(0))
+        else:
+            ckpts = []
+            done = 0
+            while done < n_steps:
+                ckpts.append(x.clone())
+                k = min(segment, n_steps - done)
+                plan.run(x, k)
+                done += k
         x = x.clone()
         ctx.plan = plan
         ctx.adj_plan = plan
@@ -124,6 +146,13 @@ class SplitEEFunction(torch.autograd.Function):
         for k in range(len(ckpts) - 1, -1, -1):
             start = k * ctx.segment
             length = min(ctx.segment, ctx.n_steps - start)
+            if length == 1:  # a stored state: nothing to recompute
+                st = ckpts[k]
+                if conv is not None:
+                    conv.copy_(st)
+                    st = conv
+                adj.adjoint_step(st, lam, grad)
+                continue
             seg_states[0].copy_(ckpts[k])
             for i in range(1, length):
                 seg_states[i].copy_(seg_states[i - 1])
@@ -156,13 +185,14 @@ def integrate(w0, grid: Grid, diff, ab, tau: float, n_steps: int, reaction: str 
     gamma = alpha_1); w_ref: [batch, n_species] reference state, held fixed
     (required when ``ab`` requires a gradient; otherwise it defaults to the
     equilibrium at the given (a, b)); segment: steps between checkpoints
-    (0: ceil(sqrt(n_steps))); adjoint_precision: "fp64" or "same" (the
-    forward plan's arithmetic).
+    (1: every state kept, no recompute; 0: 1 when the n_steps states fit the
+    memory budget, else ceil(sqrt(n_steps))); adjoint_precision: "fp64" or
+    "same" (the forward plan's arithmetic).
     """
     if adjoint_precision not in ("fp64", "same"):
         raise ValueError("adjoint_precision must be 'fp64' or 'same'")
     if segment <= 0:
-        segment = max(1, int(math.ceil(math.sqrt(n_steps))))
+        segment = checkpoint_segment(w0, n_steps)
     if w_ref is None and isinstance(ab, torch.Tensor) and ab.requires_grad:
         raise ValueError("integrate: give w_ref explicitly when ab requires a gradient (the reference "
                          "state is held fixed by the reverse sweep)")

@@ -1771,6 +1771,33 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
   });
 }
 
+int tg_run_history(tg_plan p, void* state, int64_t n_steps, void* history, void* stream) {
+  return guarded([&] {
+    TG_REQUIRE(p && state && history && n_steps >= 0, TG_EINVAL, "tg_run_history: bad argument");
+    TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_history: state must be aligned to 4 elements");
+    const size_t bytes = static_cast<size_t>(p->state_elems) * (p->precision == TG_FP64 ? 8 : 4);
+    const char* s0 = static_cast<const char*>(state);
+    const char* h0 = static_cast<const char*>(history);
+    const size_t hbytes = bytes * static_cast<size_t>(n_steps);
+    TG_REQUIRE(h0 + hbytes <= s0 || s0 + bytes <= h0, TG_EINVAL, "tg_run_history: history overlaps the state");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* h = static_cast<char*>(history);
+    for (int64_t k = 0; k < n_steps; ++k) {
+      hip_check(hipMemcpyAsync(h + static_cast<size_t>(k) * bytes, state, bytes, hipMemcpyDeviceToDevice, st),
+                "tg_run_history: copy");
+      step_any(p, state, st);
+    }
+    int flag = 0;
+    hip_check(hipMemcpyAsync(&flag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "tg_run_history: flag copy");
+    hip_check(hipStreamSynchronize(st), "tg_run_history: synchronize");
+    if (flag) {
+      hip_check(hipMemset(p->dflag, 0, sizeof(int)), "tg_run_history: flag reset");
+      throw Fail(TG_ENONFINITE, "tg_run_history: non-finite value in the state");
+    }
+    return TG_OK;
+  });
+}
+
 int tg_run_prepare(tg_plan p, void* state) {
   return guarded([&] {
     TG_REQUIRE(p && state, TG_EINVAL, "tg_run_prepare: null pointer");
