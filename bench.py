@@ -357,6 +357,8 @@ def other_workloads(tg, torch, steps):
     x0 = plan.state_from_deviation(workloads.perturbation(wl)[None])
     tgt = torch.from_numpy(workloads.target_pattern(wl)).to("cuda", torch.float32)
     fwd_flops = sum(f for _, f in plan.chain())  # per step
+    plan.set_route("generic")
+    per_mode = [f for _, f in plan.chain()]
     segment = checkpoint_segment(x0, wl.steps)  # what integrate picks: 1 = every state kept
     res = {}
 
@@ -386,7 +388,7 @@ def other_workloads(tg, torch, steps):
         # (the partial products S_k F of every op but the last, the tangent's
         # of every op but the first) and, with checkpoints, the recomputed
         # forward step
-        ops = [f for _, f in plan.chain()]
+        ops = per_mode  # the adjoint runs the per-mode products
         rev_flops = fwd_flops + (2 * fwd_flops - ops[0] - ops[-1]) + (fwd_flops if segment > 1 else 0.0)
         res[adj] = {"forward_ms_per_step": tf * 1e3 / wl.steps, "gradient_ms_per_step": tb * 1e3 / wl.steps,
                     "gradient_over_forward": tb / tf, "first_call_s": setup,
