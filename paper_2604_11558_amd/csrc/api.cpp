@@ -776,7 +776,8 @@ void build_plan(tg_plan_s* P) {
 // Launch one chain op reading X and writing Y (or updating Y += tau * acc).
 // Fusions for the adjoint: Y2 also receives the same product through epi2;
 // with L2 and X2 the product runs over the concatenated contraction,
-// Y = L X + L2 X2 (L2 a factor of the same shape as c.L).
+// Y = L X + L2 X2 (L2 a factor of the same shape as c.L); with X2 and Y2
+// (no L2; modes >= 2) a second product Y2 = L X2 shares the factor tiles.
 struct OpExtra {
   void* Y2 = nullptr;
   int epi2 = tg::EPI_STORE;
@@ -823,6 +824,7 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
     hip_check(tg::launch_mode_gemm<T>(g, st), "per-slice product launch");
     return;
   }
+  TG_REQUIRE(!(ex.X2 && !ex.L2) || (ex.Y2 && c.mode >= 2), TG_ENOTSUP, "dual product needs mode >= 2");
   if (c.mode == 1) {
     // C (nb x nm) = X (nb x nm, K-contiguous) * L^T
     g.A = X; g.B = c.L; g.C = Y;
@@ -837,6 +839,7 @@ void launch_op(const tg_plan_s* P, const tg::ChainOp& c, const void* X, void* Y,
     // per b: C (nm x na) = L (nm x nm) * X_b (nm x na)
     g.A = c.L; g.B = X; g.C = Y;
     if (ex.L2) { g.A2 = ex.L2; g.B2 = ex.X2; }
+    else if (ex.X2) g.B2 = ex.X2;  // dual product into Y2
     g.M = nm; g.N = static_cast<int>(na); g.K = nm; g.nbatch = static_cast<int>(nb);
     g.lda = nm; g.ldb = na; g.ldc = na;
     g.a_bstride = 0; g.b_bstride = nm * na; g.c_bstride = nm * na;
@@ -1235,6 +1238,12 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
       }
       launch_op<T>(P, cd, x, tn, tg::EPI_STORE, st, -1.0, nullptr, ex);
       if (need_x) launch_op<T>(P, c, x, xn, tg::EPI_STORE, st);
+      t_written = true;
+    } else if (t && need_x && c.mode >= 2) {  // L t and L x from shared factor tiles
+      OpExtra ex;
+      ex.X2 = x;
+      ex.Y2 = xn;
+      launch_op<T>(P, c, t, tn, tg::EPI_STORE, st, -1.0, nullptr, ex);
       t_written = true;
     } else {
       if (t) {

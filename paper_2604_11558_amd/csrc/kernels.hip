@@ -84,7 +84,8 @@ __device__ __forceinline__ float phi2_t(float x) {
 // through LDS (over the staging tiles) in the fixed order 0, 1, ..., SK - 1,
 // so results are reproducible.
 //   FUSE = 0: plain product; 1: also C2 through epi2; 2: the contraction
-//   concatenated with A2 B2.
+//   concatenated with A2 B2; 3: a second product A B2 (sharing A's tiles)
+//   into C2 through epi2.
 template <typename T, int TM, int TN, int KC, int SK, int FUSE>
 __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   using acc_t = typename Mfma<T>::acc_t;
@@ -94,15 +95,18 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   constexpr int LA = TM * KC / NT, LB = TN * KC / NT;
   static_assert(LA >= 1 && LB >= 1 && LA * NT == TM * KC && LB * NT == TN * KC, "tile does not fit the threads");
   static_assert(KC % (4 * SK) == 0, "K chunk not a multiple of the k-step split");
+  constexpr bool dual = FUSE == 3;
+  constexpr int NACC = dual ? 2 : 1;
   __shared__ union {
     struct {
       T a[KC][TM + 4];
-      T b[KC][TN + 4];
+      T b[NACC][KC][TN + 4];
     } st;
-    acc_t red[SK > 1 ? SK - 1 : 1][4 * FM * FN][64];
+    acc_t red[SK > 1 ? SK - 1 : 1][NACC * 4 * FM * FN][64];
   } sm;
   auto& sA = sm.st.a;
-  auto& sB = sm.st.b;
+  auto& sB = sm.st.b[0];
+  auto& sB2 = sm.st.b[NACC - 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -121,18 +125,24 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
   // second pair of the concatenated contraction (k >= K), same offsets
   constexpr bool cat = FUSE == 2;
   const T* A2 = cat ? static_cast<const T*>(g.A2) + (A - static_cast<const T*>(g.A)) : nullptr;
-  const T* B2 = cat ? static_cast<const T*>(g.B2) + (B - static_cast<const T*>(g.B)) : nullptr;
+  const T* B2 = (cat || dual) ? static_cast<const T*>(g.B2) + (B - static_cast<const T*>(g.B)) : nullptr;
   const int Kt = cat ? 2 * g.K : g.K;
   const int64_t bcol = g.b_ncol ? g.b_ncol : 1, ccol = g.c_ncol ? g.c_ncol : 1;
 
-  acc_t acc[FM][FN];
+  acc_t acc[FM][FN], acc2[dual ? FM : 1][dual ? FN : 1];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  if constexpr (dual) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc2[i][j] = acc_t{0, 0, 0, 0};
+  }
 
   const int li = lane & 15, lk = lane >> 4;
-  T ra[LA], rb[LB];
+  T ra[LA], rb[LB], rb2[dual ? LB : 1];
   // The split takes contiguous K ranges of Kq (a multiple of the k-step)
   // per wave group, so each partial sums neighbouring terms in order as the
   // unsplit product does (operands such as stencil differences cancel
@@ -167,12 +177,14 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
           const bool ok = kmap(t, kk, gk) && gn < g.N;
           const bool hi = cat && gk >= g.K;
           rb[e] = ok ? (hi ? B2 : B)[gn * g.ldb + (hi ? gk - g.K : gk)] : T(0);
+          if constexpr (dual) rb2[e] = ok ? B2[gn * g.ldb + gk] : T(0);
         } else {
           const int kk = idx / TN, nn = idx % TN;
           const int gn = n0 + nn;
           const bool ok = kmap(t, kk, gk) && gn < g.N;
           const bool hi = cat && gk >= g.K;
           rb[e] = ok ? (hi ? B2 : B)[(hi ? gk - g.K : gk) * g.ldb + gn * bcol] : T(0);
+          if constexpr (dual) rb2[e] = ok ? B2[gk * g.ldb + gn * bcol] : T(0);
         }
       }
     };
@@ -189,6 +201,10 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
         const int idx = tid + NT * e;
         if (g.b_kcontig) sB[idx % KC][idx / KC] = rb[e];
         else sB[idx / TN][idx % TN] = rb[e];
+        if constexpr (dual) {
+          if (g.b_kcontig) sB2[idx % KC][idx / KC] = rb2[e];
+          else sB2[idx / TN][idx % TN] = rb2[e];
+        }
       }
       __syncthreads();
       if ((t + 1) * KCQ < Kq) gload(t + 1);  // in flight during this chunk's MFMAs
@@ -203,17 +219,29 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) acc[i][j] = Mfma<T>::mac(av[i], bv[j], acc[i][j]);
+        if constexpr (dual) {
+#pragma unroll
+          for (int j = 0; j < FN; ++j) bv[j] = sB2[kk + lk][wn * WN + j * 16 + li];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc2[i][j] = Mfma<T>::mac(av[i], bv[j], acc2[i][j]);
+        }
       }
     }
   };
   if constexpr (SK > 1) {
     auto& red = sm.red;
     __syncthreads();  // every wave is done with the staging tiles
+    constexpr int NB = 4 * FM * FN;  // blocks of one accumulator set
     if (kq > 0) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) red[kq - 1][(quarter * FM + i) * FN + j][lane] = acc[i][j];
+        for (int j = 0; j < FN; ++j) {
+          red[kq - 1][(quarter * FM + i) * FN + j][lane] = acc[i][j];
+          if constexpr (dual) red[kq - 1][NB + (quarter * FM + i) * FN + j][lane] = acc2[i][j];
+        }
     }
     __syncthreads();
     if (kq == 0) {
@@ -222,12 +250,16 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) acc[i][j] = acc[i][j] + red[p][(quarter * FM + i) * FN + j][lane];
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = acc[i][j] + red[p][(quarter * FM + i) * FN + j][lane];
+            if constexpr (dual) acc2[i][j] = acc2[i][j] + red[p][NB + (quarter * FM + i) * FN + j][lane];
+          }
     }
   }
 
-  T* C2 = FUSE == 1 ? static_cast<T*>(g.C2) + (C - static_cast<T*>(g.C)) : nullptr;
-  const bool phi_epi = g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC || (FUSE == 1 && g.epi2 == EPI_PHI);
+  T* C2 = (FUSE == 1 || dual) ? static_cast<T*>(g.C2) + (C - static_cast<T*>(g.C)) : nullptr;
+  const bool phi_epi =
+      g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC || ((FUSE == 1 || dual) && g.epi2 == EPI_PHI);
   const double cs = phi_epi ? g.cs[s] : 0.0;
   const double pbv = (phi_epi && g.pb) ? g.pb[b] : 1.0;
   const bool diag = g.dg.part != nullptr;  // EPI_UPDATE of a first-mode product
@@ -250,7 +282,10 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
             if (g.pm) x *= g.pm[row];
             if (g.pn) x *= g.pn[col];
           }
-          if constexpr (FUSE == 1) C2[off] = g.epi2 == EPI_PHI ? v * phi1_t(static_cast<T>(x)) : v;
+          if constexpr (FUSE == 1 || dual) {
+            const T v2 = dual ? acc2[dual ? i : 0][dual ? j : 0][r] : v;
+            C2[off] = g.epi2 == EPI_PHI ? v2 * phi1_t(static_cast<T>(x)) : v2;
+          }
           if (g.epi == EPI_PHI || g.epi == EPI_DPHI || g.epi == EPI_PHI_ACC) {
             const T xt = static_cast<T>(x);
             if (g.epi == EPI_PHI) {
@@ -276,7 +311,7 @@ __global__ __launch_bounds__(256 * SK) void mode_gemm_kernel(GemmArgs g) {
                   reinterpret_cast<double*>(&sm));
 }
 
-template <typename T, int TM, int TN, int SK>
+template <typename T, int TM, int TN, int SK, int FUSE>
 static hipError_t launch_tile_sk(const GemmArgs& g, hipStream_t s) {
   constexpr int KC = SK > 2 ? 64 : 32;
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
@@ -286,28 +321,28 @@ static hipError_t launch_tile_sk(const GemmArgs& g, hipStream_t s) {
     if (g.epi != EPI_UPDATE || !g.b_kcontig || g.nbatch != 1 || tiles > h.dg.cap) return hipErrorInvalidValue;
   }
   dim3 grid(tiles, g.nbatch, g.nslab);
-  if (g.A2) hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, 2>), grid, dim3(256 * SK), 0, s, h);
-  else if (g.C2) hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, 1>), grid, dim3(256 * SK), 0, s, h);
-  else hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, 0>), grid, dim3(256 * SK), 0, s, h);
+  hipLaunchKernelGGL((mode_gemm_kernel<T, TM, TN, KC, SK, FUSE>), grid, dim3(256 * SK), 0, s, h);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !h.dg.part) return e;
   return launch_diag_finish(h.dg, g.nslab, s);
 }
 
-// LDS of one workgroup: the two staging tiles, or the partial quarters of
-// the split, whichever is larger.
-template <typename T, int TM, int TN, int SK>
+// LDS of one workgroup: the staging tiles, or the partial quarters of the
+// split, whichever is larger (two B tiles and two accumulator sets for the
+// dual product).
+template <typename T, int TM, int TN, int SK, int FUSE>
 constexpr size_t gemm_lds() {
   constexpr int KC = SK > 2 ? 64 : 32;
-  const size_t st = static_cast<size_t>(KC) * (TM + 4 + TN + 4) * sizeof(T);
-  const size_t red = static_cast<size_t>(SK - 1) * TM * TN * sizeof(T);
+  constexpr int nacc = FUSE == 3 ? 2 : 1;
+  const size_t st = static_cast<size_t>(KC) * (TM + 4 + nacc * (TN + 4)) * sizeof(T);
+  const size_t red = static_cast<size_t>(nacc) * (SK - 1) * TM * TN * sizeof(T);
   return st > red ? st : red;
 }
 
 // Waves per SIMD: SK = 4 while the tiles give at most one workgroup of
 // 4 waves per compute unit, SK = 2 while they give at most two, else 1
 // (each within 64 KB of LDS).
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, int FUSE>
 static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
   static int cus = 0;
   if (cus == 0) {
@@ -319,24 +354,34 @@ static hipError_t launch_tile(const GemmArgs& g, hipStream_t s) {
       cus = 256;
   }
   const int64_t wgs = static_cast<int64_t>((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN) * g.nbatch * g.nslab;
-  if constexpr (gemm_lds<T, TM, TN, 4>() <= 65536)
-    if (wgs <= cus) return launch_tile_sk<T, TM, TN, 4>(g, s);
-  if constexpr (gemm_lds<T, TM, TN, 2>() <= 65536)
-    if (wgs <= 2 * cus) return launch_tile_sk<T, TM, TN, 2>(g, s);
-  return launch_tile_sk<T, TM, TN, 1>(g, s);
+  if constexpr (gemm_lds<T, TM, TN, 4, FUSE>() <= 65536)
+    if (wgs <= cus) return launch_tile_sk<T, TM, TN, 4, FUSE>(g, s);
+  if constexpr (gemm_lds<T, TM, TN, 2, FUSE>() <= 65536)
+    if (wgs <= 2 * cus) return launch_tile_sk<T, TM, TN, 2, FUSE>(g, s);
+  static_assert(gemm_lds<T, TM, TN, 1, FUSE>() <= 65536, "GEMM tile exceeds 64 KB of LDS");
+  return launch_tile_sk<T, TM, TN, 1, FUSE>(g, s);
+}
+
+template <typename T, int TM, int TN>
+static hipError_t launch_tile_fused(const GemmArgs& g, hipStream_t s) {
+  if (g.A2) return launch_tile<T, TM, TN, 2>(g, s);
+  if (g.C2 && g.B2) return launch_tile<T, TM, TN, 3>(g, s);
+  if (g.C2) return launch_tile<T, TM, TN, 1>(g, s);
+  return launch_tile<T, TM, TN, 0>(g, s);
 }
 
 template <typename T>
 hipError_t launch_mode_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.nbatch <= 0 || g.nslab <= 0) return hipErrorInvalidValue;
-  if ((g.A2 != nullptr) != (g.B2 != nullptr) || (g.A2 && g.C2)) return hipErrorInvalidValue;
+  if ((g.A2 && (!g.B2 || g.C2)) || (g.B2 && !g.A2 && !g.C2)) return hipErrorInvalidValue;
   if (g.C2 && (g.dg.part || (g.epi2 != EPI_STORE && g.epi2 != EPI_PHI))) return hipErrorInvalidValue;
+  if (g.C2 && g.B2 && (g.epi == EPI_UPDATE || g.epi == EPI_PHI_ACC)) return hipErrorInvalidValue;
   if (g.nbatch > 65535 || g.nslab > 65535) return hipErrorInvalidValue;
   switch (g.tile) {
-    case 1: return launch_tile<T, 32, 64>(g, s);
-    case 2: return launch_tile<T, 64, 32>(g, s);
-    case 3: return launch_tile<T, 32, 32>(g, s);
-    default: return launch_tile<T, 64, 64>(g, s);
+    case 1: return launch_tile_fused<T, 32, 64>(g, s);
+    case 2: return launch_tile_fused<T, 64, 32>(g, s);
+    case 3: return launch_tile_fused<T, 32, 32>(g, s);
+    default: return launch_tile_fused<T, 64, 64>(g, s);
   }
 }
 
