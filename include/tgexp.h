@@ -285,9 +285,9 @@ int tg_coupled_run(tg_plan bulk, tg_plan surface, void* bulk_state, void* surfac
  * device, plan layout); lambda: dL/dW_{n+1} in, dL/dW_n out (device, same
  * layout); grad: device doubles [2 * nslab], accumulated.  Runs the
  * per-mode kernels in the plan's storage type (FP32 for split-bf16 plans)
- * and allocates an 8-state workspace (plus 128 doubles and one counter per
- * slab for the dot products' partial sums, added in a fixed order, so
- * repeated sweeps give identical gradients) on first use.  The reference state
+ * and allocates an 8-state workspace (plus three doubles per slab and
+ * block of 256 points for the gradient's partial sums, added in a fixed
+ * order, so repeated sweeps give identical gradients) on first use.  The reference state
  * (and the cylinder's Dirichlet value) is held fixed. */
 int tg_adjoint_step(tg_plan p, const void* state_n, void* lambda, double* grad, void* stream);
 

@@ -1183,17 +1183,11 @@ void step_impl(tg_plan_s* P, void* state, hipStream_t st, const tg::DiagArgs* dg
 template <typename T>
 void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipStream_t st) {
   const size_t bytes = static_cast<size_t>(P->state_elems) * sizeof(T);
-  const size_t pbytes = sizeof(double) * 2 * tg::kDotBlocks * static_cast<size_t>(P->nslab);
-  const size_t cbytes = sizeof(unsigned) * static_cast<size_t>(P->nslab);
+  // the gradient's partial sums: three per species and block of 256 points
+  const size_t pbytes = sizeof(double) * 3 * static_cast<size_t>(P->nslab) * static_cast<size_t>((P->npts + 255) / 256);
+  if (!P->adj_ws) hip_check(hipMalloc(&P->adj_ws, 8 * bytes + pbytes), "hipMalloc(adjoint workspace)");
   char* w = static_cast<char*>(P->adj_ws);
-  if (!w) {
-    hip_check(hipMalloc(&P->adj_ws, 8 * bytes + pbytes + cbytes), "hipMalloc(adjoint workspace)");
-    w = static_cast<char*>(P->adj_ws);
-    // the dot products' finishing counters start at zero and are left there
-    hip_check(hipMemsetAsync(w + 8 * bytes + pbytes, 0, cbytes, st), "hipMemsetAsync(adjoint counters)");
-  }
-  double* part = reinterpret_cast<double*>(w + 8 * bytes);  // dot-product partial sums
-  unsigned* count = reinterpret_cast<unsigned*>(w + 8 * bytes + pbytes);
+  double* part = reinterpret_cast<double*>(w + 8 * bytes);
   void* F = w;
   void* DMW = w + bytes;
   void* xbuf[2] = {w + 2 * bytes, w + 3 * bytes};
@@ -1260,9 +1254,6 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
     }
   }
   TG_REQUIRE(t != nullptr, TG_EINVAL, "adjoint: chain without a d-dependent factor");
-  // dL/dd_s += tau <lambda_s, (dS/dd) F_s>
-  hip_check(tg::launch_dot<T>(lam, t, npts, nslab, P->d_tau, grad, nullptr, nullptr, part, count, st),
-            "adjoint dot");
 
   // mu = S^T lambda: transposed factors in reverse order; each Hadamard
   // factor moves to the product that precedes it in the reversed chain
@@ -1285,9 +1276,6 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
     y = out;
     yb ^= 1;
   }
-  // dL/dd_s += (tau / d_s) <mu_s, d_s M W_s>;  dL/dc_s += tau sum mu_s
-  hip_check(tg::launch_dot<T>(MU, DMW, npts, nslab, P->d_taurd, grad, P->d_tau, grad + nslab, part, count, st),
-            "adjoint dot");
   // lambda += tau (d M^T mu + J^T mu)
   tg::StencilArgs a = stencil_args(P, MU, MTMU, TG_APPLY_DIFFUSION);
   a.coef = P->d_coefT;
@@ -1297,6 +1285,14 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   aa.mu = MU;
   aa.mtmu = MTMU;
   aa.lam = lam;
+  // dL/dd_s += tau <lambda_s, (dS/dd) F_s> + (tau / d_s) <mu_s, d_s M W_s>;
+  // dL/dc_s += tau sum mu_s (old lambda: read before the update)
+  aa.tang = t;
+  aa.dmw = DMW;
+  aa.part = part;
+  aa.grad = grad;
+  aa.tau_s = P->d_tau;
+  aa.taurd_s = P->d_taurd;
   aa.npts = npts;
   aa.nspecies = P->ns;
   aa.batch = P->batch;

@@ -567,122 +567,110 @@ hipError_t launch_diag_finish(const DiagArgs& d, int nslab, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Per-slab dot products (double accumulation, block reduction in LDS): each
-// block stores its partial pair, and the last block of a slab to finish
-// adds the partials by a tree over the block index, so repeated runs give
-// identical results whatever the order the blocks ran in.
-template <typename T>
-__global__ __launch_bounds__(256) void dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t npts,
-                                                  double* part, unsigned* count, const double* scale, double* out,
-                                                  const double* scale2, double* out2) {
-  __shared__ double red[2][256];
-  __shared__ int last;
-  const int s = blockIdx.y, t = threadIdx.x;
-  const T* as = a + static_cast<int64_t>(s) * npts;
-  const T* bs = b ? b + static_cast<int64_t>(s) * npts : nullptr;
-  double acc = 0.0, sum = 0.0;
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + t; p < npts; p += static_cast<int64_t>(gridDim.x) * 256) {
-    const double av = static_cast<double>(as[p]);
-    acc += av * (bs ? static_cast<double>(bs[p]) : 1.0);
-    sum += av;
-  }
-  red[0][t] = acc;
-  red[1][t] = sum;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      red[0][t] += red[0][t + w];
-      red[1][t] += red[1][t + w];
-    }
-    __syncthreads();
-  }
-  const int nb = gridDim.x;
-  double* ps = part + 2 * static_cast<int64_t>(s) * nb;
-  if (t == 0) {
-    ps[2 * blockIdx.x] = red[0][0];
-    ps[2 * blockIdx.x + 1] = red[1][0];
-    __threadfence();  // the partials are visible device-wide before the count
-    last = atomicAdd(&count[s], 1u) == static_cast<unsigned>(nb - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  // the last block: every partial pair loaded at once, then the same
-  // fixed-order tree over the block index
-  __threadfence();
-  red[0][t] = t < nb ? ps[2 * t] : 0.0;
-  red[1][t] = t < nb ? ps[2 * t + 1] : 0.0;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      red[0][t] += red[0][t + w];
-      red[1][t] += red[1][t + w];
-    }
-    __syncthreads();
-  }
-  if (t != 0) return;
-  out[s] += red[0][0] * (scale ? scale[s] : 1.0);
-  if (out2) out2[s] += red[1][0] * (scale2 ? scale2[s] : 1.0);
-  count[s] = 0u;  // ready for the next launch
-}
-
-template <typename T>
-hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
-                      const double* scale2, double* out2, double* part, unsigned* count, hipStream_t s) {
-  if (npts <= 0 || nslab <= 0 || nslab > 65535 || !part || !count || !out) return hipErrorInvalidValue;
-  const int blocks = static_cast<int>(std::min<int64_t>((npts + 255) / 256, kDotBlocks));
-  hipLaunchKernelGGL(dot_kernel<T>, dim3(blocks, nslab), dim3(256), 0, s, static_cast<const T*>(a),
-                     static_cast<const T*>(b), npts, part, count, scale, out, scale2, out2);
-  return hipGetLastError();
-}
-
-template hipError_t launch_dot<double>(const void*, const void*, int64_t, int, const double*, double*, const double*,
-                                       double*, double*, unsigned*, hipStream_t);
-template hipError_t launch_dot<float>(const void*, const void*, int64_t, int, const double*, double*, const double*,
-                                      double*, double*, unsigned*, hipStream_t);
-
 // lam_s += tau (mtmu_s + sum_r J[r][s] mu_r), J = dG/dW at W = w_ref + state.
 template <typename T>
 __global__ __launch_bounds__(256) void adjoint_combine_kernel(AdjointArgs a) {
+  __shared__ double red[4][9];
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const int inst = blockIdx.y;
-  if (p >= a.npts) return;
+  const bool in = p < a.npts;
   const int ns = a.nspecies;
-  const int64_t base = static_cast<int64_t>(inst) * ns * a.npts + p;
+  const int64_t base = static_cast<int64_t>(inst) * ns * a.npts + (in ? p : 0);
   const T* st = static_cast<const T*>(a.state) + base;
   const T* mu = static_cast<const T*>(a.mu) + base;
   const T* mt = static_cast<const T*>(a.mtmu) + base;
+  const T* tg = static_cast<const T*>(a.tang) + base;
+  const T* dm = static_cast<const T*>(a.dmw) + base;
   T* lam = static_cast<T*>(a.lam) + base;
   const double* wr = a.wref + inst * ns;
-  double m[3] = {0, 0, 0}, jt[3] = {0, 0, 0};
-  for (int q = 0; q < ns && q < 3; ++q) m[q] = static_cast<double>(mu[q * a.npts]);
-  if (a.reaction == 1 || a.reaction == 3) {  // (gamma times) g_u = a - u + u^2 v,  g_v = b - u^2 v
-    const double gam = a.reaction == 3 ? a.rparams[inst * kRParams + 2] : 1.0;
-    const double u = wr[0] + static_cast<double>(st[0]);
-    const double v = wr[1] + static_cast<double>(st[a.npts]);
-    jt[0] = gam * ((-1.0 + 2.0 * u * v) * m[0] - 2.0 * u * v * m[1]);
-    jt[1] = gam * (u * u * m[0] - u * u * m[1]);
-  } else if (a.reaction == 2) {  // + kappa u w and mu (u - w) terms
-    const double* rp = a.rparams + inst * kRParams;
-    const double kap = rp[2], mup = rp[3];
-    const double u = wr[0] + static_cast<double>(st[0]);
-    const double v = wr[1] + static_cast<double>(st[a.npts]);
-    const double w = wr[2] + static_cast<double>(st[2 * a.npts]);
-    jt[0] = (-1.0 + 2.0 * u * v - kap * w) * m[0] - 2.0 * u * v * m[1] + mup * m[2];
-    jt[1] = u * u * m[0] - u * u * m[1];
-    jt[2] = -kap * u * m[0] - mup * m[2];
+  double m[3] = {0, 0, 0}, jt[3] = {0, 0, 0}, d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (in) {
+    for (int q = 0; q < ns && q < 3; ++q) m[q] = static_cast<double>(mu[q * a.npts]);
+    if (a.reaction == 1 || a.reaction == 3) {  // (gamma times) g_u = a - u + u^2 v,  g_v = b - u^2 v
+      const double gam = a.reaction == 3 ? a.rparams[inst * kRParams + 2] : 1.0;
+      const double u = wr[0] + static_cast<double>(st[0]);
+      const double v = wr[1] + static_cast<double>(st[a.npts]);
+      jt[0] = gam * ((-1.0 + 2.0 * u * v) * m[0] - 2.0 * u * v * m[1]);
+      jt[1] = gam * (u * u * m[0] - u * u * m[1]);
+    } else if (a.reaction == 2) {  // + kappa u w and mu (u - w) terms
+      const double* rp = a.rparams + inst * kRParams;
+      const double kap = rp[2], mup = rp[3];
+      const double u = wr[0] + static_cast<double>(st[0]);
+      const double v = wr[1] + static_cast<double>(st[a.npts]);
+      const double w = wr[2] + static_cast<double>(st[2 * a.npts]);
+      jt[0] = (-1.0 + 2.0 * u * v - kap * w) * m[0] - 2.0 * u * v * m[1] + mup * m[2];
+      jt[1] = u * u * m[0] - u * u * m[1];
+      jt[2] = -kap * u * m[0] - mup * m[2];
+    }
+    for (int q = 0; q < ns && q < 3; ++q) {
+      const double l = static_cast<double>(lam[q * a.npts]);
+      d[3 * q] = l * static_cast<double>(tg[q * a.npts]);
+      d[3 * q + 1] = m[q] * static_cast<double>(dm[q * a.npts]);
+      d[3 * q + 2] = m[q];
+      const double add = a.tau * (static_cast<double>(mt[q * a.npts]) + jt[q]);
+      lam[q * a.npts] = static_cast<T>(l + add);
+    }
   }
-  for (int q = 0; q < ns && q < 3; ++q) {
-    const double add = a.tau * (static_cast<double>(mt[q * a.npts]) + jt[q]);
-    lam[q * a.npts] = static_cast<T>(static_cast<double>(lam[q * a.npts]) + add);
+  // block partials of the three sums per species: butterfly within each
+  // wave, then the four waves in order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d[k] += __shfl_xor(d[k], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[wave][k] = d[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 * ns) {
+    const int k = threadIdx.x;
+    const double v = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    a.part[(static_cast<int64_t>(inst) * gridDim.x + blockIdx.x) * (3 * ns) + k] = v;
+  }
+}
+
+// One block per (species, instance): the three sums of the slab over the
+// combine launch's blocks, by a fixed tree, into the gradient.
+__global__ __launch_bounds__(256) void adjoint_dots_kernel(const double* __restrict__ part, int blocks, int ns,
+                                                           const double* tau_s, const double* taurd_s,
+                                                           double* grad, int nslab) {
+  __shared__ double red[3][256];
+  const int q = blockIdx.x, inst = blockIdx.y, t = threadIdx.x;
+  double v[3] = {0, 0, 0};
+  for (int bl = t; bl < blocks; bl += 256)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] += part[(static_cast<int64_t>(inst) * blocks + bl) * (3 * ns) + 3 * q + c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) red[c][t] = v[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) red[c][t] += red[c][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int s = inst * ns + q;
+    grad[s] += red[0][0] * tau_s[s];
+    grad[s] += red[1][0] * taurd_s[s];
+    grad[nslab + s] += red[2][0] * tau_s[s];
   }
 }
 
 template <typename T>
 hipError_t launch_adjoint_combine(const AdjointArgs& a, hipStream_t s) {
-  if (a.npts <= 0 || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
-  dim3 grid(static_cast<unsigned>((a.npts + 255) / 256), a.batch);
+  if (a.npts <= 0 || a.batch <= 0 || a.batch > 65535 || a.nspecies < 1 || a.nspecies > 3) return hipErrorInvalidValue;
+  if (!a.tang || !a.dmw || !a.part || !a.grad || !a.tau_s || !a.taurd_s) return hipErrorInvalidValue;
+  const int64_t blocks = (a.npts + 255) / 256;
+  if (blocks > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+  dim3 grid(static_cast<unsigned>(blocks), a.batch);
   hipLaunchKernelGGL(adjoint_combine_kernel<T>, grid, dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adjoint_dots_kernel, dim3(a.nspecies, a.batch), dim3(256), 0, s, a.part, static_cast<int>(blocks),
+                     a.nspecies, a.tau_s, a.taurd_s, a.grad, a.batch * a.nspecies);
   return hipGetLastError();
 }
 

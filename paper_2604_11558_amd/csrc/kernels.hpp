@@ -139,28 +139,27 @@ struct StencilArgs {
 template <typename T>
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t s);
 
-// out[s] += scale[s] * sum_p a[s][p] * b[s][p] (b == nullptr: b = 1) over the
-// npts points of each of nslab slabs, and, where out2 is given,
-// out2[s] += scale2[s] * sum_p a[s][p] (null scales: 1).  Double
-// accumulation; each block stores its partial pair in
-// part[nslab][kDotBlocks][2], and the block that finishes last in a slab
-// (counted in count[nslab], which must start at zero and is left at zero)
-// adds the partials by a fixed tree over the block index, so results do
-// not depend on timing.
-constexpr int kDotBlocks = 64;  // at most the block size (the finishing tree); each
-                                // block pays a device-scope release, so few
-template <typename T>
-hipError_t launch_dot(const void* a, const void* b, int64_t npts, int nslab, const double* scale, double* out,
-                      const double* scale2, double* out2, double* part, unsigned* count, hipStream_t s);
-
 // Adjoint combination per point, all species of an instance:
 //   lam_s += tau * (mtmu_s + sum_r dG_r/dw_s (W) mu_r)
 // with W = w_ref + state (the reaction Jacobian at step n).
+// The same launch gathers, per block of 256 points and species s, the
+// partial sums of lam_s tang_s (the old lam), mu_s dmw_s and mu_s into
+// part[batch][blocks][3 * nspecies]; a second launch adds each slab's
+// partials by a fixed tree over the blocks and accumulates
+//   grad[s] += tau[s] <lam_s, tang_s> + taurd[s] <mu_s, dmw_s>,
+//   grad[nslab + s] += tau[s] sum mu_s
+// (no atomics: repeated sweeps give identical gradients).
 struct AdjointArgs {
   const void* state;
   const void* mu;     // S^T lambda (unscaled)
   const void* mtmu;   // d_s M^T mu
   void* lam;
+  const void* tang;   // (dS/dd) F of the step
+  const void* dmw;    // d_s M W of the step
+  double* part;       // [batch][blocks][3 * nspecies], blocks = ceil(npts / 256)
+  double* grad;       // [2 * batch * nspecies], accumulated
+  const double* tau_s;    // [nslab] tau
+  const double* taurd_s;  // [nslab] tau / d_s
   int64_t npts;
   int nspecies, batch, reaction;
   double tau;
