@@ -180,12 +180,15 @@ int tg_sync_status(tg_plan p, void* stream);
 int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream);
 /* n_steps steps (in place) keeping the state before each one, for a reverse
  * sweep of the discrete adjoint (tg_adjoint_step) that recomputes nothing:
- * history (device, caller-owned, n_steps * the plan's state size, in the
- * plan's storage type and layout) receives in slot k the state before step
- * k, k = 0 .. n_steps - 1, by a device copy ahead of the step's launches.
+ * history (device, caller-owned, n_steps * the plan's state size elements,
+ * the plan's layout) receives in slot k the state before step k, k = 0 ..
+ * n_steps - 1, ahead of the step's launches: a device copy in the plan's
+ * storage type, or, with history_fp64 != 0 and an FP32-storage plan, the
+ * values widened to FP64 (for an FP64 reverse sweep of an FP32 forward).
  * history must not overlap state.  Steps launch directly (no graphs);
  * synchronises the stream at the end and returns TG_ENONFINITE as tg_run. */
-int tg_run_history(tg_plan p, void* state, int64_t n_steps, void* history, void* stream);
+int tg_run_history(tg_plan p, void* state, int64_t n_steps, void* history, int32_t history_fp64,
+                   void* stream);
 /* Capture (without running anything) the graphs tg_run replays for this
  * state pointer, so that a later tg_run spends no time capturing or
  * instantiating them.  Nothing to do on route 4.  Host-synchronous; the

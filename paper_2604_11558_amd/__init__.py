@@ -47,7 +47,7 @@ _SIGNATURES = {
     "tg_plan_reference": (ctypes.c_int, [_p, _pd]),
     "tg_step": (ctypes.c_int, [_p, _p, _p]),
     "tg_run": (ctypes.c_int, [_p, _p, _c_i64, _p]),
-    "tg_run_history": (ctypes.c_int, [_p, _p, _c_i64, _p, _p]),
+    "tg_run_history": (ctypes.c_int, [_p, _p, _c_i64, _p, ctypes.c_int32, _p]),
     "tg_run_prepare": (ctypes.c_int, [_p, _p]),
     "tg_step_diag_noalloc": (ctypes.c_int, [_p, _p, _p, _p]),
     "tg_step_diag": (ctypes.c_int, [_p, _p, _p, _p]),
@@ -239,13 +239,16 @@ class Plan:
 
     def run_history(self, state, n_steps: int, history, stream=None):
         """``n_steps`` steps keeping the state before each in ``history[k]``
-        (a device tensor of shape (n_steps,) + state shape, same dtype)."""
+        (a device tensor of shape (n_steps,) + state shape, in the plan's
+        dtype, or float64 for an FP32-storage plan: the values widened)."""
+        import torch
         self._check_tensor(state)
-        if (not history.is_cuda or not history.is_contiguous() or history.dtype != self.dtype
+        fp64 = history.dtype == torch.float64 and self.dtype != torch.float64
+        if (not history.is_cuda or not history.is_contiguous() or (history.dtype != self.dtype and not fp64)
                 or tuple(history.shape) != (int(n_steps),) + tuple(state.shape)):
             raise ValueError("history must be a contiguous device tensor of shape (n_steps,) + state shape "
-                             "in the plan's dtype")
-        _check(lib().tg_run_history(self._h, state.data_ptr(), int(n_steps), history.data_ptr(),
+                             "in the plan's dtype or float64")
+        _check(lib().tg_run_history(self._h, state.data_ptr(), int(n_steps), history.data_ptr(), int(fp64),
                                     _stream_ptr(stream)))
 
     def prepare_run(self, state):

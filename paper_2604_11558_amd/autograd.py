@@ -80,9 +80,9 @@ _STORE_ALL_CAP = 8 << 30
 
 def checkpoint_segment(w0, n_steps: int) -> int:
     """Steps between checkpoints: 1 (keep every state) when n_steps states
-    of w0's size fit min(8 GiB, a quarter of the free device memory), else
-    ceil(sqrt(n_steps))."""
-    need = int(n_steps) * w0.numel() * w0.element_size()
+    of w0's size, kept in FP64, fit min(8 GiB, a quarter of the free device
+    memory), else ceil(sqrt(n_steps))."""
+    need = int(n_steps) * w0.numel() * 8
     free, _ = torch.cuda.mem_get_info(w0.device)
     if need <= min(_STORE_ALL_CAP, free // 4):
         return 1
@@ -107,8 +107,10 @@ class SplitEEFunction(torch.autograd.Function):
             x = torch.empty(w0.shape, dtype=plan.dtype, device=w0.device)
             plan._autograd_state = x
         x.copy_(w0.detach())
-        if segment == 1:  # every state, in one allocation
-            hist = torch.empty((n_steps,) + tuple(x.shape), dtype=x.dtype, device=x.device)
+        wide = adjoint_precision == "fp64" and plan.dtype != torch.float64
+        if segment == 1:  # every state, in one allocation, in the reverse sweep's precision
+            hist = torch.empty((n_steps,) + tuple(x.shape), dtype=torch.float64 if wide else x.dtype,
+                               device=x.device)
             plan.run_history(x, n_steps, hist)
             ckpts = list(hist.unbind(0))
         else:
@@ -148,7 +150,7 @@ class SplitEEFunction(torch.autograd.Function):
             length = min(ctx.segment, ctx.n_steps - start)
             if length == 1:  # a stored state: nothing to recompute
                 st = ckpts[k]
-                if conv is not None:
+                if st.dtype != adj.dtype:
                     conv.copy_(st)
                     st = conv
                 adj.adjoint_step(st, lam, grad)

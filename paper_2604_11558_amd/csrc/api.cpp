@@ -1776,20 +1776,29 @@ int tg_run(tg_plan p, void* state, int64_t n_steps, void* stream) {
   });
 }
 
-int tg_run_history(tg_plan p, void* state, int64_t n_steps, void* history, void* stream) {
+int tg_run_history(tg_plan p, void* state, int64_t n_steps, void* history, int32_t history_fp64, void* stream) {
   return guarded([&] {
     TG_REQUIRE(p && state && history && n_steps >= 0, TG_EINVAL, "tg_run_history: bad argument");
     TG_REQUIRE(aligned(p, state), TG_EINVAL, "tg_run_history: state must be aligned to 4 elements");
-    const size_t bytes = static_cast<size_t>(p->state_elems) * (p->precision == TG_FP64 ? 8 : 4);
+    const bool f64 = p->precision == TG_FP64;
+    const bool widen = history_fp64 != 0 && !f64;
+    const size_t bytes = static_cast<size_t>(p->state_elems) * (f64 ? 8 : 4);
+    const size_t hslot = static_cast<size_t>(p->state_elems) * (f64 || widen ? 8 : 4);
     const char* s0 = static_cast<const char*>(state);
     const char* h0 = static_cast<const char*>(history);
-    const size_t hbytes = bytes * static_cast<size_t>(n_steps);
+    const size_t hbytes = hslot * static_cast<size_t>(n_steps);
     TG_REQUIRE(h0 + hbytes <= s0 || s0 + bytes <= h0, TG_EINVAL, "tg_run_history: history overlaps the state");
+    TG_REQUIRE(!widen || (reinterpret_cast<uintptr_t>(history) & 15) == 0, TG_EINVAL,
+               "tg_run_history: an FP64 history must be 16-byte aligned");
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* h = static_cast<char*>(history);
     for (int64_t k = 0; k < n_steps; ++k) {
-      hip_check(hipMemcpyAsync(h + static_cast<size_t>(k) * bytes, state, bytes, hipMemcpyDeviceToDevice, st),
-                "tg_run_history: copy");
+      void* slot = h + static_cast<size_t>(k) * hslot;
+      if (widen)
+        hip_check(tg::launch_widen(static_cast<const float*>(state), static_cast<double*>(slot), p->state_elems, st),
+                  "tg_run_history: widen");
+      else
+        hip_check(hipMemcpyAsync(slot, state, bytes, hipMemcpyDeviceToDevice, st), "tg_run_history: copy");
       step_any(p, state, st);
     }
     int flag = 0;

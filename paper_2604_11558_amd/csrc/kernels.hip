@@ -674,6 +674,26 @@ hipError_t launch_adjoint_combine(const AdjointArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void widen_kernel(const float4* __restrict__ src, double* __restrict__ dst,
+                                                    int64_t n4) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n4) return;
+  const float4 v = src[i];
+  double2* d = reinterpret_cast<double2*>(dst + 4 * i);
+  d[0] = double2{v.x, v.y};
+  d[1] = double2{v.z, v.w};
+}
+
+hipError_t launch_widen(const float* src, double* dst, int64_t n, hipStream_t s) {
+  // states are padded to whole float4 groups and 16-byte aligned
+  if (n <= 0 || n % 4 != 0 || (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15))
+    return hipErrorInvalidValue;
+  const int64_t n4 = n / 4;
+  hipLaunchKernelGGL(widen_kernel, dim3(static_cast<unsigned>((n4 + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(src), dst, n4);
+  return hipGetLastError();
+}
+
 template hipError_t launch_adjoint_combine<double>(const AdjointArgs&, hipStream_t);
 template hipError_t launch_adjoint_combine<float>(const AdjointArgs&, hipStream_t);
 

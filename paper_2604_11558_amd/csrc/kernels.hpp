@@ -169,4 +169,7 @@ struct AdjointArgs {
 template <typename T>
 hipError_t launch_adjoint_combine(const AdjointArgs& a, hipStream_t s);
 
+// dst[i] = (double) src[i], i < n (FP32 states kept in FP64).
+hipError_t launch_widen(const float* src, double* dst, int64_t n, hipStream_t s);
+
 }  // namespace tg
