@@ -37,7 +37,7 @@ COPY_BYTES = 256 << 20
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
 TRAFFIC = {"fused:0:16,64": 11039419, "fused:1:16,64": 13307046}
-TRAFFIC_DIGEST = "2a83c9dc3a5931a16c1ba401c11015e66b583b9da1ddbbe05686fd34c7b9ee01"
+TRAFFIC_DIGEST = "4cd3034e1cb59f59f5e5d883526f806bc4700707bf431242f63e6a2a3c86c2d9"
 
 
 def cpu_model() -> str:
