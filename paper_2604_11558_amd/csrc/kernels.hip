@@ -74,7 +74,7 @@ __device__ __forceinline__ float phi2_t(float x) {
 
 // Workgroup of 4 SK waves computes a TM x TN tile of C; wave w owns the
 // (TM/2) x (TN/2) quarter w % 4 of the tile, made of 16x16 MFMA blocks, over
-// every SK-th k-step starting at w / 4.  The K range is walked in chunks of
+// the (w / 4)-th of SK contiguous ranges of K.  The K range is walked in chunks of
 // KC staged through LDS (k-major so MFMA operand reads are unit-stride
 // across lanes); the global loads of the next chunk are issued before the
 // MFMAs of the current one, so their latency overlaps the products instead
