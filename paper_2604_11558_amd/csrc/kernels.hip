@@ -389,33 +389,9 @@ template hipError_t launch_mode_gemm<double>(const GemmArgs&, hipStream_t);
 template hipError_t launch_mode_gemm<float>(const GemmArgs&, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Stencil + reaction: one thread per grid point of one instance; all species
-// of the point are handled together because the reaction couples them.
-template <typename T>
-__global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
-  const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
-  const int npts = n1 * n2 * n3;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int inst = blockIdx.y;
-  if (p >= npts) return;
-  const int i = p % n1;
-  const int j = (p / n1) % n2;
-  const int k = p / (n1 * n2);
-  const int ns = a.nspecies;
-  const T* Wi = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * ns * npts;
-  T* F = static_cast<T*>(a.F) + static_cast<int64_t>(inst) * ns * npts;
-  double G[3] = {0, 0, 0};
-  if (a.what != 1 && a.reaction != 0) {
-    double w[3] = {0, 0, 0};
-    for (int sp = 0; sp < ns && sp < 3; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
-    reaction_dev(a, inst, w, G);
-  }
-  for (int sp = 0; sp < ns; ++sp) {
-    double f = a.what != 2 ? diffusion_dev<T>(a, Wi, inst, sp, p, i, j, k) : 0.0;
-    if (a.what != 1 && sp < 3) f += G[sp];
-    F[sp * npts + p] = static_cast<T>(f);
-  }
-}
+// Stencil + reaction (stencil_fast_kernel below): one thread per grid point
+// of one instance; all species of the point are handled together because
+// the reaction couples them.
 
 // Bulk-surface exchange terms (see CoupleArgs) at point p = i + n1 q of this
 // side; du, dv are this side's deviations there.
