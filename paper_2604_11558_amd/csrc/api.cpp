@@ -94,13 +94,6 @@ double bf16_value(uint16_t b) {
 
 int bf16_terms(int precision) { return precision == TG_BF16X2 ? 2 : (precision == TG_BF16X3 ? 3 : 0); }
 
-std::vector<double> transpose(const std::vector<double>& A, int n) {
-  std::vector<double> B(A.size());
-  for (int r = 0; r < n; ++r)
-    for (int c = 0; c < n; ++c) B[c * n + r] = A[r * n + c];
-  return B;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1194,7 +1187,6 @@ void adjoint_impl(tg_plan_s* P, const void* state, void* lam, double* grad, hipS
   void* tbuf[2] = {w + 4 * bytes, w + 5 * bytes};
   void* MU = w + 6 * bytes;
   void* MTMU = w + 7 * bytes;
-  const int nslab = P->nslab;
   const int64_t npts = P->npts;
 
   // F = d M W + g(W) and d M W at step n (one launch)
@@ -1378,7 +1370,6 @@ template <typename T>
 void coupled_impl(const Coupled& C, void* ub, void* us, hipStream_t st) {
   tg_plan_s* B = C.bulk;
   tg_plan_s* S = C.surf;
-  const int rb = active_route(B), rs = active_route(S);
   void* fb = !use_fused(B) ? B->scratch[0] : B->scratch[1];
   void* fs = !use_fused(S) ? S->scratch[0] : S->scratch[1];
   tg::StencilArgs ab = stencil_args(B, ub, fb, TG_APPLY_F);
