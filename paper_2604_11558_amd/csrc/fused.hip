@@ -975,6 +975,107 @@ void strided_kernel(StridedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Multi-tile form of the strided launches without an in-tile stencil or a
+// plane tail (the same products and rounding as strided_tile): a tile is a
+// few microseconds of load and barrier latency around a fraction of a
+// microsecond of MFMA work, so a workgroup walks a run of consecutive tiles,
+// loading the next tile into registers while the current one is
+// multiplied; the factor rows of a wave stay in registers while the slab is
+// unchanged.  Wave w owns rows 16 w .. 16 w + 15 (NP = 16 KCH rows, KCH
+// waves) and all TN = 16 FN columns; a thread loads EPT = 4 FN rows of one
+// column.  The data tile is double-buffered: one barrier per tile for a
+// single product, two for a sandwich.
+template <typename T, int KCH, int FN, int SW>
+__global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
+  constexpr int NW = KCH, NTH = 64 * NW, NP = 16 * KCH, TN = 16 * FN, EPT = 4 * FN, LD = TN + 4;
+  using acc_t = typename M16<T>::acc;
+  using v4 = typename M16<T>::v4;
+  extern __shared__ __align__(256) unsigned char smem[];
+  T* const sX = reinterpret_cast<T*>(smem);  // two buffers of NP x LD
+  T* const sT = sX + 2 * NP * LD;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, na = a.na, nb = a.nb;
+  const int nbx = (na + TN - 1) / TN;
+  const int per_slab = nbx * nb;
+  const int64_t total = static_cast<int64_t>(per_slab) * a.nslab;
+  // logical workgroup w is XCD-major (blockIdx round-robins over the 8
+  // XCDs), so one XCD's runs are adjacent; run w = [total w / G, total (w + 1) / G)
+  const int G = gridDim.x, per_xcd = G / 8;
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int lo = static_cast<int>(total * w / G), hi = static_cast<int>(total * (w + 1) / G);
+  if (lo >= hi) return;
+  const int lc = tid % TN, lk = (tid / TN) * EPT;
+  const int r0 = 16 * wave;
+  const T* X = static_cast<const T*>(a.X);
+  T* Y = static_cast<T*>(a.Y);
+  const int64_t slab = static_cast<int64_t>(nm) * na * nb;
+
+  T pre[EPT];
+  auto fetch = [&](int L) {
+    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    const T* x = X + s * slab + static_cast<int64_t>(b) * nm * na + a0 + lc;
+    const bool col = a0 + lc < na;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) pre[i] = (col && lk + i < nm) ? x[static_cast<int64_t>(lk + i) * na] : T(0);
+  };
+  fetch(lo);
+
+  v4 f1[1][KCH], f2[1][SW ? KCH : 1];
+  double fr[1][4];
+  if (a.phi) row_factors<T, 1>(fr, a.ph.pm, r0, g, nm, 0);
+  int scur = -1;
+  int buf = 0;
+  for (int L = lo; L < hi; ++L, buf ^= 1) {
+    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    T* const sb = sX + buf * NP * LD;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) sb[(lk + i) * LD + lc] = pre[i];
+    if (L + 1 < hi) fetch(L + 1);
+    if (s != scur) {
+      scur = s;
+      load_rows_u<T, 1, KCH>(f1, factor_of<T>(a.L1, s), a.L1.ld, r0, lane);
+      if constexpr (SW) load_rows_u<T, 1, KCH>(f2, factor_of<T>(a.L2, s), a.L2.ld, r0, lane);
+    }
+    double fc[FN];
+    double cb = 0.0;
+    if (a.phi) {
+      cb = a.ph.cs[s] * (a.ph.pb ? a.ph.pb[b] : 1.0);
+      col_factors<FN>(fc, a.ph.pn, 0, li, na - a0, a0);
+    }
+    __syncthreads();
+
+    acc_t acc[1][FN];
+    zero<T, 1, FN>(acc);
+    mma_rows_sB<T, 1, FN, KCH>(acc, f1, sb, LD, 0, lane);
+    T* const y = Y + s * slab + static_cast<int64_t>(b) * nm * na + a0;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + M16<T>::row(g, r), col = 16 * j + li;
+        T v = acc[0][j][r];
+        const bool in = row < nm && a0 + col < na;
+        if (a.phi) v *= M16<T>::phi1(static_cast<T>(cb * fr[0][r] * fc[j]));
+        if (SW) sT[row * LD + col] = in ? v : T(0);
+        else if (in) y[static_cast<int64_t>(row) * na + col] = v;
+      }
+    if constexpr (SW) {
+      __syncthreads();
+      zero<T, 1, FN>(acc);
+      mma_rows_sB<T, 1, FN, KCH>(acc, f2, sT, LD, 0, lane);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + M16<T>::row(g, r), col = 16 * j + li;
+          if (row < nm && a0 + col < na) y[static_cast<int64_t>(row) * na + col] = acc[0][j][r];
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One tile of a first-mode launch: rows bx * tm .., slab by.
 template <typename T, int FM, int FN, int KCH, bool DG = true>
 __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, unsigned char* smem) {
@@ -1231,6 +1332,31 @@ static hipError_t with_svar(int v, F&& f) {
   }
 }
 
+// Multi-tile launches: as many workgroups as fit on the device at once (at
+// most one per tile), a multiple of 8 for the XCD-major run order.
+template <typename T, int KCH, int FN, int SW>
+static hipError_t go_strided_mt(const StridedArgs& a, hipStream_t s) {
+  auto k = strided_mt_kernel<T, KCH, FN, SW>;
+  constexpr int threads = 64 * KCH;
+  constexpr size_t lds = static_cast<size_t>(2 + SW) * 16 * KCH * (16 * FN + 4) * sizeof(T);
+  static int fit = 0;
+  if (fit == 0) {
+    hipError_t e = allow_lds(k, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidValue;
+    fit = per_cu * cus;
+  }
+  const int64_t total = static_cast<int64_t>((a.na + 16 * FN - 1) / (16 * FN)) * a.nb * a.nslab;
+  if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
+  const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_strided(const StridedArgs& a, hipStream_t s) {
   if (a.nm <= 0 || a.na <= 0 || a.nb <= 0 || a.nslab <= 0 || a.nb > 65535 || a.nslab > 65535)
@@ -1248,6 +1374,14 @@ hipError_t launch_strided(const StridedArgs& a, hipStream_t s) {
   if (b.dg.part) {  // indicators: plane-tail updates, one partial pair per tile
     b.dg.tiles = (a.na + a.tn - 1) / a.tn * a.nb;
     if (!a.plane || !a.update || b.dg.tiles > b.dg.cap) return hipErrorInvalidValue;
+  }
+  if (!a.stencil && !a.plane && !b.dg.part && pick_kch(a.nm) > 0 && (a.tn == 16 || a.tn == 32)) {
+    const bool k8 = pick_kch(a.nm) == 8;
+    if (a.tn == 16)
+      return a.sandwich ? (k8 ? go_strided_mt<T, 8, 1, 1>(a, s) : go_strided_mt<T, 4, 1, 1>(a, s))
+                        : (k8 ? go_strided_mt<T, 8, 1, 0>(a, s) : go_strided_mt<T, 4, 1, 0>(a, s));
+    return a.sandwich ? (k8 ? go_strided_mt<T, 8, 2, 1>(a, s) : go_strided_mt<T, 4, 2, 1>(a, s))
+                      : (k8 ? go_strided_mt<T, 8, 2, 0>(a, s) : go_strided_mt<T, 4, 2, 0>(a, s));
   }
   hipError_t e = with_svar(v, [&]<int FM, int FN, int KCH, int NW>() -> hipError_t {
     auto k = strided_kernel<T, FM, FN, KCH, NW>;

@@ -41,7 +41,7 @@ __device__ __forceinline__ float phi1f(float x) { return phi1_f32(x); }
 
 // LDS pitch (bf16 elements) of a k-contiguous row of NP values: the byte
 // stride 2 NP + 16 puts 8 consecutive rows on distinct 16-byte bank groups.
-__host__ __device__ inline int pitch_k(int np) { return np + 8; }
+__host__ __device__ constexpr int pitch_k(int np) { return np + 8; }
 
 // acc[f][j] += sum_k A(r0 + 16 f + li, k) B(k, c0 + 16 j + li) over the
 // term pairs i + j < NT.  A: rows of a split factor in global memory
@@ -337,6 +337,182 @@ __global__ __launch_bounds__(64 * NW) void strided_bf16_kernel(StridedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Strided mode, multi-tile form for launches without an in-tile stencil or
+// plane tail (the same products, the same rounding as strided_bf16_kernel).
+// A tile of one of these launches is a few microseconds of latency and a
+// fraction of a microsecond of MFMA work, so here a workgroup walks a run of
+// consecutive tiles: the next tile's values are loaded into registers while
+// the current one is multiplied, and the factor rows a wave multiplies stay
+// in registers while the slab does not change.  Wave w owns rows
+// 16 w .. 16 w + 15 of every product and all TN = 16 FN columns; a thread
+// loads EPT = 4 FN consecutive rows of one column and stores their terms
+// with one LDS write per term.  The data tile is double-buffered (one
+// barrier per tile for a single product, two for a sandwich).
+template <int NT, int KB, int FN, int SW>
+__global__ __launch_bounds__(128 * KB) void strided_bf16_mt_kernel(StridedArgs a) {
+  constexpr int NW = 2 * KB, NTH = 64 * NW, NP = 32 * KB, TN = 16 * FN, EPT = 4 * FN;
+  constexpr int LDK = NP + 8, TSTR = TN * LDK;
+  extern __shared__ __align__(256) unsigned char smem[];
+  __bf16* const sX = reinterpret_cast<__bf16*>(smem);  // two buffers of NT terms
+  __bf16* const sT = sX + 2 * NT * TSTR;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, na = a.na, nb = a.nb;
+  const int nbx = (na + TN - 1) / TN;
+  const int per_slab = nbx * nb;
+  const int64_t total = static_cast<int64_t>(per_slab) * a.nslab;
+  // logical workgroup w = XCD-major (blockIdx round-robins over 8 XCDs), so
+  // the runs of one XCD are adjacent tiles; run w = [total w / G, total (w+1) / G)
+  const int G = gridDim.x, per_xcd = G / 8;
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int lo = static_cast<int>(total * w / G), hi = static_cast<int>(total * (w + 1) / G);
+  if (lo >= hi) return;
+  const int lc = tid % TN, lk = (tid / TN) * EPT;  // this thread's loads
+  const int r0 = 16 * wave;                          // this wave's rows
+  const float* X = static_cast<const float*>(a.X);
+  float* Y = static_cast<float*>(a.Y);
+  const int64_t slab = static_cast<int64_t>(nm) * na * nb;
+
+  float pre[EPT];
+  auto fetch = [&](int L) {
+    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    const float* x = X + s * slab + static_cast<int64_t>(b) * nm * na + a0 + lc;
+    const bool col = a0 + lc < na;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) pre[i] = (col && lk + i < nm) ? x[static_cast<int64_t>(lk + i) * na] : 0.0f;
+  };
+  fetch(lo);
+
+  bx8 f1[KB][NT], f2[SW ? KB : 1][NT];
+  double pmr[4];
+  int scur = -1;
+  double csl = 0.0;
+  int buf = 0;
+  for (int L = lo; L < hi; ++L, buf ^= 1) {
+    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    __bf16* const sb = sX + buf * NT * TSTR;
+    {  // the prefetched rows lk .. lk + EPT - 1 of column lc, one write per term
+      __bf16 t[EPT][NT];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) split_terms<NT>(pre[i], t[i]);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        if constexpr (EPT == 4) {
+          bx4 v = {t[0][q], t[1][q], t[2][q], t[3][q]};
+          *reinterpret_cast<bx4*>(sb + q * TSTR + lc * LDK + lk) = v;
+        } else {
+          bx8 v = {t[0][q], t[1][q], t[2][q], t[3][q], t[4][q], t[5][q], t[6][q], t[7][q]};
+          *reinterpret_cast<bx8*>(sb + q * TSTR + lc * LDK + lk) = v;
+        }
+      }
+    }
+    if (L + 1 < hi) fetch(L + 1);
+    if (s != scur) {  // this slab's factor rows r0 + li, k = 32 kb + 8 g .. + 7
+      scur = s;
+      const __bf16* A1 = bf_factor(a.L1, s);
+      const int64_t t1 = static_cast<int64_t>(a.L1.ld) * a.L1.ld;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          f1[kb][t] = *reinterpret_cast<const bx8*>(A1 + t * t1 + static_cast<int64_t>(r0 + li) * a.L1.ld + 32 * kb + 8 * g);
+      if constexpr (SW) {
+        const __bf16* A2 = bf_factor(a.L2, s);
+        const int64_t t2 = static_cast<int64_t>(a.L2.ld) * a.L2.ld;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            f2[kb][t] =
+                *reinterpret_cast<const bx8*>(A2 + t * t2 + static_cast<int64_t>(r0 + li) * a.L2.ld + 32 * kb + 8 * g);
+      }
+      if (a.phi) {
+        csl = a.ph.cs[s];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pmr[r] = a.ph.pm ? a.ph.pm[min(r0 + 4 * g + r, nm - 1)] : 1.0;
+      }
+    }
+    float ph[FN][4];
+    if (a.phi) {
+      const double cb = csl * (a.ph.pb ? a.ph.pb[b] : 1.0);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const double pn = a.ph.pn ? a.ph.pn[min(a0 + 16 * j + li, na - 1)] : 1.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double x = cb;
+          if (a.ph.pm) x *= pmr[r];
+          if (a.ph.pn) x *= pn;
+          ph[j][r] = phi1f(static_cast<float>(x));
+        }
+      }
+    }
+    __syncthreads();
+
+    fx4 acc[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[j] = fx4{0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      bx8 v[FN][NT];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          v[j][t] = *reinterpret_cast<const bx8*>(sb + t * TSTR + (16 * j + li) * LDK + 32 * kb + 8 * g);
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < NT - ta; ++tb)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[j] = mfma_bf16(f1[kb][ta], v[j][tb], acc[j]);
+    }
+    float* const y = Y + s * slab + static_cast<int64_t>(b) * nm * na + a0;
+    const int rb = r0 + 4 * g;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = 16 * j + li;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool in = rb + r < nm && a0 + col < na;
+        v[r] = acc[j][r] * (a.phi ? ph[j][r] : 1.0f);
+        if (!in) v[r] = 0.0f;
+        if (!SW && in) y[static_cast<int64_t>(rb + r) * na + col] = v[r];
+      }
+      if (SW) put4_kcontig<NT>(sT, TSTR, LDK, col, rb, v);
+    }
+    if constexpr (SW) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[j] = fx4{0, 0, 0, 0};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        bx8 v[FN][NT];
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            v[j][t] = *reinterpret_cast<const bx8*>(sT + t * TSTR + (16 * j + li) * LDK + 32 * kb + 8 * g);
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < NT - ta; ++tb)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[j] = mfma_bf16(f2[kb][ta], v[j][tb], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * j + li;
+          if (rb + r < nm && a0 + col < na) y[static_cast<int64_t>(rb + r) * na + col] = acc[j][r];
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // First mode: data tile rows (k-contiguous) of NT terms.
 template <int NT, int FM, int FN, int KB>
 __global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
@@ -483,9 +659,42 @@ static hipError_t go_sbf(const StridedArgs& a, size_t lds, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Multi-tile launches: as many workgroups as fit on the device at once (at
+// most one per tile), a multiple of 8 for the XCD-major run order.
+template <int NT, int KB, int FN, int SW>
+static hipError_t go_sbf_mt(const StridedArgs& a, hipStream_t s) {
+  auto k = strided_bf16_mt_kernel<NT, KB, FN, SW>;
+  constexpr int threads = 128 * KB;
+  constexpr size_t lds = static_cast<size_t>(2 + SW) * NT * 16 * FN * pitch_k(32 * KB) * 2;
+  static int fit = 0;
+  if (fit == 0) {
+    hipError_t e = bf_allow(k, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidValue;
+    fit = per_cu * cus;
+  }
+  const int64_t total = static_cast<int64_t>((a.na + 16 * FN - 1) / (16 * FN)) * a.nb * a.nslab;
+  if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
+  const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NT, int KB>
+static hipError_t sbf_mt(const StridedArgs& a, hipStream_t s) {
+  if (a.tn == 16) return a.sandwich ? go_sbf_mt<NT, KB, 1, 1>(a, s) : go_sbf_mt<NT, KB, 1, 0>(a, s);
+  return a.sandwich ? go_sbf_mt<NT, KB, 2, 1>(a, s) : go_sbf_mt<NT, KB, 2, 0>(a, s);
+}
+
 template <int NT>
 static hipError_t sbf_dispatch(const StridedArgs& a, size_t lds, hipStream_t s) {
   const int kb = bf_kb(a.nm);
+  if (!a.stencil && !a.plane && !a.dg.part && (a.tn == 16 || a.tn == 32) && kb > 0)
+    return kb == 2 ? sbf_mt<NT, 2>(a, s) : sbf_mt<NT, 4>(a, s);
   const bool fn2 = a.tn % 32 == 0;
   // 8 waves where a tile has 8 or more 16-wide sub-tiles (more waves per
   // SIMD to overlap the latencies of the few workgroups of these launches)
