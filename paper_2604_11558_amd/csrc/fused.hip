@@ -1193,6 +1193,120 @@ __device__ __forceinline__ void first_tile(const FirstArgs& a, int bx, int by, u
   flush();
 }
 
+// Multi-tile form of the single first-mode product (no sandwich, no
+// indicators), with or without the update W += alpha Z: the same products
+// and rounding as first_tile.  A workgroup walks a run of consecutive row
+// tiles; the next tile's rows (and the state values its update adds to)
+// are loaded into registers while the current one is multiplied, and each
+// wave keeps the factor rows of its 32 output columns in registers while
+// the slab is unchanged.  TM = 16 FM rows per tile, NP = 16 KCH columns,
+// KCH / 2 waves.
+template <typename T, int KCH, int FM>
+__global__ __launch_bounds__(32 * KCH) void first_mt_kernel(FirstArgs a) {
+  constexpr int FN = 2, NW = KCH / 2, NTH = 64 * NW, NP = 16 * KCH, TM = 16 * FM, LD = NP + 4;
+  constexpr int VPT = TM * NP / 4 / NTH;  // 4-element groups per thread
+  using acc_t = typename M16<T>::acc;
+  using v4 = typename M16<T>::v4;
+  extern __shared__ __align__(256) unsigned char smem[];
+  T* const sX = reinterpret_cast<T*>(smem);  // two buffers of TM x LD
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, rows = a.rows;
+  const int nrt = (rows + TM - 1) / TM;
+  const int64_t total = static_cast<int64_t>(nrt) * a.nslab;
+  const int G = gridDim.x, per_xcd = G / 8;
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int lo = static_cast<int>(total * w / G), hi = static_cast<int>(total * (w + 1) / G);
+  if (lo >= hi) return;
+  const int c0 = 32 * wave;
+  const bool vec = nm % 4 == 0;
+  const T* X = static_cast<const T*>(a.X);
+  T* Y = static_cast<T*>(a.Y);
+  const T alpha = static_cast<T>(a.alpha);
+  const int64_t slab = static_cast<int64_t>(rows) * nm;
+
+  v4 pre[VPT];
+  T yn[FM][FN][4];
+  auto fetch = [&](int L) {
+    const int s = L / nrt, rt0 = (L % nrt) * TM;
+    const T* x = X + s * slab;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int e = 4 * (tid + NTH * q), r = e / NP, c = e % NP;
+      const int64_t off = static_cast<int64_t>(rt0 + r) * nm + c;
+      const bool rin = rt0 + r < rows;
+      if (vec) {
+        pre[q] = (rin && c < nm) ? *reinterpret_cast<const v4*>(x + off) : v4{0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pre[q][u] = (rin && c + u < nm) ? x[off + u] : T(0);
+      }
+    }
+    if (a.update) {
+      const T* y = Y + s * slab;
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rg = min(rt0 + 16 * f + M16<T>::row(g, r), rows - 1);
+            const int col = min(c0 + 16 * j + li, nm - 1);
+            yn[f][j][r] = y[static_cast<int64_t>(rg) * nm + col];
+          }
+    }
+  };
+  fetch(lo);
+
+  v4 fb[FN][KCH];
+  int scur = -1;
+  int buf = 0;
+  for (int L = lo; L < hi; ++L, buf ^= 1) {
+    const int s = L / nrt, rt0 = (L % nrt) * TM;
+    T* const sb = sX + buf * TM * LD;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int e = 4 * (tid + NTH * q), r = e / NP, c = e % NP;
+      *reinterpret_cast<v4*>(sb + r * LD + c) = pre[q];
+    }
+    T yv[FM][FN][4];
+    if (a.update) {
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yv[f][j][r] = yn[f][j][r];
+    }
+    if (L + 1 < hi) fetch(L + 1);
+    if (s != scur) {
+      scur = s;
+      load_cols_u<T, FN, KCH>(fb, factor_of<T>(a.L1, s), a.L1.ld, c0, lane);
+    }
+    __syncthreads();
+
+    acc_t acc[FM][FN];
+    zero<T, FM, FN>(acc);
+    mma_sA_cols<T, FM, FN, KCH>(acc, sb, LD, 0, fb, lane);
+    T* const y = Y + s * slab;
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rg = rt0 + 16 * f + M16<T>::row(g, r), col = c0 + 16 * j + li;
+          const T nv = a.update ? yv[f][j][r] + alpha * acc[f][j][r] : acc[f][j][r];
+          if (rg < rows && col < nm) {
+            y[static_cast<int64_t>(rg) * nm + col] = nv;
+            bad |= !isfinite(nv);
+          }
+        }
+    if (bad && a.update && a.flag) atomicOr(a.flag, 1);
+  }
+}
+
 template <typename T, int FM, int FN, int KCH>
 __global__ __launch_bounds__(256) void first_kernel(FirstArgs a) {
   extern __shared__ __align__(256) unsigned char smem[];
@@ -1407,6 +1521,29 @@ static hipError_t go_first(const FirstArgs& a, size_t lds, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int KCH, int FM>
+static hipError_t go_first_mt(const FirstArgs& a, hipStream_t s) {
+  auto k = first_mt_kernel<T, KCH, FM>;
+  constexpr int threads = 32 * KCH;
+  constexpr size_t lds = static_cast<size_t>(2) * 16 * FM * (16 * KCH + 4) * sizeof(T);
+  static int fit = 0;
+  if (fit == 0) {
+    hipError_t e = allow_lds(k, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidValue;
+    fit = per_cu * cus;
+  }
+  const int64_t total = static_cast<int64_t>((a.rows + 16 * FM - 1) / (16 * FM)) * a.nslab;
+  if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
+  const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_first(const FirstArgs& a, hipStream_t s) {
   if (a.nm <= 0 || a.rows <= 0 || a.nslab <= 0 || a.nslab > 65535) return hipErrorInvalidValue;
@@ -1421,6 +1558,14 @@ hipError_t launch_first(const FirstArgs& a, hipStream_t s) {
     if (!a.update || b.dg.tiles > b.dg.cap) return hipErrorInvalidValue;
   }
   const int kch = pick_kch(a.nm);
+  // multi-tile for FP32 only (measured: the FP64 single-tile kernel with
+  // 32-row tiles is faster than either multi-tile FP64 form)
+  if constexpr (sizeof(T) == 4) {
+    if (!a.sandwich && !b.dg.part && kch > 0) {
+      if (a.tm == 16) return kch == 4 ? go_first_mt<T, 4, 1>(a, s) : go_first_mt<T, 8, 1>(a, s);
+      return kch == 4 ? go_first_mt<T, 4, 2>(a, s) : go_first_mt<T, 8, 2>(a, s);
+    }
+  }
   hipError_t e;
   if (a.tm == 16) {
     if (kch == 4) e = go_first<T, 1, 2, 4>(b, lds, s);

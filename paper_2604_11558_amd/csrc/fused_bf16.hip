@@ -622,6 +622,149 @@ __global__ __launch_bounds__(256) void first_bf16_kernel(FirstArgs a) {
   flush();
 }
 
+// Multi-tile form of the single first-mode product (no sandwich, no
+// indicators), with or without the update: the same products and rounding
+// as first_bf16_kernel.  A workgroup walks a run of consecutive row tiles,
+// loading the next tile's rows and the state values of its update into
+// registers while the current one is multiplied; each wave keeps the split
+// factor rows of its 32 output columns in registers while the slab is
+// unchanged.  TM = 16 FM rows, NP = 32 KB columns, KB waves.
+template <int NT, int KB, int FM>
+__global__ __launch_bounds__(64 * KB) void first_bf16_mt_kernel(FirstArgs a) {
+  constexpr int FN = 2, NW = KB, NTH = 64 * NW, NP = 32 * KB, TM = 16 * FM, LDK = NP + 8, TSTR = TM * LDK;
+  constexpr int VPT = TM * NP / 4 / NTH;  // 4-element groups per thread
+  extern __shared__ __align__(256) unsigned char smem[];
+  __bf16* const sX = reinterpret_cast<__bf16*>(smem);  // two buffers of NT terms
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nm = a.nm, rows = a.rows;
+  const int nrt = (rows + TM - 1) / TM;
+  const int64_t total = static_cast<int64_t>(nrt) * a.nslab;
+  const int G = gridDim.x, per_xcd = G / 8;
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int lo = static_cast<int>(total * w / G), hi = static_cast<int>(total * (w + 1) / G);
+  if (lo >= hi) return;
+  const int c0 = 32 * wave;
+  const bool vec = nm % 4 == 0;
+  const float* X = static_cast<const float*>(a.X);
+  float* Y = static_cast<float*>(a.Y);
+  const float alpha = static_cast<float>(a.alpha);
+  const int64_t slab = static_cast<int64_t>(rows) * nm;
+
+  fx4 pre[VPT];
+  float yn[FM][FN][4];
+  auto fetch = [&](int L) {
+    const int s = L / nrt, rt0 = (L % nrt) * TM;
+    const float* x = X + s * slab;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int e = 4 * (tid + NTH * q), r = e / NP, c = e % NP;
+      const int64_t off = static_cast<int64_t>(rt0 + r) * nm + c;
+      const bool rin = rt0 + r < rows;
+      if (vec) {
+        pre[q] = (rin && c < nm) ? *reinterpret_cast<const fx4*>(x + off) : fx4{0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pre[q][u] = (rin && c + u < nm) ? x[off + u] : 0.0f;
+      }
+    }
+    if (a.update) {
+      const float* y = Y + s * slab;
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rg = min(rt0 + 16 * f + 4 * g + r, rows - 1);
+            const int col = min(c0 + 16 * j + li, nm - 1);
+            yn[f][j][r] = y[static_cast<int64_t>(rg) * nm + col];
+          }
+    }
+  };
+  fetch(lo);
+
+  bx8 fb[KB][FN][NT];
+  int scur = -1;
+  int buf = 0;
+  for (int L = lo; L < hi; ++L, buf ^= 1) {
+    const int s = L / nrt, rt0 = (L % nrt) * TM;
+    __bf16* const sb = sX + buf * NT * TSTR;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int e = 4 * (tid + NTH * q), r = e / NP, c = e % NP;
+      __bf16 t[4][NT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) split_terms<NT>(pre[q][u], t[u]);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        bx4 v = {t[0][k], t[1][k], t[2][k], t[3][k]};
+        *reinterpret_cast<bx4*>(sb + k * TSTR + r * LDK + c) = v;
+      }
+    }
+    float yv[FM][FN][4];
+    if (a.update) {
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yv[f][j][r] = yn[f][j][r];
+    }
+    if (L + 1 < hi) fetch(L + 1);
+    if (s != scur) {  // factor rows c0 + 16 j + li, k = 32 kb + 8 g .. + 7
+      scur = s;
+      const __bf16* B = bf_factor(a.L1, s);
+      const int64_t t1 = static_cast<int64_t>(a.L1.ld) * a.L1.ld;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            fb[kb][j][t] = *reinterpret_cast<const bx8*>(B + t * t1 + static_cast<int64_t>(c0 + 16 * j + li) * a.L1.ld +
+                                                         32 * kb + 8 * g);
+    }
+    __syncthreads();
+
+    fx4 acc[FM][FN];
+    zero_acc<FM, FN>(acc);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      bx8 av[FM][NT];
+#pragma unroll
+      for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          av[f][t] = *reinterpret_cast<const bx8*>(sb + t * TSTR + (16 * f + li) * LDK + 32 * kb + 8 * g);
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < NT - ta; ++tb)
+#pragma unroll
+          for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[f][j] = mfma_bf16(av[f][ta], fb[kb][j][tb], acc[f][j]);
+    }
+    float* const y = Y + s * slab;
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rg = rt0 + 16 * f + 4 * g + r, col = c0 + 16 * j + li;
+          const float nv = a.update ? yv[f][j][r] + alpha * acc[f][j][r] : acc[f][j][r];
+          if (rg < rows && col < nm) {
+            y[static_cast<int64_t>(rg) * nm + col] = nv;
+            bad |= !isfinite(nv);
+          }
+        }
+    if (bad && a.update && a.flag) atomicOr(a.flag, 1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 static int bf_np_strided(int nm) { return nm <= 64 ? 64 : (nm <= 128 ? 128 : (nm + 63) / 64 * 64); }
 static int bf_np_first(int nm) { return nm <= 64 ? 64 : (nm <= 128 ? 128 : (nm + 31) / 32 * 32); }
@@ -740,9 +883,36 @@ static hipError_t go_fbf(const FirstArgs& a, size_t lds, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NT, int KB, int FM>
+static hipError_t go_fbf_mt(const FirstArgs& a, hipStream_t s) {
+  auto k = first_bf16_mt_kernel<NT, KB, FM>;
+  constexpr int threads = 64 * KB;
+  constexpr size_t lds = static_cast<size_t>(2) * NT * 16 * FM * pitch_k(32 * KB) * 2;
+  static int fit = 0;
+  if (fit == 0) {
+    hipError_t e = bf_allow(k, lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidValue;
+    fit = per_cu * cus;
+  }
+  const int64_t total = static_cast<int64_t>((a.rows + 16 * FM - 1) / (16 * FM)) * a.nslab;
+  if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
+  const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int NT>
 static hipError_t fbf_dispatch(const FirstArgs& a, size_t lds, hipStream_t s) {
   const int kb = bf_kb(a.nm);
+  if (!a.sandwich && !a.dg.part && kb > 0) {
+    if (a.tm == 16) return kb == 2 ? go_fbf_mt<NT, 2, 1>(a, s) : go_fbf_mt<NT, 4, 1>(a, s);
+    return kb == 2 ? go_fbf_mt<NT, 2, 2>(a, s) : go_fbf_mt<NT, 4, 2>(a, s);
+  }
   if (a.tm == 16) {
     if (kb == 2) return go_fbf<NT, 1, 2, 2>(a, lds, s);
     if (kb == 4) return go_fbf<NT, 1, 2, 4>(a, lds, s);
