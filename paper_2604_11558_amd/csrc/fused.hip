@@ -978,10 +978,11 @@ void strided_kernel(StridedArgs a) {
 // Multi-tile form of the strided launches without an in-tile stencil or a
 // plane tail (the same products and rounding as strided_tile): a tile is a
 // few microseconds of load and barrier latency around a fraction of a
-// microsecond of MFMA work, so a workgroup walks a run of consecutive tiles,
-// loading the next tile into registers while the current one is
-// multiplied; the factor rows of a wave stay in registers while the slab is
-// unchanged.  Wave w owns rows 16 w .. 16 w + 15 (NP = 16 KCH rows, KCH
+// microsecond of MFMA work, so a workgroup walks a run of consecutive tiles
+// (row block b fastest, then the column tile, then the slab), loading the
+// next tile into registers while the current one is multiplied; the factor
+// rows of a wave stay in registers while the slab is unchanged, and the
+// phi_1 factors while the column tile is (unless they depend on b).  Wave w owns rows 16 w .. 16 w + 15 (NP = 16 KCH rows, KCH
 // waves) and all TN = 16 FN columns; a thread loads EPT = 4 FN rows of one
 // column.  The data tile is double-buffered: one barrier per tile for a
 // single product, two for a sandwich.
@@ -1013,7 +1014,7 @@ __global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
 
   T pre[EPT];
   auto fetch = [&](int L) {
-    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    const int s = L / per_slab, rest = L % per_slab, b = rest % nb, a0 = (rest / nb) * TN;
     const T* x = X + s * slab + static_cast<int64_t>(b) * nm * na + a0 + lc;
     const bool col = a0 + lc < na;
 #pragma unroll
@@ -1024,10 +1025,11 @@ __global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
   v4 f1[1][KCH], f2[1][SW ? KCH : 1];
   double fr[1][4];
   if (a.phi) row_factors<T, 1>(fr, a.ph.pm, r0, g, nm, 0);
-  int scur = -1;
+  T ph[FN][4];
+  int scur = -1, phs = -1, pha = -1;
   int buf = 0;
   for (int L = lo; L < hi; ++L, buf ^= 1) {
-    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    const int s = L / per_slab, rest = L % per_slab, b = rest % nb, a0 = (rest / nb) * TN;
     T* const sb = sX + buf * NP * LD;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) sb[(lk + i) * LD + lc] = pre[i];
@@ -1037,11 +1039,17 @@ __global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
       load_rows_u<T, 1, KCH>(f1, factor_of<T>(a.L1, s), a.L1.ld, r0, lane);
       if constexpr (SW) load_rows_u<T, 1, KCH>(f2, factor_of<T>(a.L2, s), a.L2.ld, r0, lane);
     }
-    double fc[FN];
-    double cb = 0.0;
-    if (a.phi) {
-      cb = a.ph.cs[s] * (a.ph.pb ? a.ph.pb[b] : 1.0);
+    // phi_1 factors: the same for every row block b unless pb scales them
+    if (a.phi && (s != phs || a0 != pha || a.ph.pb)) {
+      phs = s;
+      pha = a0;
+      double fc[FN];
+      const double cb = a.ph.cs[s] * (a.ph.pb ? a.ph.pb[b] : 1.0);
       col_factors<FN>(fc, a.ph.pn, 0, li, na - a0, a0);
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ph[j][r] = M16<T>::phi1(static_cast<T>(cb * fr[0][r] * fc[j]));
     }
     __syncthreads();
 
@@ -1056,7 +1064,7 @@ __global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
         const int row = r0 + M16<T>::row(g, r), col = 16 * j + li;
         T v = acc[0][j][r];
         const bool in = row < nm && a0 + col < na;
-        if (a.phi) v *= M16<T>::phi1(static_cast<T>(cb * fr[0][r] * fc[j]));
+        if (a.phi) v *= ph[j][r];
         if (SW) sT[row * LD + col] = in ? v : T(0);
         else if (in) y[static_cast<int64_t>(row) * na + col] = v;
       }

@@ -341,9 +341,11 @@ __global__ __launch_bounds__(64 * NW) void strided_bf16_kernel(StridedArgs a) {
 // plane tail (the same products, the same rounding as strided_bf16_kernel).
 // A tile of one of these launches is a few microseconds of latency and a
 // fraction of a microsecond of MFMA work, so here a workgroup walks a run of
-// consecutive tiles: the next tile's values are loaded into registers while
-// the current one is multiplied, and the factor rows a wave multiplies stay
-// in registers while the slab does not change.  Wave w owns rows
+// consecutive tiles (row block b fastest, then the column tile, then the
+// slab): the next tile's values are loaded into registers while the current
+// one is multiplied, the factor rows a wave multiplies stay in registers
+// while the slab does not change, and so do the phi_1 factors while the
+// column tile does not (unless they depend on b).  Wave w owns rows
 // 16 w .. 16 w + 15 of every product and all TN = 16 FN columns; a thread
 // loads EPT = 4 FN consecutive rows of one column and stores their terms
 // with one LDS write per term.  The data tile is double-buffered (one
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(128 * KB) void strided_bf16_mt_kernel(StridedArgs a
 
   float pre[EPT];
   auto fetch = [&](int L) {
-    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    const int s = L / per_slab, rest = L % per_slab, b = rest % nb, a0 = (rest / nb) * TN;
     const float* x = X + s * slab + static_cast<int64_t>(b) * nm * na + a0 + lc;
     const bool col = a0 + lc < na;
 #pragma unroll
@@ -385,11 +387,12 @@ __global__ __launch_bounds__(128 * KB) void strided_bf16_mt_kernel(StridedArgs a
 
   bx8 f1[KB][NT], f2[SW ? KB : 1][NT];
   double pmr[4];
-  int scur = -1;
+  float ph[FN][4];
+  int scur = -1, phs = -1, pha = -1;
   double csl = 0.0;
   int buf = 0;
   for (int L = lo; L < hi; ++L, buf ^= 1) {
-    const int s = L / per_slab, rest = L % per_slab, b = rest / nbx, a0 = (rest % nbx) * TN;
+    const int s = L / per_slab, rest = L % per_slab, b = rest % nb, a0 = (rest / nb) * TN;
     __bf16* const sb = sX + buf * NT * TSTR;
     {  // the prefetched rows lk .. lk + EPT - 1 of column lc, one write per term
       __bf16 t[EPT][NT];
@@ -432,8 +435,10 @@ __global__ __launch_bounds__(128 * KB) void strided_bf16_mt_kernel(StridedArgs a
         for (int r = 0; r < 4; ++r) pmr[r] = a.ph.pm ? a.ph.pm[min(r0 + 4 * g + r, nm - 1)] : 1.0;
       }
     }
-    float ph[FN][4];
-    if (a.phi) {
+    // phi_1 factors: the same for every row block b unless pb scales them
+    if (a.phi && (s != phs || a0 != pha || a.ph.pb)) {
+      phs = s;
+      pha = a0;
       const double cb = csl * (a.ph.pb ? a.ph.pb[b] : 1.0);
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
