@@ -36,8 +36,8 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11039419, "fused:1:16,64": 13307046}
-TRAFFIC_DIGEST = "4cd3034e1cb59f59f5e5d883526f806bc4700707bf431242f63e6a2a3c86c2d9"
+TRAFFIC = {"fused:0:16,64": 11036111, "fused:1:16,64": 13325570}
+TRAFFIC_DIGEST = "41a593ca342bc32afb529d9479aead7786674056fc32f8b37cbd0925e971fad8"
 
 
 def cpu_model() -> str:
