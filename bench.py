@@ -36,8 +36,8 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11036111, "fused:1:16,64": 13325570}
-TRAFFIC_DIGEST = "41a593ca342bc32afb529d9479aead7786674056fc32f8b37cbd0925e971fad8"
+TRAFFIC = {"fused:0:16,64": 11036238, "fused:1:16,64": 13325577}
+TRAFFIC_DIGEST = "ee5cd52ba0097daabb0c3ea47d07f9f8d4afa1e674e9b988047212368d3faee0"
 
 
 def cpu_model() -> str:

@@ -9,6 +9,9 @@
 // k to (step, group) is valid as long as both operands use the same one).
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "fused.hpp"
 #include "diag_dev.hpp"
@@ -1454,6 +1457,21 @@ static hipError_t with_svar(int v, F&& f) {
   }
 }
 
+int resident_workgroups(const void* kernel, int threads, size_t lds) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, int, size_t>, int> known;
+  const auto key = std::make_tuple(kernel, dev, threads, lds);
+  std::lock_guard<std::mutex> hold(mu);
+  const auto it = known.find(key);
+  if (it != known.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
+  return known[key] = per_cu * cus;
+}
+
 // Multi-tile launches: as many workgroups as fit on the device at once (at
 // most one per tile), a multiple of 8 for the XCD-major run order.
 template <typename T, int KCH, int FN, int SW>
@@ -1461,17 +1479,10 @@ static hipError_t go_strided_mt(const StridedArgs& a, hipStream_t s) {
   auto k = strided_mt_kernel<T, KCH, FN, SW>;
   constexpr int threads = 64 * KCH;
   constexpr size_t lds = static_cast<size_t>(2 + SW) * 16 * KCH * (16 * FN + 4) * sizeof(T);
-  static int fit = 0;
-  if (fit == 0) {
-    hipError_t e = allow_lds(k, lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorInvalidValue;
-    fit = per_cu * cus;
-  }
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  const int fit = resident_workgroups(reinterpret_cast<const void*>(k), threads, lds);
+  if (fit < 1) return hipErrorInvalidValue;
   const int64_t total = static_cast<int64_t>((a.na + 16 * FN - 1) / (16 * FN)) * a.nb * a.nslab;
   if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
@@ -1534,17 +1545,10 @@ static hipError_t go_first_mt(const FirstArgs& a, hipStream_t s) {
   auto k = first_mt_kernel<T, KCH, FM>;
   constexpr int threads = 32 * KCH;
   constexpr size_t lds = static_cast<size_t>(2) * 16 * FM * (16 * KCH + 4) * sizeof(T);
-  static int fit = 0;
-  if (fit == 0) {
-    hipError_t e = allow_lds(k, lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorInvalidValue;
-    fit = per_cu * cus;
-  }
+  hipError_t e = allow_lds(k, lds);
+  if (e != hipSuccess) return e;
+  const int fit = resident_workgroups(reinterpret_cast<const void*>(k), threads, lds);
+  if (fit < 1) return hipErrorInvalidValue;
   const int64_t total = static_cast<int64_t>((a.rows + 16 * FM - 1) / (16 * FM)) * a.nslab;
   if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);

@@ -144,6 +144,12 @@ size_t resident_lds_bytes(int ns, int nm, int na);
 // terms per operand).  Factors are NT-term bf16 stacks: term t of block f at
 // (bf16*) L + f * fstride + t * ld * ld.  A plane launch needs a sandwich
 // and tn == na rounded up to 32.
+// Workgroups of `kernel` (with `threads` threads and `lds` bytes of dynamic
+// LDS) that fit on the current device at once: the occupancy per CU times
+// the CU count, queried once per kernel, shape and device (thread-safe);
+// 0 when the query fails.  Multi-tile launches size their grids with it.
+int resident_workgroups(const void* kernel, int threads, size_t lds);
+
 hipError_t launch_strided_bf16(int nterms, const StridedArgs& a, hipStream_t s);
 hipError_t launch_first_bf16(int nterms, const FirstArgs& a, hipStream_t s);
 size_t strided_bf16_lds_bytes(int nterms, int nm, int na, int tn, int sandwich, int plane);

@@ -814,17 +814,10 @@ static hipError_t go_sbf_mt(const StridedArgs& a, hipStream_t s) {
   auto k = strided_bf16_mt_kernel<NT, KB, FN, SW>;
   constexpr int threads = 128 * KB;
   constexpr size_t lds = static_cast<size_t>(2 + SW) * NT * 16 * FN * pitch_k(32 * KB) * 2;
-  static int fit = 0;
-  if (fit == 0) {
-    hipError_t e = bf_allow(k, lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorInvalidValue;
-    fit = per_cu * cus;
-  }
+  hipError_t e = bf_allow(k, lds);
+  if (e != hipSuccess) return e;
+  const int fit = resident_workgroups(reinterpret_cast<const void*>(k), threads, lds);
+  if (fit < 1) return hipErrorInvalidValue;
   const int64_t total = static_cast<int64_t>((a.na + 16 * FN - 1) / (16 * FN)) * a.nb * a.nslab;
   if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
@@ -893,17 +886,10 @@ static hipError_t go_fbf_mt(const FirstArgs& a, hipStream_t s) {
   auto k = first_bf16_mt_kernel<NT, KB, FM>;
   constexpr int threads = 64 * KB;
   constexpr size_t lds = static_cast<size_t>(2) * NT * 16 * FM * pitch_k(32 * KB) * 2;
-  static int fit = 0;
-  if (fit == 0) {
-    hipError_t e = bf_allow(k, lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, lds)) != hipSuccess) return e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if (per_cu < 1) return hipErrorInvalidValue;
-    fit = per_cu * cus;
-  }
+  hipError_t e = bf_allow(k, lds);
+  if (e != hipSuccess) return e;
+  const int fit = resident_workgroups(reinterpret_cast<const void*>(k), threads, lds);
+  if (fit < 1) return hipErrorInvalidValue;
   const int64_t total = static_cast<int64_t>((a.rows + 16 * FM - 1) / (16 * FM)) * a.nslab;
   if (total >= (int64_t(1) << 30)) return hipErrorInvalidValue;
   const int grid = static_cast<int>((std::min<int64_t>(fit, total) + 7) / 8 * 8);
