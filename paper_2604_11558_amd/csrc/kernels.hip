@@ -449,7 +449,13 @@ __device__ __forceinline__ void exchange(const StencilArgs& a, int inst, int p, 
 }
 
 // Same computation with the mode count and species count fixed at compile
-// time: every neighbour load of every species is issued before use.
+// time, in three stages: every load of the point (its value and its two
+// neighbours along each mode for every species, the operator coefficients
+// and the scale factors of its coordinates) is issued before any
+// arithmetic, then F is evaluated, then stored.  Unscaled coordinates keep
+// the factor 1 without a load (multiplying by it is exact, as skipping it
+// was).  W does not overlap F or F2 (the launcher checks), so no store has
+// to precede a later load.
 // DUAL: also the operator part alone into F2 (what == 3).
 template <typename T, int NDIM, int NS, bool DUAL>
 __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
@@ -462,12 +468,47 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   const int i = p - q * n1;
   const int k = q / n2;
   const int j = q - k * n2;
-  const T* Wi = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * NS * npts;
-  T* F = static_cast<T*>(a.F) + static_cast<int64_t>(inst) * NS * npts;
+  const T* __restrict__ Wi = static_cast<const T*>(a.W) + static_cast<int64_t>(inst) * NS * npts;
+  T* __restrict__ F = static_cast<T*>(a.F) + static_cast<int64_t>(inst) * NS * npts;
   const ReactConst rc = react_const(a, inst);  // uniform constants, requested first
+  const int nm = a.nmax;
+  const int idx[3] = {i, j, k};
+  const int stride[3] = {1, n1, n1 * n2};
+
+  // 1. loads
+  T wc[NS], wlo[NS][NDIM], wup[NS][NDIM];
+  double clo[NDIM], cdg[NDIM], cup[NDIM], sc0[NDIM], sc1[NDIM], sc2[NDIM];
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) wc[sp] = Wi[sp * npts + p];
+#pragma unroll
+  for (int mu = 0; mu < NDIM; ++mu) {
+    const int x = idx[mu];
+    const int nmu = a.n[mu];
+    const bool per = (a.periodic_mask >> mu) & 1;
+    // non-periodic ends have zero lo / up coefficients; the offset 0 then
+    // just re-reads the centre value
+    const int dm = x > 0 ? -stride[mu] : (per ? (nmu - 1) * stride[mu] : 0);
+    const int dp = x + 1 < nmu ? stride[mu] : (per ? -(nmu - 1) * stride[mu] : 0);
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp) {
+      wlo[sp][mu] = Wi[sp * npts + p + dm];
+      wup[sp][mu] = Wi[sp * npts + p + dp];
+    }
+    const double* cf = a.coef + mu * 3 * nm;
+    clo[mu] = cf[x];
+    cdg[mu] = cf[nm + x];
+    cup[mu] = cf[2 * nm + x];
+    const double* sc = a.scale + mu * 3 * nm;
+    const int sm = a.scale_mask >> (3 * mu);
+    sc0[mu] = (sm & 1) ? sc[i] : 1.0;
+    sc1[mu] = (sm & 2) ? sc[nm + j] : 1.0;
+    sc2[mu] = (sm & 4) ? sc[2 * nm + k] : 1.0;
+  }
+
+  // 2. arithmetic
   double w[3] = {0, 0, 0};
 #pragma unroll
-  for (int sp = 0; sp < NS; ++sp) w[sp] = static_cast<double>(Wi[sp * npts + p]);
+  for (int sp = 0; sp < NS; ++sp) w[sp] = static_cast<double>(wc[sp]);
   double G[3] = {0, 0, 0};
   if (a.what != 1 && a.reaction != 0) {
     if (a.reaction >= 4) reaction_ext(a, inst, w[0], w[1], w[2], G[0], G[1], G[2]);
@@ -476,12 +517,28 @@ __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   if constexpr (NS == 2) {
     if (a.cp.kind != 0 && a.what != 1) exchange<T>(a, inst, p, i, npts, w[0], w[1], G[0], G[1]);
   }
+  double f[NS];
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
-    double f = a.what != 2 ? diffusion_fast<T, NDIM>(a, Wi + sp * npts, w[sp], sp, inst, p, i, j, k) : 0.0;
-    if constexpr (DUAL) static_cast<T*>(a.F2)[static_cast<int64_t>(inst) * NS * npts + sp * npts + p] = static_cast<T>(f);
-    if (a.what != 1) f += G[sp];
-    F[sp * npts + p] = static_cast<T>(f);
+    double acc = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < NDIM; ++mu) {
+      double scl = 1.0;
+      scl *= sc0[mu];
+      scl *= sc1[mu];
+      scl *= sc2[mu];
+      acc += scl * (clo[mu] * static_cast<double>(wlo[sp][mu]) + cdg[mu] * w[sp] +
+                    cup[mu] * static_cast<double>(wup[sp][mu]));
+    }
+    f[sp] = a.what != 2 ? a.diff[inst * a.nspecies + sp] * acc : 0.0;
+  }
+
+  // 3. stores
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) {
+    if constexpr (DUAL)
+      static_cast<T*>(a.F2)[static_cast<int64_t>(inst) * NS * npts + sp * npts + p] = static_cast<T>(f[sp]);
+    F[sp * npts + p] = static_cast<T>(a.what != 1 ? f[sp] + G[sp] : f[sp]);
   }
 }
 
@@ -501,6 +558,15 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
   const int64_t npts = static_cast<int64_t>(a.n[0]) * a.n[1] * a.n[2];
   if (npts <= 0 || npts >= (int64_t(1) << 31) || a.batch <= 0 || a.batch > 65535) return hipErrorInvalidValue;
   if (a.what < 0 || a.what > 3 || (a.what == 3 && (!a.F2 || a.cp.kind != 0))) return hipErrorInvalidValue;
+  // the kernel reads W through a restrict-qualified pointer: W must not
+  // overlap F or F2
+  const size_t span = static_cast<size_t>(npts) * a.nspecies * a.batch * sizeof(T);
+  auto overlap = [&](const void* x, const void* y) {
+    const char* u = static_cast<const char*>(x);
+    const char* v = static_cast<const char*>(y);
+    return u < v + span && v < u + span;
+  };
+  if (overlap(a.W, a.F) || (a.F2 && overlap(a.W, a.F2))) return hipErrorInvalidValue;
   dim3 grid(static_cast<unsigned>((npts + 255) / 256), a.batch);
   if (a.what == 3) return a.ndim == 3 ? go_stencil<T, 3, true>(a, grid, s) : go_stencil<T, 2, true>(a, grid, s);
   return a.ndim == 3 ? go_stencil<T, 3, false>(a, grid, s) : go_stencil<T, 2, false>(a, grid, s);
