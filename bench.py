@@ -36,7 +36,9 @@ COPY_BYTES = 256 << 20
 # the copy calibration), keyed "route:launch:tiles", from the rocprofv3
 # counter runs of `bench.py --profile` summarised under profiles/; valid
 # only while the kernel sources hash to TRAFFIC_DIGEST.
-TRAFFIC = {"fused:0:16,64": 11036238, "fused:1:16,64": 13325577}
+TRAFFIC = {"fused:0:16,64": 11036238, "fused:1:16,64": 13325577,
+           "fused_stencil_apart:0:32,64": 9694866, "fused_stencil_apart:1:32,64": 13325586,
+           "fused_stencil_apart:0:16,64": 9651842, "fused_stencil_apart:1:16,64": 13325574}
 TRAFFIC_DIGEST = "ee5cd52ba0097daabb0c3ea47d07f9f8d4afa1e674e9b988047212368d3faee0"
 
 
