@@ -2074,6 +2074,10 @@ int tg_apply_operator(tg_plan p, const void* in, void* out, int32_t what, void* 
   return guarded([&] {
     TG_REQUIRE(p && in && out && in != out, TG_EINVAL, "tg_apply_operator: bad pointers");
     TG_REQUIRE(what >= 0 && what <= 2, TG_EINVAL, "tg_apply_operator: bad selector");
+    const size_t bytes = static_cast<size_t>(p->state_elems) * p->esize;
+    const char* ib = static_cast<const char*>(in);
+    const char* ob = static_cast<const char*>(out);
+    TG_REQUIRE(ib + bytes <= ob || ob + bytes <= ib, TG_EINVAL, "tg_apply_operator: in and out overlap");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->precision == TG_FP64) launch_stencil_stage<double>(p, in, out, what, st);
     else launch_stencil_stage<float>(p, in, out, what, st);

@@ -73,6 +73,26 @@ def test_misaligned_and_mismatched_buffers_are_refused():
         case.plan.step(x[..., :-1].contiguous())  # wrong size
 
 
+def test_overlapping_operator_buffers_are_refused():
+    """The stencil reads its input through a restrict-qualified pointer, so
+    tg_apply_operator refuses an output that overlaps the input (TG_EINVAL)
+    before any launch, and the plan still works afterwards."""
+    case = Case("disk", (12, 16), "fp64", seed=4)
+    x = case.device_state()
+    n = x.numel()
+    big = torch.zeros(2 * n, dtype=x.dtype, device=x.device)
+    big[:n].copy_(x.view(-1))
+    a, b = big[:n].view(x.shape), big[4:n + 4].view(x.shape)  # both 32-byte aligned
+    with pytest.raises(tg.TGError) as err:
+        case.plan.apply_operator(a, b)
+    assert err.value.code == -1
+    out = torch.empty_like(x)
+    case.plan.apply_operator(x, out)
+    ref = torch.empty_like(x)
+    case.plan.apply_operator(x, ref)
+    assert torch.equal(out, ref)
+
+
 def test_oversized_plan_reports_enomem_and_the_device_stays_usable():
     """A plan whose scratch buffers exceed the device memory: 9000 instances
     of two species on a 128^3 cylinder in FP64 need two state-sized buffers
