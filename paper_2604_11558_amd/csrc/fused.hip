@@ -991,7 +991,7 @@ void strided_kernel(StridedArgs a) {
 // single product, two for a sandwich.
 template <typename T, int KCH, int FN, int SW>
 __global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
-  constexpr int NW = KCH, NTH = 64 * NW, NP = 16 * KCH, TN = 16 * FN, EPT = 4 * FN, LD = TN + 4;
+  constexpr int NP = 16 * KCH, TN = 16 * FN, EPT = 4 * FN, LD = TN + 4;  // KCH waves
   using acc_t = typename M16<T>::acc;
   using v4 = typename M16<T>::v4;
   extern __shared__ __align__(256) unsigned char smem[];

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(64 * NW) void strided_bf16_kernel(StridedArgs a) {
 // barrier per tile for a single product, two for a sandwich).
 template <int NT, int KB, int FN, int SW>
 __global__ __launch_bounds__(128 * KB) void strided_bf16_mt_kernel(StridedArgs a) {
-  constexpr int NW = 2 * KB, NTH = 64 * NW, NP = 32 * KB, TN = 16 * FN, EPT = 4 * FN;
+  constexpr int NP = 32 * KB, TN = 16 * FN, EPT = 4 * FN;  // 2 KB waves
   constexpr int LDK = NP + 8, TSTR = TN * LDK;
   extern __shared__ __align__(256) unsigned char smem[];
   __bf16* const sX = reinterpret_cast<__bf16*>(smem);  // two buffers of NT terms

@@ -666,7 +666,7 @@ __global__ __launch_bounds__(256) void adjoint_combine_kernel(AdjointArgs a) {
     for (int k = 0; k < 9; ++k) red[wave][k] = d[k];
   }
   __syncthreads();
-  if (threadIdx.x < 3 * ns) {
+  if (static_cast<int>(threadIdx.x) < 3 * ns) {
     const int k = threadIdx.x;
     const double v = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     a.part[(static_cast<int64_t>(inst) * gridDim.x + blockIdx.x) * (3 * ns) + k] = v;
