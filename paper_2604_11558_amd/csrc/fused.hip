@@ -985,10 +985,11 @@ void strided_kernel(StridedArgs a) {
 // (row block b fastest, then the column tile, then the slab), loading the
 // next tile into registers while the current one is multiplied; the factor
 // rows of a wave stay in registers while the slab is unchanged, and the
-// phi_1 factors while the column tile is (unless they depend on b).  Wave w owns rows 16 w .. 16 w + 15 (NP = 16 KCH rows, KCH
-// waves) and all TN = 16 FN columns; a thread loads EPT = 4 FN rows of one
-// column.  The data tile is double-buffered: one barrier per tile for a
-// single product, two for a sandwich.
+// phi_1 factors while the column tile is (unless they depend on b).  Wave w
+// owns rows 16 w .. 16 w + 15 (NP = 16 KCH rows, KCH waves) and all
+// TN = 16 FN columns; a thread loads EPT = 4 FN rows of one column.  The data
+// tile is double-buffered: one barrier per tile for a single product, two
+// for a sandwich.
 template <typename T, int KCH, int FN, int SW>
 __global__ __launch_bounds__(64 * KCH) void strided_mt_kernel(StridedArgs a) {
   constexpr int NP = 16 * KCH, TN = 16 * FN, EPT = 4 * FN, LD = TN + 4;  // KCH waves
