@@ -461,9 +461,16 @@ template <typename T, int NDIM, int NS, bool DUAL>
 __global__ __launch_bounds__(256) void stencil_fast_kernel(StencilArgs a) {
   const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
   const int npts = n1 * n2 * n3;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-major block order: the grid's x extent is a multiple of 8 and
+  // workgroups go round-robin over the 8 XCDs, so XCD x takes the blocks
+  // x * per_xcd .. (x + 1) * per_xcd, a contiguous range of slowest-mode
+  // layers whose neighbours along that mode stay in its L2
+  const int per_xcd = gridDim.x >> 3;
+  const int blk = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int64_t pl = static_cast<int64_t>(blk) * 256 + threadIdx.x;
   const int inst = blockIdx.y;
-  if (p >= npts) return;
+  if (pl >= npts) return;
+  const int p = static_cast<int>(pl);
   const int q = p / n1;
   const int i = p - q * n1;
   const int k = q / n2;
@@ -567,7 +574,7 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t s) {
     return u < v + span && v < u + span;
   };
   if (overlap(a.W, a.F) || (a.F2 && overlap(a.W, a.F2))) return hipErrorInvalidValue;
-  dim3 grid(static_cast<unsigned>((npts + 255) / 256), a.batch);
+  dim3 grid(static_cast<unsigned>((npts + 2047) / 2048 * 8), a.batch);
   if (a.what == 3) return a.ndim == 3 ? go_stencil<T, 3, true>(a, grid, s) : go_stencil<T, 2, true>(a, grid, s);
   return a.ndim == 3 ? go_stencil<T, 3, false>(a, grid, s) : go_stencil<T, 2, false>(a, grid, s);
 }
