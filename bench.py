@@ -164,6 +164,7 @@ def other_workloads(tg, torch, steps):
     out["sphere_64x256x512_32x128x256_fp32_grouped"] = {
         "value": dof / sec, "unit": "dof-steps/s", "ms_per_step": sec * 1e3, "dof": dof,
         "launches_per_step": info["launches_per_step"], "grouped": info["grouped"], "route": plans[0].route,
+        "tiles": [p.tiles() for p in plans],
         "roofline": step_roofline(flops, sec, PEAK["fp32"], "step: every grouped launch of one step")}
     del plans, states
     torch.cuda.empty_cache()
@@ -421,10 +422,14 @@ def profile_mode(tg, torch, w, pert, steps, route, tiles, precision="fp32"):
         for wl, rows in ((big, prm[:big.batch]), (small, prm[big.batch:])):
             diff = np.stack([np.ones(wl.batch), rows[:, 2]], axis=1)
             plan = tg.Plan(tg.Grid("sphere", wl.n), diff, "schnakenberg", rows[:, :2], wl.tau, "fp32", wl.batch)
+            if route:  # the group autotuner's choice: a route shared by every plan
+                plan.set_route(route)
+            if tiles:  # and its tile widths (the same for both grids)
+                plan.set_tiles([int(t) for t in tiles.split(",")])
             plans.append(plan)
             states.append(plan.state_from_deviation(workloads.batch_perturbations(wl)))
         info = tg.group_info(plans, states)
-        print(f"configuration grouped={info['grouped']} route={plans[0].route}", flush=True)
+        print(f"configuration grouped={info['grouped']} route={plans[0].route} tiles={plans[0].tiles()}", flush=True)
         tg.group_run(plans, states, steps)
         desc = f"{steps} grouped FP32 steps of the 96-instance sphere batch"
     elif w.name == "disk_256x512":

@@ -324,8 +324,10 @@ int tg_apply_split_phi1(tg_plan p, const void* in, void* out, void* stream);
  * species from the same LDS; TG_ENOTSUP where the species' tiles of an
  * instance do not fit in LDS together (160 KB) or the step has another
  * shape.  Steps with indicators (tg_step_diag) run route 0's launches.
- * Routes 0 and 2 fall back to 1 where a shape does not fit in LDS.  All
- * routes compute the same step.  tg_plan_autotune also tries routes 3 and
+ * Routes 0 and 2 fall back to 1 where a shape does not fit in LDS; a
+ * column width set by tg_plan_set_tiles that the new route's in-tile
+ * stencil does not fit goes back to 16.  All routes compute the same
+ * step.  tg_plan_autotune also tries routes 3 and
  * 4 where they exist. */
 int tg_plan_set_route(tg_plan p, int32_t route);
 /* The route actually used by tg_step / tg_run (after fall-back). */
@@ -376,9 +378,11 @@ int tg_group_info(const tg_plan* plans, int32_t n_plans, void* const* states, in
                   int32_t* launches_per_step);
 
 /* Route for a grouped run: times `iters` grouped steps (after 2 warm-up
- * steps) with every plan on route 0 and then on route 2, on private copies
- * of the states (not modified), and sets the faster route (by at least 2%)
- * on all plans, so that they stay groupable.  Plans whose fused route does
+ * steps) with every plan on route 0, on route 2, and on route 2 with the
+ * 16-column strided launches without a plane tail widened to 32 columns
+ * where that fits (only route 0's in-tile stencil held them at 16), on
+ * private copies of the states (not modified), and sets the fastest
+ * (by at least 2%) on all plans, so that they stay groupable.  Plans whose fused route does
  * not fit are left as they are (*best_us = 0).  Allocates one copy of each
  * state for the duration of the call; synchronous. */
 int tg_group_autotune(const tg_plan* plans, int32_t n_plans, void* const* states, int32_t iters, void* stream,
@@ -407,7 +411,12 @@ int tg_plan_tiles(tg_plan p, int32_t* n_ops, int32_t* tiles);
 /* Set the tile widths (n_ops = number of fused launches; 16 / 32 rows for
  * first-mode launches, 16 or a multiple of 32 columns for strided ones;
  * launches that cover whole planes keep theirs).  TG_EINVAL, nothing
- * changed, if a width is not allowed or does not fit in LDS. */
+ * changed, if a width is not allowed or does not fit in LDS as the active
+ * route launches it: route 0 computes F inside the first launch's tile
+ * load, which also needs LDS for the stencil's neighbours, route 2 does
+ * not, so route 2 can take wider first tiles.  tg_plan_set_route to a
+ * route whose in-tile stencil does not fit a width set before puts that
+ * launch back to 16 columns. */
 int tg_plan_set_tiles(tg_plan p, int32_t n_ops, const int32_t* tiles);
 
 #ifdef __cplusplus

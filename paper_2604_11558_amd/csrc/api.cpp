@@ -1122,6 +1122,39 @@ bool stencil_apart(const tg_plan_s* P) {
   return P->ns > 1 && op.kind == 0 && op.sa.stencil && op.sa.plane;
 }
 
+// Whether the active route computes F inside the first fused op's tile
+// load, which then needs LDS for the stencil's neighbours as well.
+bool in_tile_stencil(const tg_plan_s* P) { return active_route(P) == 0 && !stencil_apart(P); }
+
+// LDS bytes of fused op `op` at tile width (kind 0: columns, kind 1: rows)
+// `t`, as the active route launches it.
+size_t fused_lds_bytes(const tg_plan_s* P, const tg::FusedOp& op, int t) {
+  const int nt = bf16_terms(P->precision);
+  if (op.kind == 1) {
+    const auto& a = op.fa;
+    return nt ? tg::first_bf16_lds_bytes(nt, a.nm, t, a.sandwich)
+              : (P->precision == TG_FP64 ? tg::first_lds_bytes<double>(a.nm, t, a.sandwich)
+                                         : tg::first_lds_bytes<float>(a.nm, t, a.sandwich));
+  }
+  const auto& a = op.sa;
+  const int st = a.stencil && in_tile_stencil(P) ? 1 : 0;
+  return nt ? tg::strided_bf16_lds_bytes(nt, a.nm, a.na, t, a.sandwich, a.plane)
+            : (P->precision == TG_FP64 ? tg::strided_lds_bytes<double>(a.nm, t, a.sandwich, a.plane, st)
+                                       : tg::strided_lds_bytes<float>(a.nm, t, a.sandwich, a.plane, st));
+}
+bool fused_tile_fits(const tg_plan_s* P, const tg::FusedOp& op, int t) {
+  const size_t b = fused_lds_bytes(P, op, t);
+  return b > 0 && b <= kLdsLimit;
+}
+
+// After a route change: column tiles chosen for a route without the
+// in-tile stencil that do not fit with it go back to 16 columns (which
+// the plan's construction checked with the stencil).
+void fit_tiles_to_route(tg_plan_s* P) {
+  for (auto& op : P->fused)
+    if (op.kind == 0 && !op.sa.plane && op.sa.tn != 16 && !fused_tile_fits(P, op, op.sa.tn)) op.sa.tn = 16;
+}
+
 // Launches of one step of the active route.
 int step_launches(const tg_plan_s* P) {
   const int r = active_route(P);
@@ -2023,6 +2056,7 @@ int tg_plan_set_route(tg_plan p, int32_t route) {
     if (route != p->route) {
       drop_graphs(p);
       p->route = route;
+      fit_tiles_to_route(p);
     }
     return TG_OK;
   });
@@ -2165,12 +2199,44 @@ int tg_group_autotune(const tg_plan* plans, int32_t n_plans, void* const* states
         if (P->route != r) {
           drop_graphs(P);
           P->route = r;
+          fit_tiles_to_route(P);
         }
     };
+    // each member's column tiles; on the stencil-apart route the products
+    // without a plane tail may also take 32 columns where only the in-tile
+    // stencil kept them at 16 (whole 128-byte lines of an FP32 row)
+    std::vector<std::vector<int>> tn0(n_plans);
+    auto save_tiles = [&]() {
+      for (int q = 0; q < n_plans; ++q) {
+        tn0[q].clear();
+        for (const auto& op : ps[q]->fused) tn0[q].push_back(op.kind == 0 ? op.sa.tn : 0);
+      }
+    };
+    auto set_wide = [&](bool wide) {
+      for (int q = 0; q < n_plans; ++q) {
+        bool changed = false;
+        for (size_t k = 0; k < ps[q]->fused.size(); ++k) {
+          auto& op = ps[q]->fused[k];
+          if (op.kind != 0 || op.sa.plane) continue;
+          const int t = wide && tn0[q][k] == 16 && fused_tile_fits(ps[q], op, 32) ? 32 : tn0[q][k];
+          changed = changed || t != op.sa.tn;
+          op.sa.tn = t;
+        }
+        if (changed) drop_graphs(ps[q]);
+      }
+    };
+    std::vector<std::pair<int, bool>> configs;
+    for (int r : routes) {
+      configs.push_back({r, false});
+      if (r == 2) configs.push_back({r, true});
+    }
     double best = std::numeric_limits<double>::infinity();
     int best_route = routes[0];
-    for (int r : routes) {
+    bool best_wide = false;
+    for (const auto& [r, wide] : configs) {
       set_route(r);
+      if (!wide) save_tiles();
+      set_wide(wide);
       tg_group_s* G = find_group(plans, n_plans, tmp.data());
       for (int w = 0; w < 2; ++w) group_step_any(G, st);
       hip_check(hipEventRecord(e0, st), "event record");
@@ -2183,9 +2249,13 @@ int tg_group_autotune(const tg_plan* plans, int32_t n_plans, void* const* states
       if (us < (std::isfinite(best) ? kTuneGain * best : best)) {
         best = us;
         best_route = r;
+        best_wide = wide;
       }
+      set_wide(false);
     }
     set_route(best_route);
+    save_tiles();
+    set_wide(best_wide);
     if (best_us) *best_us = best;
     return TG_OK;
   });
@@ -2235,26 +2305,18 @@ int tg_plan_set_tiles(tg_plan p, int32_t n_ops, const int32_t* tiles) {
   return guarded([&] {
     TG_REQUIRE(p && tiles && n_ops == static_cast<int32_t>(p->fused.size()), TG_EINVAL,
                "tg_plan_set_tiles: one tile width per fused launch");
-    const int nt = bf16_terms(p->precision);
     for (int k = 0; k < n_ops; ++k) {
       const auto& op = p->fused[k];
       const int t = tiles[k];
       if (op.kind == 1) {
         TG_REQUIRE(t == 16 || t == 32, TG_EINVAL, "tg_plan_set_tiles: first-mode tiles are 16 or 32 rows");
-        const size_t b = nt ? tg::first_bf16_lds_bytes(nt, op.fa.nm, t, op.fa.sandwich)
-                            : (p->precision == TG_FP64 ? tg::first_lds_bytes<double>(op.fa.nm, t, op.fa.sandwich)
-                                                       : tg::first_lds_bytes<float>(op.fa.nm, t, op.fa.sandwich));
-        TG_REQUIRE(b > 0 && b <= kLdsLimit, TG_EINVAL, "tg_plan_set_tiles: tile does not fit in LDS");
       } else {
-        const auto& a = op.sa;
         TG_REQUIRE(t == 16 || (t > 0 && t % 32 == 0), TG_EINVAL, "tg_plan_set_tiles: 16 or a multiple of 32 columns");
-        TG_REQUIRE(!a.plane || t == a.tn, TG_EINVAL, "tg_plan_set_tiles: a plane launch keeps its width");
-        const size_t b = nt ? tg::strided_bf16_lds_bytes(nt, a.nm, a.na, t, a.sandwich, a.plane)
-                            : (p->precision == TG_FP64
-                                   ? tg::strided_lds_bytes<double>(a.nm, t, a.sandwich, a.plane, a.stencil)
-                                   : tg::strided_lds_bytes<float>(a.nm, t, a.sandwich, a.plane, a.stencil));
-        TG_REQUIRE(b > 0 && b <= kLdsLimit, TG_EINVAL, "tg_plan_set_tiles: tile does not fit in LDS");
+        TG_REQUIRE(!op.sa.plane || t == op.sa.tn, TG_EINVAL, "tg_plan_set_tiles: a plane launch keeps its width");
       }
+      // as the active route launches it (the in-tile stencil's LDS only
+      // where that route computes F in the tile load)
+      TG_REQUIRE(fused_tile_fits(p, op, t), TG_EINVAL, "tg_plan_set_tiles: tile does not fit in LDS");
     }
     for (int k = 0; k < n_ops; ++k) {
       if (p->fused[k].kind == 1) p->fused[k].fa.tm = tiles[k];
@@ -2279,19 +2341,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
     hip_check(hipEventCreate(&e1), "event");
     const int nt = bf16_terms(p->precision);
     auto lds_ok = [&](const tg::FusedOp& op) {
-      size_t b;
-      if (op.kind == 0) {
-        const auto& a = op.sa;
-        b = nt ? tg::strided_bf16_lds_bytes(nt, a.nm, a.na, a.tn, a.sandwich, a.plane)
-               : (p->precision == TG_FP64 ? tg::strided_lds_bytes<double>(a.nm, a.tn, a.sandwich, a.plane, a.stencil)
-                                          : tg::strided_lds_bytes<float>(a.nm, a.tn, a.sandwich, a.plane, a.stencil));
-      } else {
-        const auto& a = op.fa;
-        b = nt ? tg::first_bf16_lds_bytes(nt, a.nm, a.tm, a.sandwich)
-               : (p->precision == TG_FP64 ? tg::first_lds_bytes<double>(a.nm, a.tm, a.sandwich)
-                                          : tg::first_lds_bytes<float>(a.nm, a.tm, a.sandwich));
-      }
-      return b > 0 && b <= kLdsLimit;
+      return fused_tile_fits(p, op, op.kind == 0 ? op.sa.tn : op.fa.tm);
     };
     // time `iters` steps of the current configuration (+inf if it cannot
     // run): direct launches, or on route 4 one resident launch of `iters`
@@ -2343,6 +2393,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
     for (int r : routes) {
       p->route = r;
       set_tiles(start_tiles);
+      fit_tiles_to_route(p);
       double cur = measure();
       if (r == 0 || r == 2) {
         // coordinate descent over the fused ops' tile sizes

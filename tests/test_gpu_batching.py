@@ -87,10 +87,13 @@ def test_group_of_split_bf16_plans_runs_member_launches():
         assert torch.equal(a, b)
 
 
-def test_c4_sphere_batches_grouped_subset_vs_oracle():
+@pytest.mark.parametrize("route,wide", [("fused", False), ("fused_stencil_apart", True)])
+def test_c4_sphere_batches_grouped_subset_vs_oracle(route, wide):
     """64 instances on 256 x 512 and 32 on 128 x 256 with per-instance
     (a, b, d_v), FP32, grouped; 8 instances (both sizes) checked against
-    the oracle after 2 steps, all instances checked finite."""
+    the oracle after 2 steps, all instances checked finite.  Both the
+    fused grouping and the one the group autotuner picks for this batch:
+    F in a launch of its own and the phi product on 32-wide column tiles."""
     big, small = workloads.WORKLOADS["sphere_256x512"], workloads.WORKLOADS["sphere_128x256"]
     prm = workloads.sphere_batch_params(big.batch + small.batch)
     members = []
@@ -98,11 +101,14 @@ def test_c4_sphere_batches_grouped_subset_vs_oracle():
         grid = tg.Grid("sphere", w.n)
         diff = np.stack([np.ones(w.batch), rows[:, 2]], axis=1)
         plan = tg.Plan(grid, diff, "schnakenberg", rows[:, :2], w.tau, "fp32", w.batch)
+        plan.set_route(route)
+        if wide:
+            plan.set_tiles([32] + plan.tiles()[1:])
         pert = workloads.batch_perturbations(w)
         members.append((w, plan, pert, diff, rows))
     plans = [m[1] for m in members]
     states = [m[1].state_from_deviation(m[2]) for m in members]
-    assert tg.group_info(plans, states) == {"grouped": True, "launches_per_step": 2}
+    assert tg.group_info(plans, states) == {"grouped": True, "launches_per_step": 2 if route == "fused" else 4}
     steps = 2
     tg.group_run(plans, states, steps)
     for (w, plan, pert, diff, rows), x in zip(members, states):
@@ -171,6 +177,42 @@ def test_set_tiles_checks_and_keeps_results():
     x = case.device_state()
     case.plan.run(x, 6)
     assert rel_err(case.full_from_device(x), case.oracle_run(6)) < 1e-12
+
+
+def test_stencil_apart_route_takes_wider_tiles():
+    """On the stencil-apart route the first product has no stencil in its
+    tile load, so it takes column widths whose LDS the fused route's
+    in-tile stencil would overflow (the 256 x 512 sphere's 512-long phi
+    contraction at 32 columns); back on the fused route the tile falls back
+    to 16 columns.  Every configuration gives the same states as the
+    16-wide stencil-apart one to FP32 rounding, and the oracle's to the
+    FP32 bound of the 256 x 512 sphere batch."""
+    case = Case("sphere", (256, 512), "fp32", tau=1e-2, seed=25)
+    plan = case.plan
+    tiles = plan.tiles()
+    assert tiles[0] == 16
+    wide = [32] + tiles[1:]
+    with pytest.raises(tg.TGError):
+        plan.set_tiles(wide)  # fused route: the stencil's LDS does not fit
+    assert plan.tiles() == tiles
+    plan.set_route("fused_stencil_apart")
+    x16 = case.device_state()
+    plan.run(x16, 3)
+    ref = case.oracle_run(3)
+    f16 = case.full_from_device(x16)
+    assert rel_err(f16, ref) < C4_FP32_TOL
+    plan.set_tiles(wide)
+    assert plan.tiles() == wide
+    x32 = case.device_state()
+    plan.run(x32, 3)
+    f32 = case.full_from_device(x32)
+    assert rel_err(f32, ref) < C4_FP32_TOL
+    assert rel_err(f32, f16) < 2.0 ** -20
+    plan.set_route("fused")
+    assert plan.tiles() == tiles  # back to a width the in-tile stencil fits
+    x = case.device_state()
+    plan.run(x, 3)
+    assert rel_err(case.full_from_device(x), ref) < C4_FP32_TOL
 
 
 def test_group_autotune_keeps_plans_groupable():

@@ -133,7 +133,9 @@ def test_cylinder_1000_steps_reduced_precisions_vs_fp64():
 
 def test_sphere_batch_2000_steps_fp32_grouped_vs_fp64():
     """Eight instances of the 96-instance batch, four per grid size (first,
-    last and two in between), with their own (a, b, d_v)."""
+    last and two in between), with their own (a, b, d_v); the FP32 group
+    in the configuration the group autotuner picks for the whole batch (F
+    in a launch of its own, the phi product on 32-wide column tiles)."""
     big, small = workloads.WORKLOADS["sphere_256x512"], workloads.WORKLOADS["sphere_128x256"]
     prm = workloads.sphere_batch_params(big.batch + small.batch)
     pick = {big: [0, 21, 42, 63], small: [0, 10, 20, 31]}
@@ -146,6 +148,9 @@ def test_sphere_batch_2000_steps_fp32_grouped_vs_fp64():
         pert = np.stack([workloads.perturbation(wl, wl.seed + i) for i in idx])
         for prec in ("fp32", "fp64"):
             plan = tg.Plan(tg.Grid("sphere", wl.n), diff, "schnakenberg", rows[:, :2], wl.tau, prec, len(idx))
+            if prec == "fp32":
+                plan.set_route("fused_stencil_apart")
+                plan.set_tiles([32] + plan.tiles()[1:])
             plans[prec].append(plan)
             states[prec].append(plan.state_from_deviation(pert))
     worst_w = worst_d = 0.0
