@@ -2428,6 +2428,7 @@ int tg_plan_autotune(tg_plan p, const void* state, int32_t iters, void* stream, 
     }
     p->route = best_route;
     set_tiles(best_tiles.empty() ? start_tiles : best_tiles);
+    fit_tiles_to_route(p);
     (void)saved_route;
     drop_graphs(p);
     if (best_us) *best_us = best;
