@@ -5,7 +5,7 @@ import pytest
 
 import paper_2604_11558_amd as tg
 import workloads
-from gpu_helpers import Case, rel_err
+from gpu_helpers import EPS, Case, rel_err
 from oracle import assemble, reactions, splitee
 
 torch = pytest.importorskip("torch")
@@ -230,6 +230,61 @@ def test_group_autotune_keeps_plans_groupable():
     tg.group_run(plans, states, 5)
     for c, x in zip(cases, states):
         assert rel_err(c.full_from_device(x), c.oracle_run(5)) < TOL["fp32"]
+
+
+def fp64_pole_tol(case, steps):
+    """FP64 steps against the oracle, relative to max|W|.  F = d M W_dev +
+    g(W) is rounded where the rows of d M reach d_max ||M||_inf (the
+    sin^-2 rows next to the poles: 7.1e8 on the 256 x 512 sphere), so each
+    step's update carries about eps tau d_max ||M||_inf max|W_dev| from
+    either side; the factor 4 as for the adjoint's bound."""
+    Minf = float(abs(case.oracles[0].M).sum(axis=1).max())
+    wmax = max(float(np.abs(np.asarray(e)).max()) for e in case.eq)
+    dev = float(np.abs(case.pert).max()) / wmax
+    return 4.0 * steps * EPS["fp64"] * (1.0 + case.tau * float(case.diff.max()) * Minf * dev)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_group_autotune_on_long_phi_contractions(precision):
+    """Group autotuner on 256 x 512 and 128 x 256 spheres.  FP32: the
+    stencil-apart route may widen the phi product to 32 columns; the
+    states are untouched, the plans stay grouped, every tile width fits
+    the chosen route (the other route can be set and set back), and the
+    grouped steps match the oracle.  FP64: the 512-row phi tiles do not fit
+    in LDS, so the plans have no fused route and the autotuner leaves them
+    on the per-mode route (best time 0); their steps match the oracle."""
+    cases = [Case("sphere", (256, 512), precision, tau=1e-2, seed=26, batch=2,
+                  params=[(0.1, 0.9), (0.12, 0.85)], diff=[(1.0, 20.0), (1.0, 30.0)]),
+             Case("sphere", (128, 256), precision, tau=1e-2, seed=27)]
+    plans = [c.plan for c in cases]
+    states = [c.device_state() for c in cases]
+    before = [x.clone() for x in states]
+    us = tg.group_autotune(plans, states, iters=3)
+    for a, b in zip(states, before):
+        assert torch.equal(a, b)
+    route = plans[0].route
+    print(precision, route, us, [p.tiles() for p in plans])
+    if precision == "fp64":
+        assert us == 0.0 and plans[0].route == "generic"
+    else:
+        assert us > 0
+        assert all(p.route == route for p in plans)
+        assert tg.group_info(plans, states)["grouped"]
+        tiles = [p.tiles() for p in plans]
+        other = "fused" if route == "fused_stencil_apart" else "fused_stencil_apart"
+        for p, t in zip(plans, tiles):
+            p.set_route(other)
+            p.set_route(route)
+            if route == "fused":
+                assert p.tiles() == t  # route 0's widths survive the round trip
+        for p, t in zip(plans, tiles):
+            p.set_tiles(t)  # the autotuner's widths are valid for its route
+    tg.group_run(plans, states, 2)
+    for c, x in zip(cases, states):
+        tol = fp64_pole_tol(c, 2) if precision == "fp64" else C4_FP32_TOL
+        err = rel_err(c.full_from_device(x), c.oracle_run(2))
+        print(c.n, "rel err %.2e (bound %.2e)" % (err, tol))
+        assert err < tol
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
